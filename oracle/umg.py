@@ -1,0 +1,277 @@
+"""All-at-once Uzawa multigrid (UMG) on the assembled global matrices (oracle).
+
+Section 3.3, eq. (Uzawa_smooth): one smoothing step is the inexact Uzawa
+iteration
+    u_{k+1} = u_k + Ahat^{-1} (f - A u_k - B^T p_k)
+    p_{k+1} = p_k + Shat^{-1} (B u_{k+1} - C p_k - g)
+with, per Section 3.5 and Table "settings" (UMG column), Ahat a symmetric
+Gauss-Seidel sweep on A (forward then backward) and Shat a forward
+Gauss-Seidel sweep on C with under-relaxation omega = 0.3.
+
+Readings taken (listed again in the design notes):
+  * ordering: the paper's hybrid Gauss-Seidel runs "row-wise red-black" inside
+    each primitive and block-Jacobi across primitives of one class.  Here both
+    sweeps use one global 4-colour ordering, colour (X+Y+Z) mod 4 of the
+    integer lattice coordinates, forward = colours 0,1,2,3 and backward =
+    3,2,1,0.  Nodes of one colour are never coupled by A or C (tests check
+    this), so a colour is updated simultaneously.
+  * "FHGS on C with under-relaxation omega" is point SOR: Shat = D_C/omega + L_C.
+  * the V-cycle (Section 3.5, "V(n_pre, n_post)") restricts the residual with
+    the transpose of P1 interpolation, zeroes velocity Dirichlet rows, starts
+    the coarse correction from zero and uses rediscretised coarse operators
+    (c_l is level dependent).  The variable cycle adds 2 pre- and 2
+    post-smoothing steps per coarser level (Section 3.5).
+  * coarse solve (Section 3.7 uses a loose PMINRES): here the level-0 system
+    is solved exactly by a dense factorisation, bordered by the constraint
+    sum_i m_i p_i = 0 when the pressure is only defined up to a constant.
+  * after each cycle the finest pressure is projected to zero mean,
+    p <- p - (sum m_i p_i)/(sum m_i) with m_i = int phi_i (Section 2.1, L^2_0);
+    the projection is skipped when a natural (outflow) face removes the
+    null space.
+  * stopping criterion (Section 3.6): ||K x_k - f~||_2 <= eps ||K x_0 - f~||_2,
+    Euclidean over free velocity rows and all pressure rows.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .fem import Hierarchy
+
+
+class UMG:
+    def __init__(self, H: Hierarchy, nu1=3, nu2=3, omega=0.3, variable=False,
+                 p_sweep="forward"):
+        self.H = H
+        self.nu1, self.nu2, self.omega = nu1, nu2, omega
+        self.variable = variable
+        self.p_sweep = p_sweep
+        self.L = len(H.levels) - 1
+        self._gs = []
+        for lv in H.levels:
+            dA, dC = lv.A.diagonal(), lv.C.diagonal()
+            g = {"v": [], "p": []}
+            for c in range(4):
+                iv = np.nonzero(lv.free & (lv.colour == c))[0]
+                ip = np.nonzero(lv.colour == c)[0]
+                g["v"].append((iv, lv.A[iv], dA[iv]))
+                g["p"].append((ip, lv.C[ip], dC[ip]))
+            self._gs.append(g)
+        self._coarse = self._factor_coarse(H.levels[0])
+
+    # -- operators -------------------------------------------------------
+    def rhs(self, f_nodal, l=None):
+        """f~ = (M I_h f on free velocity rows, g_l(I_h f))."""
+        lv = self.H.levels[self.L if l is None else l]
+        b = np.zeros((4, lv.N))
+        for k in range(3):
+            b[k] = lv.M @ f_nodal[k]
+            b[k][lv.dirichlet] = 0.0
+        b[3] = sum(lv.Gf[k] @ f_nodal[k] for k in range(3))
+        return b
+
+    def apply(self, l, x):
+        """y = K x on free velocity rows and all pressure rows; x carries the
+        Dirichlet values in its Dirichlet velocity entries."""
+        lv = self.H.levels[l]
+        y = np.zeros_like(x)
+        for k in range(3):
+            y[k] = lv.A @ x[k] + lv.B[k].T @ x[3]
+            y[k][lv.dirichlet] = 0.0
+        y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
+        return y
+
+    def residual(self, l, x, b):
+        return b - self.apply(l, x)
+
+    def norm(self, l, r):
+        lv = self.H.levels[l]
+        return float(np.sqrt(np.sum(r[:3, lv.free] ** 2) + np.sum(r[3] ** 2)))
+
+    # -- smoother (eq. Uzawa_smooth) ---------------------------------------
+    def sgs(self, l, r):
+        """Ahat^{-1} r: one symmetric Gauss-Seidel sweep on A d = r from d = 0."""
+        d = np.zeros_like(r)
+        order = list(range(4)) + list(range(3, -1, -1))
+        for c in order:
+            idx, rows, diag = self._gs[l]["v"][c]
+            d[idx] += (r[idx] - rows @ d) / diag
+        return d
+
+    def sor(self, l, s):
+        """Shat^{-1} s with Shat = D/omega + L (forward), or its symmetric
+        version (forward then backward) when p_sweep == 'symmetric'."""
+        d = np.zeros_like(s)
+        order = list(range(4))
+        if self.p_sweep == "symmetric":
+            order += list(range(3, -1, -1))
+        for c in order:
+            idx, rows, diag = self._gs[l]["p"][c]
+            d[idx] += self.omega * (s[idx] - rows @ d) / diag
+        return d
+
+    def uzawa(self, l, x, b):
+        lv = self.H.levels[l]
+        u, p = x[:3], x[3]
+        for k in range(3):
+            ru = b[k] - lv.A @ u[k] - lv.B[k].T @ p
+            ru[lv.dirichlet] = 0.0
+            u[k] += self.sgs(l, ru)
+        s = sum(lv.B[k] @ u[k] for k in range(3)) - lv.C @ p - b[3]
+        x[3] = p + self.sor(l, s)
+        return x
+
+    # -- grid transfer -------------------------------------------------------
+    def restrict(self, l, r):
+        """Residual of level l -> right-hand side of level l-1: P^T r, velocity
+        Dirichlet rows of the coarse level set to zero."""
+        P = self.H.P[l]
+        c = self.H.levels[l - 1]
+        rc = np.stack([P.T @ r[k] for k in range(4)])
+        rc[:3, c.dirichlet] = 0.0
+        return rc
+
+    def prolong(self, l, e):
+        P = self.H.P[l]
+        return np.stack([P @ e[k] for k in range(4)])
+
+    # -- coarse grid -------------------------------------------------------
+    def _coarse_system(self, lv):
+        fr = np.nonzero(lv.free)[0]
+        nf, N = fr.shape[0], lv.N
+        A = lv.A[fr][:, fr].toarray()
+        K = np.zeros((3 * nf + N, 3 * nf + N))
+        for k in range(3):
+            Bk = lv.B[k][:, fr].toarray()
+            K[k * nf:(k + 1) * nf, k * nf:(k + 1) * nf] = A
+            K[3 * nf:, k * nf:(k + 1) * nf] = Bk
+            K[k * nf:(k + 1) * nf, 3 * nf:] = Bk.T
+        K[3 * nf:, 3 * nf:] = -lv.C.toarray()
+        return fr, K
+
+    def _factor_coarse(self, lv):
+        fr, K = self._coarse_system(lv)
+        if self.H.project:
+            n = K.shape[0]
+            Kb = np.zeros((n + 1, n + 1))
+            Kb[:n, :n] = K
+            Kb[n, n - lv.N:n] = lv.mass
+            Kb[n - lv.N:n, n] = lv.mass
+            K = Kb
+        return fr, sla.lu_factor(K)
+
+    def coarse_solve(self, b):
+        """Exact solution of the level-0 system (mean-zero pressure if needed)."""
+        lv = self.H.levels[0]
+        fr, lu = self._coarse
+        nf = fr.shape[0]
+        rhs = np.concatenate([b[0][fr], b[1][fr], b[2][fr], b[3]])
+        if self.H.project:
+            rhs = np.append(rhs, 0.0)
+        sol = sla.lu_solve(lu, rhs)
+        x = np.zeros((4, lv.N))
+        for k in range(3):
+            x[k][fr] = sol[k * nf:(k + 1) * nf]
+        x[3] = sol[3 * nf:3 * nf + lv.N]
+        return x
+
+    # -- cycle -----------------------------------------------------------------
+    def steps(self, l):
+        extra = 2 * (self.L - l) if self.variable else 0
+        return self.nu1 + extra, self.nu2 + extra
+
+    def vcycle(self, l, x, b):
+        if l == 0:
+            return x + self.coarse_solve(self.residual(0, x, b))
+        pre, post = self.steps(l)
+        for _ in range(pre):
+            self.uzawa(l, x, b)
+        bc = self.restrict(l, self.residual(l, x, b))
+        ec = self.vcycle(l - 1, np.zeros_like(bc), bc)
+        x += self.prolong(l, ec)
+        for _ in range(post):
+            self.uzawa(l, x, b)
+        return x
+
+    def project(self, x, l=None):
+        lv = self.H.levels[self.L if l is None else l]
+        if self.H.project:
+            x[3] -= np.dot(lv.mass, x[3]) / lv.mass.sum()
+        return x
+
+    def cycle(self, x, b):
+        """One solver iteration: a V-cycle on the finest level, then the
+        mean-zero projection of the pressure."""
+        x = self.vcycle(self.L, x, b)
+        return self.project(x)
+
+    def solve(self, x, b, rtol=1e-8, max_cycles=100, callback=None):
+        L = self.L
+        r0 = self.norm(L, self.residual(L, x, b))
+        hist = [r0]
+        if r0 == 0.0:
+            return x, hist
+        for _ in range(max_cycles):
+            x = self.cycle(x, b)
+            r = self.norm(L, self.residual(L, x, b))
+            hist.append(r)
+            if callback is not None:
+                callback(x, r)
+            if r <= rtol * r0:
+                break
+        return x, hist
+
+    # -- direct reference ------------------------------------------------------
+    def direct_solve(self, b, l=None, xbc=None):
+        l = self.L if l is None else l
+        return direct_solve(self.H.levels[l], b, self.H.project, xbc)
+
+
+def apply_level(lv, x):
+    """y = K x on one level (same as UMG.apply, usable without a hierarchy)."""
+    y = np.zeros_like(x)
+    for k in range(3):
+        y[k] = lv.A @ x[k] + lv.B[k].T @ x[3]
+        y[k][lv.dirichlet] = 0.0
+    y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
+    return y
+
+
+def direct_solve(lv, b, project, xbc=None):
+    """Sparse direct solution of K x = b - K x_D on one level; used as a
+    reference at small sizes.  xbc carries Dirichlet velocity values.  When the
+    pressure is only defined up to a constant, the pressure of node 0 is fixed
+    to zero (the remaining system is regular for a compatible right-hand side)
+    and the result is projected to zero mean."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    fr = np.nonzero(lv.free)[0]
+    nf, N = fr.shape[0], lv.N
+    xd = np.zeros((4, N)) if xbc is None else xbc.copy()
+    xd[:3, fr] = 0.0
+    xd[3] = 0.0
+    r = b - apply_level(lv, xd)
+    A = lv.A[fr][:, fr]
+    blocks = [[None] * 4 for _ in range(4)]
+    for k in range(3):
+        blocks[k][k] = A
+        Bk = lv.B[k][:, fr]
+        blocks[3][k] = Bk
+        blocks[k][3] = Bk.T
+    blocks[3][3] = -lv.C
+    K = sp.bmat(blocks, format="lil")
+    rhs = np.concatenate([r[0][fr], r[1][fr], r[2][fr], r[3]])
+    if project:
+        i0 = 3 * nf
+        K[i0, :] = 0.0
+        K[:, i0] = 0.0
+        K[i0, i0] = 1.0
+        rhs[i0] = 0.0
+    sol = spla.spsolve(K.tocsc(), rhs)
+    x = xd.copy()
+    for k in range(3):
+        x[k][fr] = sol[k * nf:(k + 1) * nf]
+    x[3] = sol[3 * nf:3 * nf + N]
+    if project:
+        x[3] -= np.dot(lv.mass, x[3]) / lv.mass.sum()
+    return x

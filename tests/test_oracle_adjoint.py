@@ -1,0 +1,60 @@
+"""Pins of the oracle's adjoint gradients against central finite differences of
+its own forward map (direct solves), which share nothing with the gradient
+formulas."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import build_hierarchy
+from oracle.adjoint import adjoint_rhs, grad_forcing, grad_viscosity, loss
+from oracle.umg import direct_solve
+
+
+def _forward(cfg, nu, f, R):
+    """Finest level only (R0 = R) and a sparse direct solve."""
+    xyz, tet, _, tags = cfg.mesh()
+    H = build_hierarchy(xyz, tet, nu, tags, R, R0=R)
+    lv = H.finest
+    x0 = np.zeros((4, lv.N))
+    x0[:3] = cfg.dirichlet_field()
+    x0[:3, lv.free] = 0.0
+    b = np.zeros((4, lv.N))
+    for k in range(3):
+        b[k] = lv.M @ f[k]
+        b[k][lv.dirichlet] = 0.0
+    b[3] = sum(lv.Gf[k] @ f[k] for k in range(3))
+    return H, direct_solve(lv, b, H.project, xbc=x0)
+
+
+@pytest.mark.parametrize("cfg_id", [4, 5])
+def test_gradients_match_finite_differences(cfg_id):
+    R = 3
+    cfg = W.WORKLOADS[cfg_id].with_R(R)
+    _, tet, nu, _ = cfg.mesh()
+    f = cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 11, 0.3)
+    H, x = _forward(cfg, nu, f, R)
+    lv = H.finest
+    _, xo = _forward(cfg, cfg.observation_viscosity(), f, R)
+    u_obs = xo[:3]
+    lam = direct_solve(lv, adjoint_rhs(lv, x[:3], u_obs), H.project)
+    gf = grad_forcing(lv, lam)
+    gnu = grad_viscosity(lv, x, lam, f, nu)
+
+    def J(nu_, f_):
+        _, xx = _forward(cfg, nu_, f_, R)
+        return loss(xx[:3], u_obs)
+
+    rng = np.random.default_rng(9)
+    for _ in range(2):
+        d = rng.normal(size=f.shape)
+        eps = 1.0                              # J is quadratic in f: central FD is exact
+        fd = (J(nu, f + eps * d) - J(nu, f - eps * d)) / (2 * eps)
+        assert np.sum(gf * d) == pytest.approx(fd, rel=1e-8, abs=1e-14)
+    eps = 1e-6
+    macros = rng.choice(nu.shape[0], size=4, replace=False)
+    fd = np.zeros(4)
+    for i, e in enumerate(macros):
+        dn = np.zeros_like(nu)
+        dn[e] = eps
+        fd[i] = (J(nu + dn, f) - J(nu - dn, f)) / (2 * eps)
+    assert np.abs(gnu[macros] - fd).max() <= 1e-6 * np.abs(gnu).max()

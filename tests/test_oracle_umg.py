@@ -1,0 +1,141 @@
+"""Pins of the oracle's Uzawa multigrid: preconditioner algebra, fixed points,
+direct solutions, convergence rates, discretisation order and the paper's
+serial iteration counts."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import UMG, build_hierarchy
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _umg(cfg_id, R, **kw):
+    cfg = W.WORKLOADS[cfg_id].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    return cfg, UMG(build_hierarchy(xyz, tet, nu, tags, R), **kw)
+
+
+@pytest.fixture(scope="module")
+def box_r3():
+    return _umg(4, 3)
+
+
+def _colour_perm(lv, idx):
+    """Indices idx ordered by colour 0..3 (stable)."""
+    return idx[np.argsort(lv.colour[idx], kind="stable")]
+
+
+def test_sgs_is_symmetric_gauss_seidel(box_r3):
+    """Ahat^{-1} r equals the textbook SGS preconditioner (D+L) D^{-1} (D+U) in
+    the colour ordering, built densely."""
+    _, umg = box_r3
+    l = 1
+    lv = umg.H.levels[l]
+    fr = _colour_perm(lv, np.nonzero(lv.free)[0])
+    A = lv.A[fr][:, fr].toarray()
+    D = np.diag(np.diag(A))
+    Lo, Up = np.tril(A, -1), np.triu(A, 1)
+    Ahat = (D + Lo) @ np.linalg.solve(D, D + Up)
+    r = np.random.default_rng(0).normal(size=lv.N)
+    r[lv.dirichlet] = 0.0
+    d = umg.sgs(l, r)
+    assert np.all(d[lv.dirichlet] == 0.0)
+    assert np.allclose(d[fr], np.linalg.solve(Ahat, r[fr]), rtol=1e-11, atol=1e-13 * abs(d).max())
+
+
+def test_sor_is_forward_relaxed_gauss_seidel(box_r3):
+    """Shat^{-1} s with Shat = D_C / omega + L_C (colour ordering)."""
+    _, umg = box_r3
+    l = 1
+    lv = umg.H.levels[l]
+    p = _colour_perm(lv, np.arange(lv.N))
+    C = lv.C[p][:, p].toarray()
+    Shat = np.diag(np.diag(C)) / umg.omega + np.tril(C, -1)
+    s = np.random.default_rng(1).normal(size=lv.N)
+    assert np.allclose(umg.sor(l, s)[p], sla.solve_triangular(Shat, s[p], lower=True),
+                       rtol=1e-11)
+
+
+def test_exact_solution_is_fixed_point(box_r3):
+    """The discrete solution is a fixed point of the Uzawa step and of the
+    V-cycle (consistency of eq. Uzawa_smooth and the coarse correction)."""
+    cfg, umg = box_r3
+    b = umg.rhs(cfg.forcing_field())
+    xs = umg.direct_solve(b)
+    L = umg.L
+    assert umg.norm(L, umg.residual(L, xs, b)) < 1e-12 * umg.norm(L, b)
+    x1 = umg.uzawa(L, xs.copy(), b)
+    assert np.abs(x1 - xs).max() < 1e-10 * np.abs(xs).max()
+    x2 = umg.cycle(xs.copy(), b)
+    assert np.abs(x2 - xs).max() < 1e-10 * np.abs(xs).max()
+
+
+def test_coarse_solve_is_exact_and_mean_free(box_r3):
+    _, umg = box_r3
+    lv = umg.H.levels[0]
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(4, lv.N))
+    x[:3, lv.dirichlet] = 0.0
+    b = umg.apply(0, x)                      # compatible right-hand side
+    e = umg.coarse_solve(b)
+    assert umg.norm(0, umg.residual(0, e, b)) < 1e-12 * umg.norm(0, b)
+    assert abs(lv.mass @ e[3]) < 1e-13 * np.abs(e[3]).max()
+    xm = x.copy()
+    xm[3] -= (lv.mass @ x[3]) / lv.mass.sum()
+    assert np.abs(e - xm).max() < 1e-11 * np.abs(xm).max()
+
+
+@pytest.mark.parametrize("cfg_id,R", [(1, 4), (4, 4), (5, 4), (4, 3), (5, 3)])
+def test_vcycle_convergence_factor(cfg_id, R):
+    """V(3,3) Uzawa multigrid from x0 = 0 (Dirichlet values set): mean
+    convergence factor per cycle at most 0.3; at R = 3 the solution also
+    agrees with the sparse direct solution."""
+    cfg, umg = _umg(cfg_id, R)
+    lv = umg.H.finest
+    b = umg.rhs(cfg.forcing_field())
+    x0 = np.zeros((4, lv.N))
+    x0[:3] = cfg.dirichlet_field()
+    x0[:3, lv.free] = 0.0
+    x, hist = umg.solve(x0.copy(), b, rtol=1e-8)
+    K = len(hist) - 1
+    rho_mean = (hist[-1] / hist[0]) ** (1.0 / K)
+    assert rho_mean <= 0.3, hist
+    assert hist[-1] <= 1e-8 * hist[0]
+    if R > 3:
+        return
+    xd = umg.direct_solve(b, xbc=x0)
+    err = np.sqrt(np.sum((x - xd) ** 2))
+    assert err <= 1e-6 * np.sqrt(np.sum(xd ** 2))
+
+
+def test_manufactured_velocity_converges_second_order():
+    errs = []
+    for R in (3, 4, 5):
+        cfg, umg = _umg(1, R)
+        b = umg.rhs(cfg.forcing_field())
+        x, _ = umg.solve(np.zeros((4, umg.H.finest.N)), b, rtol=1e-11)
+        ue = W.manufactured_velocity(cfg.points())
+        errs.append(np.sqrt(np.mean((x[:3] - ue) ** 2)))
+    ratios = [errs[i] / errs[i + 1] for i in range(2)]
+    assert ratios[-1] > 3.5, (errs, ratios)
+
+
+def test_paper_style_iteration_count():
+    """Section 3.6 / Table T:itertime1: f = 0, u0 ~ U[0,1], p0 ~ U[0, 1/h_min],
+    Vvar(3,3), eps = 1e-8: 9 cycles at L=2 (R=4).  The global 4-colour ordering
+    differs from the paper's hybrid Gauss-Seidel, so a band of +-2 is allowed."""
+    gold = json.load(open(os.path.join(GOLD, "paper_serial_table.json")))
+    cfg, umg = _umg(1, 4, variable=True)
+    lv = umg.H.finest
+    hmin = (1.0 / (6 * lv.n ** 3)) ** (1.0 / 3.0)
+    x0 = W.random_initial_guess(lv.N, 1.0 / hmin, seed=0)
+    x0[:3, lv.dirichlet] = 0.0
+    b = np.zeros_like(x0)
+    _, hist = umg.solve(x0, b, rtol=1e-8)
+    it = len(hist) - 1
+    assert abs(it - gold["umg_iterations"]["2"]) <= 2, hist

@@ -1,0 +1,267 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module builds *inputs only*: macro meshes (Kuhn-split boxes), boundary
+tags, per-macro viscosities, nodal forcing fields and random initial guesses.
+It contains none of the solver's arithmetic (no element matrices, no
+stencils, no smoothing); both the CPU oracle and the GPU path consume exactly
+the arrays produced here, and neither regenerates them.
+
+Nodal fields are given on the vertices of the R-times refined box in lattice
+order: the node with integer lattice coordinates (X, Y, Z), 0 <= X <= a*2^R,
+0 <= Y, Z <= 2^R, has index X + nx*(Y + ny*Z) with nx = a*2^R + 1 and
+ny = 2^R + 1.
+
+Workloads (the paper's serial problems are the unit cube split into 6 macro
+tetrahedra, Section 4 and Table "iteration numbers and time-to-solution"):
+
+  1  unit cube, 6 macros, R=4 (17^3 lattice), manufactured forcing, nu=1, fp64
+  2  unit cube, 6 macros, R=7 (129^3), manufactured forcing + N(0, 0.01) nodal
+     noise (seed 2), fp64
+  3  unit cube, 6 macros, R=8 (257^3), manufactured forcing, mixed precision
+  4  box [0,2]x[0,1]^2, 12 macros, R=6, nu_e log-uniform in [0.1, 10] (seed 4),
+     8-mode Fourier forcing (seed 41), observation viscosity nu_e*exp(0.1 xi_e)
+     (seed 42), fp64 forward + adjoint
+  5  channel [0,4]x[0,1]^2, 24 macros, R=7, parabolic inflow at x=0, natural
+     outflow at x=4, no-slip walls, f=0, nu_e log-uniform in [0.5, 2] (seed 5),
+     observation viscosity seed 52, mixed precision forward + adjoint
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# boundary tags of macro faces (face f is the face opposite local vertex f)
+FACE_INTERIOR = 0
+FACE_DIRICHLET = 1
+FACE_NATURAL = 2
+
+
+def box_mesh(a: int):
+    """Macro mesh of the box [0,a]x[0,1]x[0,1]: each unit cube is split into the
+    6 Kuhn tetrahedra {c, c+e_s0, c+e_s0+e_s1, c+(1,1,1)} over the permutations
+    s of the three axes.  Vertices are listed in this path order, which is the
+    order the refinement and the tests rely on.
+
+    Returns (xyz [nv,3] float64, tet [nt,4] int32)."""
+    nx, ny, nz = a + 1, 2, 2
+    pts = np.array([(x, y, z) for z in range(nz) for y in range(ny) for x in range(nx)],
+                   dtype=np.float64)
+
+    def vid(x, y, z):
+        return x + nx * (y + ny * z)
+
+    tets = []
+    for cx in range(a):
+        for perm in itertools.permutations((0, 1, 2)):
+            v = np.array([cx, 0, 0])
+            path = [vid(*v)]
+            for ax in perm:
+                v = v.copy()
+                v[ax] += 1
+                path.append(vid(*v))
+            tets.append(path)
+    return pts, np.asarray(tets, dtype=np.int32)
+
+
+def face_tags(xyz, tet, a: int, natural_x: float | None = None):
+    """Boundary tag per (macro, face): a face lying in a plane of the box
+    boundary is Dirichlet, except the face(s) in the plane x = natural_x, which
+    are natural (do-nothing) faces.  Interior faces are 0."""
+    nt = tet.shape[0]
+    tags = np.zeros((nt, 4), dtype=np.int8)
+    planes = [(0, 0.0), (0, float(a)), (1, 0.0), (1, 1.0), (2, 0.0), (2, 1.0)]
+    for t in range(nt):
+        for f in range(4):
+            fv = xyz[np.delete(tet[t], f)]
+            for ax, val in planes:
+                if np.all(fv[:, ax] == val):
+                    if natural_x is not None and ax == 0 and val == natural_x:
+                        tags[t, f] = FACE_NATURAL
+                    else:
+                        tags[t, f] = FACE_DIRICHLET
+    return tags
+
+
+def lattice_shape(a: int, R: int):
+    n = 1 << R
+    return a * n + 1, n + 1, n + 1
+
+
+def lattice_points(a: int, R: int):
+    """Physical coordinates [N,3] of the refined box vertices in lattice order."""
+    nx, ny, nz = lattice_shape(a, R)
+    h = 1.0 / (1 << R)
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return np.stack([X.ravel() * h, Y.ravel() * h, Z.ravel() * h], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# manufactured solution of configs 1-3:
+#   u = curl(psi*(1,1,1)), psi = (sin(pi x) sin(pi y) sin(pi z))^2,
+#   p = x + y + z - 3/2,  f = -nu*Lap(u) + grad(p)
+# written with S(t) = sin^2(pi t) and its derivatives D1 = S', D2 = S'', D3 = S'''
+# ---------------------------------------------------------------------------
+def _S(t):
+    return np.sin(np.pi * t) ** 2
+
+
+def _D1(t):
+    return np.pi * np.sin(2 * np.pi * t)
+
+
+def _D2(t):
+    return 2 * np.pi ** 2 * np.cos(2 * np.pi * t)
+
+
+def _D3(t):
+    return -4 * np.pi ** 3 * np.sin(2 * np.pi * t)
+
+
+def manufactured_velocity(x):
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    px = _D1(X) * _S(Y) * _S(Z)
+    py = _S(X) * _D1(Y) * _S(Z)
+    pz = _S(X) * _S(Y) * _D1(Z)
+    return np.stack([py - pz, pz - px, px - py], axis=0)
+
+
+def manufactured_pressure(x):
+    return x[:, 0] + x[:, 1] + x[:, 2] - 1.5
+
+
+def manufactured_forcing(x, nu: float = 1.0):
+    """[3,N] nodal values of f = -nu*Lap(u) + grad(p) for the manufactured pair."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    # derivatives of Lap(psi) along each axis
+    lx = _D3(X) * _S(Y) * _S(Z) + _D1(X) * _D2(Y) * _S(Z) + _D1(X) * _S(Y) * _D2(Z)
+    ly = _D2(X) * _D1(Y) * _S(Z) + _S(X) * _D3(Y) * _S(Z) + _S(X) * _D1(Y) * _D2(Z)
+    lz = _D2(X) * _S(Y) * _D1(Z) + _S(X) * _D2(Y) * _D1(Z) + _S(X) * _S(Y) * _D3(Z)
+    lap_u = np.stack([ly - lz, lz - lx, lx - ly], axis=0)
+    return -nu * lap_u + 1.0
+
+
+def fourier_forcing(x, seed: int, modes: int = 8):
+    """f = sum_m d_m sin(pi k_m . x + phi_m): k_m in {1,2,3}^3, phi_m ~ U[0, 2 pi),
+    d_m a random unit vector (amplitude 1).  Returns [3,N]."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 4, size=(modes, 3))
+    phi = rng.uniform(0.0, 2 * np.pi, size=modes)
+    d = rng.normal(size=(modes, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    f = np.zeros((3, x.shape[0]))
+    for m in range(modes):
+        s = np.sin(np.pi * (x @ k[m]) + phi[m])
+        f += d[m][:, None] * s[None, :]
+    return f
+
+
+def nodal_noise(N: int, seed: int, sigma: float):
+    """i.i.d. N(0, sigma^2) per node and component, [3,N]."""
+    return np.random.default_rng(seed).normal(0.0, sigma, size=(3, N))
+
+
+def log_uniform_viscosity(nt: int, lo: float, hi: float, seed: int):
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=nt))
+
+
+def perturbed_viscosity(nu, seed: int, scale: float = 0.1):
+    """Viscosity of the synthetic observation: nu_e * exp(scale * xi_e), xi ~ N(0,1)."""
+    xi = np.random.default_rng(seed).normal(size=nu.shape[0])
+    return nu * np.exp(scale * xi)
+
+
+def inflow_profile(x):
+    """[3,N] Dirichlet data of the channel: u_x = 16 y(1-y) z(1-z) on the inflow
+    plane x = 0; zero elsewhere (walls).  Values off the Dirichlet set are
+    ignored by both solvers."""
+    g = np.zeros((3, x.shape[0]))
+    on = x[:, 0] == 0.0
+    y, z = x[on, 1], x[on, 2]
+    g[0, on] = 16.0 * y * (1 - y) * z * (1 - z)
+    return g
+
+
+def random_initial_guess(N: int, pmax: float, seed: int = 0):
+    """Random start of the paper's serial runs: u in U[0,1], p in U[0, pmax]
+    (the paper uses pmax = 1/h_min).  Returns [4,N]."""
+    rng = np.random.default_rng(seed)
+    x = np.empty((4, N))
+    x[:3] = rng.uniform(0.0, 1.0, size=(3, N))
+    x[3] = rng.uniform(0.0, pmax, size=N)
+    return x
+
+
+# ---------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    a: int                      # box length in x (unit cubes)
+    R: int                      # refinements of the macro mesh
+    precision: str              # "fp64" | "mixed"
+    natural_x: float | None = None
+    nu_range: tuple | None = None
+    nu_seed: int | None = None
+    nu_obs_seed: int | None = None
+    forcing: str = "manufactured"   # manufactured | manufactured+noise | fourier | zero
+    forcing_seed: int | None = None
+    noise_sigma: float = 0.0
+    inflow: bool = False
+    extra: dict = field(default_factory=dict)
+
+    # -- inputs ----------------------------------------------------------
+    def mesh(self):
+        xyz, tet = box_mesh(self.a)
+        tags = face_tags(xyz, tet, self.a, self.natural_x)
+        if self.nu_range is None:
+            nu = np.ones(tet.shape[0])
+        else:
+            nu = log_uniform_viscosity(tet.shape[0], self.nu_range[0], self.nu_range[1],
+                                       self.nu_seed)
+        return xyz, tet, nu, tags
+
+    def with_R(self, R: int) -> "Workload":
+        d = dict(self.__dict__)
+        d["R"] = R
+        return Workload(**d)
+
+    def points(self):
+        return lattice_points(self.a, self.R)
+
+    def forcing_field(self):
+        x = self.points()
+        if self.forcing == "manufactured":
+            return manufactured_forcing(x)
+        if self.forcing == "manufactured+noise":
+            return manufactured_forcing(x) + nodal_noise(x.shape[0], self.forcing_seed,
+                                                         self.noise_sigma)
+        if self.forcing == "fourier":
+            return fourier_forcing(x, self.forcing_seed)
+        if self.forcing == "zero":
+            return np.zeros((3, x.shape[0]))
+        raise ValueError(self.forcing)
+
+    def dirichlet_field(self):
+        """[3,N] Dirichlet velocity values (inflow profile or zero)."""
+        x = self.points()
+        if self.inflow:
+            return inflow_profile(x)
+        return np.zeros((3, x.shape[0]))
+
+    def observation_viscosity(self):
+        _, _, nu, _ = self.mesh()
+        return perturbed_viscosity(nu, self.nu_obs_seed)
+
+
+WORKLOADS = {
+    1: Workload("unit-cube-R4-fp64", a=1, R=4, precision="fp64"),
+    2: Workload("unit-cube-R7-fp64", a=1, R=7, precision="fp64",
+                forcing="manufactured+noise", forcing_seed=2, noise_sigma=0.1),
+    3: Workload("unit-cube-R8-mixed", a=1, R=8, precision="mixed"),
+    4: Workload("box2-R6-adjoint-fp64", a=2, R=6, precision="fp64", nu_range=(0.1, 10.0),
+                nu_seed=4, nu_obs_seed=42, forcing="fourier", forcing_seed=41),
+    5: Workload("channel4-R7-adjoint-mixed", a=4, R=7, precision="mixed", natural_x=4.0,
+                nu_range=(0.5, 2.0), nu_seed=5, nu_obs_seed=52, forcing="zero", inflow=True),
+}
