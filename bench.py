@@ -1,0 +1,208 @@
+"""Benchmark: Stokes DoFs solved per second on one MI355X.
+
+One step = one complete solve of the unit-cube Stokes problem refined 7 times
+(129^3 lattice, 8,291,838 DoFs, FP64, manufactured forcing plus N(0, 0.01)
+nodal noise, V(3,3) Uzawa multigrid to a 1e-8 relative residual from x0 = 0):
+right-hand side assembly, every V-cycle and the per-cycle residual check.
+Inputs are resident in HBM before the timed region.
+
+Printed as one JSON line with, besides the contract fields:
+  tme_factor   solve time / time of one K apply on the finest level (the
+               paper's work unit, Section 5), both measured here;
+  roofline     the velocity colour sweep (the dominant kernel) against the
+               8 TB/s HBM peak, algorithmic bytes per launch / measured mean
+               launch time (hipEvents around every launch on its stream);
+  cpu_baseline the FP64 oracle (numpy/scipy) solving the same problem at a
+               bounded size on the host cores, setup excluded.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Stokes DoFs solved/s to 1e-8 rel. residual; TME factor; smoother HBM GB/s"
+
+
+def cpu_baseline(workload_id: int, R: int, timeout: float = 600.0):
+    """Times the oracle's solve in a single-threaded child process."""
+    code = f"""
+import json, time, sys
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+import workloads as W
+from oracle import build_hierarchy, UMG
+cfg = W.WORKLOADS[{workload_id}].with_R({R})
+xyz, tet, nu, tags = cfg.mesh()
+H = build_hierarchy(xyz, tet, nu, tags, {R})
+umg = UMG(H)
+lv = H.finest
+f = cfg.forcing_field()
+t0 = time.perf_counter()
+b = umg.rhs(f)
+x0 = np.zeros((4, lv.N)); x0[:3] = cfg.dirichlet_field(); x0[:3, lv.free] = 0.0
+x, hist = umg.solve(x0, b, rtol=1e-8, max_cycles=100)
+t = time.perf_counter() - t0
+print(json.dumps({{"seconds": t, "dofs": lv.ndofs(), "cycles": len(hist) - 1}}))
+"""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = "1"
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=timeout, env=env)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-R", type=int, default=6,
+                    help="refinements of the oracle's bounded sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "
+              f"(requested --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    import paper_1511_02134_amd as P
+
+    cfg = W.WORKLOADS[args.workload]
+    xyz, tet, nu, tags = cfg.mesh()
+    precision = 1 if cfg.precision == "mixed" else 0
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision)
+    dofs = s.num_dofs()
+    dev = torch.device("cuda")
+    f = torch.tensor(cfg.forcing_field(), dtype=torch.float64, device=dev)
+    x0n = torch.zeros(4, s.num_nodes(), dtype=torch.float64, device=dev)
+    x0n[:3] = torch.tensor(cfg.dirichlet_field(), device=dev)
+    _, dmask = s.node_info()
+    x0n[:3, ~torch.tensor(dmask, device=dev)] = 0.0
+    f_int = s.scatter(f)
+    x0 = s.scatter(x0n)
+    x = torch.empty_like(x0)
+    torch.cuda.synchronize()
+
+    def step():
+        b = s.rhs(f_int)
+        x.copy_(x0)
+        return s.solve(x, b, rtol=1e-8, max_cycles=100)
+
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    if info["status"] != 0:
+        print(f"solve did not converge: {info}", file=sys.stderr)
+        sys.exit(1)
+
+    # work unit: one K apply on the finest level, FP64
+    y = torch.empty_like(x)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    times = []
+    for _ in range(25):
+        ev[0].record()
+        s.apply(x, None, out=y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    t_apply = float(np.median(times[5:]))
+
+    # roofline of the dominant kernel: every finest-level velocity colour sweep
+    # of the same steps, bracketed by hipEvents on the solver's stream
+    s.set_timing(True)
+    for _ in range(min(args.steps, 3)):
+        step()
+    torch.cuda.synchronize()
+    nvel, ms_vel, bytes_vel = s.kernel_time(P.K_VEL)
+    npres, ms_pres, bytes_pres = s.kernel_time(P.K_PRES)
+    napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
+    s.set_timing(False)
+    vel_avg_ms = ms_vel / max(nvel, 1)
+    achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": dofs / (ms_per_step * 1e-3),
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32-in-f64",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg.name,
+            "mesh": f"box [0,{cfg.a}]x[0,1]^2, {tet.shape[0]} Kuhn macro tetrahedra",
+            "refinements": cfg.R,
+            "dofs": dofs,
+            "cycle": "V(3,3)",
+            "rtol": 1e-8,
+            "cycles": info["cycles"],
+            "rho_mean": info["rho_mean"],
+        },
+        "tme_factor": ms_per_step / t_apply,
+        "t_apply_ms": t_apply,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_colour<double,velocity> (finest level)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": nvel,
+            "avg_us": 1000.0 * vel_avg_ms,
+            "bytes_per_launch": bytes_vel / max(nvel, 1),
+        },
+        "kernel_classes": {
+            "velocity_sweep": {"launches": nvel, "ms": ms_vel,
+                               "GB/s": bytes_vel / max(ms_vel, 1e-12) / 1e6},
+            "pressure_sweep": {"launches": npres, "ms": ms_pres,
+                               "GB/s": bytes_pres / max(ms_pres, 1e-12) / 1e6},
+            "full_passes": {"launches": napp, "ms": ms_app,
+                            "GB/s": bytes_app / max(ms_app, 1e-12) / 1e6},
+        },
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(args.workload, args.cpu_R)
+        line["cpu_baseline"] = {
+            "value": cb["dofs"] / cb["seconds"],
+            "unit": "DoF/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": (f"oracle (numpy/scipy, single thread) full solve of the same problem "
+                       f"at {args.cpu_R} refinements ({cb['dofs']} DoFs, {cb['cycles']} cycles, "
+                       f"{cb['seconds']:.1f} s; setup excluded)"),
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * hhg.h -- C ABI of the MI355X Uzawa-multigrid Stokes solver.
+ *
+ * Method: all-at-once Uzawa multigrid (UMG) for the P1-P1 PSPG-stabilised
+ * Stokes system in Laplace form on hierarchical hybrid grids (Gmeiner, Huber,
+ * John, Ruede, Wohlmuth, arXiv:1511.02134): Section 2.1 (discretisation,
+ * eq. linear-system), Section 3.3 (inexact Uzawa smoother, eq. Uzawa_smooth),
+ * Section 3.5 (smoothers, V-cycle), Section 3.6 (stopping criterion) and
+ * Section 3.7 (coarse-grid PMINRES).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * Status: every call returns an hhg_status; nothing throws across the ABI.
+ *    Arguments and meshes are validated on the host before any launch; a
+ *    failed validation returns HHG_EINVAL and launches nothing.  The message
+ *    of the last failure is returned by hhg_last_error (per context) or
+ *    hhg_global_error (calls that have no context yet).
+ *  * Memory: the caller owns all device memory.  hhg_plan reports the size of
+ *    one device workspace; hhg_create carves every table and work vector out
+ *    of it.  The library never allocates device memory.
+ *  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every
+ *    call only enqueues work on that stream unless it says it synchronises.
+ *  * Levels: level l = 0..L holds the mesh refined R_l = l + 2 times (level 0
+ *    is the paper's coarse grid T_0, the twice refined macro mesh); L = R - 2.
+ *  * Vectors: a "vector" of level l is an array of 4 fields (u_x, u_y, u_z, p)
+ *    of hhg_vec_len(ctx, l) values each, field-major, in the library's
+ *    per-macro layout: every macro tetrahedron stores the full closure of its
+ *    refined vertices (tetrahedral slab/row order, each row split into four
+ *    sub-rows by i mod 4), so vertices on macro faces, edges and corners
+ *    exist once per macro that contains them.  All calls keep those copies
+ *    identical (the ghost exchange).  Vectors are double precision unless
+ *    stated otherwise.  hhg_scatter / hhg_gather convert to and from nodal
+ *    arrays in lattice order.
+ *  * Nodal (lattice) order: node (X, Y, Z) of the level-l lattice, integer
+ *    coordinates in units of 2^-R_l, has index X + nx*(Y + ny*Z) where
+ *    nx, ny, nz are the lattice extents of the bounding box of the mesh.
+ *  * Dirichlet data live in the Dirichlet velocity entries of the solution
+ *    vector x and are never modified; the residual and K x vanish on those
+ *    rows.  Pressure is an unknown at every vertex.
+ */
+#ifndef HHG_H
+#define HHG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hhg_ctx hhg_ctx;
+typedef void* hhg_stream; /* hipStream_t */
+
+typedef enum {
+    HHG_OK = 0,
+    HHG_EINVAL = 1,   /* bad argument or malformed mesh; nothing was launched */
+    HHG_ENOMEM = 2,   /* workspace too small */
+    HHG_EDEVICE = 3,  /* a HIP runtime call failed */
+    HHG_ENOCONV = 4,  /* solve stopped before the tolerance (info is filled) */
+    HHG_ENAN = 5      /* NaN or Inf in a residual norm */
+} hhg_status;
+
+/* Macro mesh T_{-2} (Section 2.1).  All arrays are host memory, read during
+ * the call only.  Requirements checked by hhg_plan / hhg_create:
+ *   xyz [nv][3]   vertex coordinates on the integer lattice;
+ *   tet [nt][4]   vertex ids in Kuhn path order: tet[1]-tet[0], tet[2]-tet[1],
+ *                 tet[3]-tet[2] are the three distinct positive unit vectors;
+ *                 the tetrahedra tile the bounding box of xyz conformingly;
+ *   nu  [nt]      per-macro viscosity > 0 (NULL: all 1);
+ *   face_bc [nt][4] tag of the face opposite vertex f: 0 interior (shared by
+ *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing). */
+typedef struct {
+    int32_t nv;
+    const double* xyz;
+    int32_t nt;
+    const int32_t* tet;
+    const double* nu;
+    const int8_t* face_bc;
+} hhg_mesh;
+
+/* Solver options (Section 3.5 and Table "settings", UMG column). */
+typedef struct {
+    int32_t nu1, nu2;     /* pre / post smoothing steps: V(nu1, nu2); default 3, 3 */
+    int32_t cycle;        /* 0: V-cycle; 1: variable V-cycle (+2 steps per coarser level) */
+    int32_t p_sweep;      /* 0: forward pressure sweep (paper); 1: forward + backward */
+    double omega;         /* pressure under-relaxation; default 0.3 */
+    int32_t precision;    /* 0: FP64 throughout; 1: FP32 cycles inside FP64 refinement */
+    double coarse_rtol;   /* coarse PMINRES relative tolerance; default 1e-14 */
+    int32_t coarse_maxit; /* coarse PMINRES iteration cap; default 500 */
+    int32_t block_order;  /* workgroup -> tile order: 0 natural, 1 XCD-aware (default),
+                             2 reversed (a schedule permutation used to test that
+                             results do not depend on workgroup order) */
+} hhg_opts;
+
+/* Result of hhg_solve. */
+typedef struct {
+    int32_t cycles;        /* cycles performed */
+    int32_t status;        /* hhg_status of the solve */
+    double r0;             /* ||f~ - K x_0||_2 (Section 3.6) */
+    double r_final;        /* ||f~ - K x_k||_2 after the last cycle */
+    double rel_res;        /* r_final / r0 */
+    double rho_mean;       /* (r_final / r0)^(1/cycles) */
+    double rho_max;        /* largest ||r_k|| / ||r_{k-1}|| */
+    double t_solve_ms;     /* wall time of the cycles, hipEvent timed on the stream */
+    double res_hist[256];  /* ||r_k||_2, k = 0..min(cycles, 255) */
+} hhg_solve_info;
+
+/* Fills opts with the defaults above. */
+void hhg_default_opts(hhg_opts* opts);
+
+/* Validates the mesh and options and reports the device workspace size in
+ * bytes for n_refine refinements (2 <= n_refine <= 10).  Host only. */
+hhg_status hhg_plan(const hhg_mesh* mesh, int32_t n_refine, const hhg_opts* opts,
+                    size_t* workspace_bytes);
+
+/* Builds the hierarchy (levels 2..n_refine), stencils (one 15-point stencil
+ * per macro and per interface primitive and level, from the P1 element
+ * matrices of a_1, b, c_l and g_l, Section 2.1) and index tables, and uploads
+ * them into d_workspace (device memory of at least hhg_plan's size,
+ * 256-byte aligned).  Synchronises the device.  With d_workspace == NULL a
+ * host-only context is built for inspection (hhg_node_coords, counts); every
+ * device call on it returns HHG_EINVAL. */
+hhg_status hhg_create(const hhg_mesh* mesh, int32_t n_refine, const hhg_opts* opts,
+                      void* d_workspace, size_t workspace_bytes, hhg_ctx** ctx);
+void hhg_destroy(hhg_ctx* ctx);
+const char* hhg_last_error(const hhg_ctx* ctx);
+const char* hhg_global_error(void);
+
+/* Sizes and geometry (host only). */
+int32_t hhg_num_levels(const hhg_ctx* ctx);               /* L + 1 */
+int64_t hhg_vec_len(const hhg_ctx* ctx, int32_t level);   /* values per field */
+int64_t hhg_num_nodes(const hhg_ctx* ctx, int32_t level); /* lattice nodes */
+int64_t hhg_num_dofs(const hhg_ctx* ctx, int32_t level);  /* 3*free velocity nodes + nodes */
+int64_t hhg_num_interface(const hhg_ctx* ctx, int32_t level); /* vertices on macro faces */
+/* Integer lattice coordinates [N][3] and velocity Dirichlet flags [N] (either
+ * may be NULL) of the level's nodes in lattice order, into host arrays. */
+hhg_status hhg_node_info(const hhg_ctx* ctx, int32_t level, int32_t* ijk, int8_t* dirichlet);
+
+/* Lumped mass m_i = int phi_i of every node (lattice order) into a host
+ * array [N]: the weights of the mean-zero pressure projection. */
+hhg_status hhg_mass_weights(const hhg_ctx* ctx, int32_t level, double* m);
+
+/* Host-only self-check of the index tables: runs the kernels' index
+ * arithmetic (tile decoding, row addressing, neighbour tables, transfer
+ * addressing) on the CPU over every level and verifies that each access stays
+ * inside the arrays and reaches the intended lattice vertex, that every
+ * vertex is visited exactly once per sweep and that colour sweeps only touch
+ * their colour.  Returns HHG_EINVAL with a message on the first violation. */
+hhg_status hhg_check_layout(const hhg_ctx* ctx);
+
+/* Layout conversion.  d_nodal: nfields arrays of N doubles (lattice order);
+ * d_x: nfields arrays of hhg_vec_len doubles.  Scatter writes every copy of
+ * every vertex; gather reads each vertex once.  1 <= nfields <= 4. */
+hhg_status hhg_scatter(hhg_ctx* ctx, int32_t level, const double* d_nodal, int32_t nfields,
+                       void* d_x, hhg_stream stream);
+hhg_status hhg_gather(hhg_ctx* ctx, int32_t level, const void* d_x, int32_t nfields,
+                      double* d_nodal, hhg_stream stream);
+/* Ghost exchange (Section 3.4, Figure "ghost layer structure"): copies the
+ * primary value of every interface vertex into all its other macro copies. */
+hhg_status hhg_exchange(hhg_ctx* ctx, int32_t level, void* d_x, int32_t nfields,
+                        hhg_stream stream);
+
+/* Right-hand side of eq. (linear-system) on the finest level from the nodal
+ * P1 interpolant of the forcing: d_rhs = (M f on free velocity rows,
+ * g_l(I_h f) on pressure rows).  d_f: 3 fields in the internal layout. */
+hhg_status hhg_rhs(hhg_ctx* ctx, const void* d_f, void* d_rhs, hhg_stream stream);
+
+/* y = K x (eq. linear-system) on level l: rows of free velocity nodes and all
+ * pressure rows; Dirichlet velocity rows of y are 0.  x must not alias y. */
+hhg_status hhg_apply(hhg_ctx* ctx, int32_t level, const void* d_x, void* d_y,
+                     hhg_stream stream);
+/* r = b - K x on level l.  If h_norm is not NULL the call synchronises the
+ * stream and stores ||r||_2 (free velocity rows and all pressure rows). */
+hhg_status hhg_residual(hhg_ctx* ctx, int32_t level, const void* d_x, const void* d_b,
+                        void* d_r, double* h_norm, hhg_stream stream);
+/* `steps` inexact Uzawa smoothing steps (eq. Uzawa_smooth) in place on x:
+ * symmetric 4-colour Gauss-Seidel on the velocity, then the pressure sweep
+ * on C with relaxation omega.  Colour of vertex (X,Y,Z) = (X+Y+Z) mod 4. */
+hhg_status hhg_smooth(hhg_ctx* ctx, int32_t level, void* d_x, const void* d_b, int32_t steps,
+                      hhg_stream stream);
+/* Restriction of a level-l residual to the right-hand side of level l-1
+ * (transpose of P1 interpolation, velocity Dirichlet rows zeroed), and
+ * interpolation of a level-(l-1) correction added to a level-l vector. */
+hhg_status hhg_restrict(hhg_ctx* ctx, int32_t level, const void* d_r_fine, void* d_b_coarse,
+                        hhg_stream stream);
+hhg_status hhg_prolong_add(hhg_ctx* ctx, int32_t level, const void* d_e_coarse,
+                           void* d_x_fine, hhg_stream stream);
+/* Level-0 solve (Section 3.7): block-diagonal preconditioned MINRES on the
+ * whole coarse Stokes system, preconditioner diag(A_0^-1, lumped 1/nu-weighted
+ * mass), run to opts.coarse_rtol, pressure projected to zero mean when the
+ * pressure has a null space.  x0 = K_0^-1 b0.  iters / relres (host, may be
+ * NULL) synchronise the stream. */
+hhg_status hhg_coarse_solve(hhg_ctx* ctx, const void* d_b0, void* d_x0, int32_t* iters,
+                            double* relres, hhg_stream stream);
+/* Pressure projection to zero mean, p -= (sum m_i p_i)/(sum m_i) with
+ * m_i = int phi_i; no-op when a natural boundary removes the null space. */
+hhg_status hhg_project(hhg_ctx* ctx, int32_t level, void* d_x, hhg_stream stream);
+
+/* One solver iteration on the finest level: a V(nu1,nu2) (or variable) cycle
+ * followed by the mean-zero projection.  In mixed precision the cycle runs
+ * in FP32 on the FP64 residual scaled by its norm (iterative refinement). */
+hhg_status hhg_vcycle(hhg_ctx* ctx, void* d_x, const void* d_b, hhg_stream stream);
+/* Cycles from x until ||b - K x||_2 <= rtol ||b - K x_0||_2 (Section 3.6) or
+ * max_cycles (<= 255).  Synchronises once per cycle (an 8-byte readback).
+ * Returns HHG_ENOCONV if the tolerance was not met, HHG_ENAN on a non-finite
+ * norm; info (may be NULL) is filled in every case. */
+hhg_status hhg_solve(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int32_t max_cycles,
+                     hhg_solve_info* info, hhg_stream stream);
+
+/* Adjoint gradients of J = 1/2 ||u - u_obs||^2 (not in the paper): given the
+ * forward solution x (with its Dirichlet values), the adjoint solution lambda
+ * of K lambda = (u - u_obs, 0) and the forcing f (3 fields, internal layout;
+ * NULL means f = 0), writes dJ/dnu_e for every macro into d_dJ_dnu [nt] and
+ * dJ/df (3 fields, internal layout) into d_dJ_df (may be NULL). */
+hhg_status hhg_grad(hhg_ctx* ctx, const void* d_x, const void* d_lambda, const void* d_f,
+                    double* d_dJ_dnu, void* d_dJ_df, hhg_stream stream);
+
+/* Replaces the per-macro viscosity (host array [nt], > 0) and rebuilds every
+ * stencil table; synchronises the device. */
+hhg_status hhg_set_viscosity(hhg_ctx* ctx, const double* nu);
+
+/* Per-kernel-class timing.  When enabled, every launch of the classes below
+ * on the finest level is bracketed by hipEvents on its stream; hhg_kernel_time
+ * synchronises and returns the number of timed launches, their summed
+ * duration in ms and the algorithmic bytes they moved. */
+enum {
+    HHG_K_VEL = 0,     /* velocity colour sweep, finest level */
+    HHG_K_PRES = 1,    /* pressure colour sweep, finest level */
+    HHG_K_APPLY = 2,   /* B^T p / B u / residual passes, finest level */
+    HHG_K_NCLASS = 3
+};
+hhg_status hhg_set_timing(hhg_ctx* ctx, int32_t on);
+hhg_status hhg_kernel_time(hhg_ctx* ctx, int32_t kclass, int64_t* launches, double* ms,
+                           double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHG_H */

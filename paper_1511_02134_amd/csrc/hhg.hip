@@ -1,0 +1,1220 @@
+// C ABI of the Uzawa multigrid Stokes solver: context, workspace layout,
+// device upload and the multigrid driver (Sections 3.3 - 3.7).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hhg.h"
+#include "hierarchy.hpp"
+#include "kernels.hpp"
+
+using namespace hhg;
+
+namespace {
+
+thread_local std::string g_error;
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(char* b) : base(b) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) / 256 * 256;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct DevLevelArrays {
+    int32_t *slab_base, *if_self, *if_nb, *if_sid, *if_cptr, *if_copy, *if_flag, *rif_fine;
+    Tile *vtiles, *ctiles;
+    double *st64, *gst64, *nu64;
+    float *st32, *gst32, *nu32;
+    int32_t *slot_node, *node_slot;
+    // work vectors (4 fields each)
+    double *x64, *b64, *r64, *t64;
+    float *x32, *b32, *r32, *t32;
+};
+
+struct TimerPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct hhg_ctx {
+    MeshInfo mi;
+    hhg_opts opts;
+    int R = 0, L = 0;
+    std::vector<HostLevel> H;
+    CoarseHost CH;
+    bool device = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<DevLevelArrays> A;
+    std::vector<LevelDev<double>> D64;
+    std::vector<LevelDev<float>> D32;
+    CoarseDev cd{};
+    size_t coarse_smem = 0;
+    double* partials = nullptr;
+    int npartials = 0;
+    double* scal = nullptr;        // small device scalars
+    double* gpart = nullptr;       // gradient partials
+    std::vector<double> inv_mass;  // 1 / sum_i m_i per level
+    std::string err;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<TimerPair> tpairs[HHG_K_NCLASS];
+    double tbytes[HHG_K_NCLASS] = {0, 0, 0};
+    // algorithmic bytes per launch (finest level) of the timed classes
+    double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
+    double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
+};
+
+namespace {
+
+hhg_status fail(hhg_ctx* c, hhg_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    g_error = msg;
+    return s;
+}
+
+#define HIPCHECK(ctx, call)                                                         \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return fail(ctx, HHG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool opts_ok(const hhg_opts* o, std::string* err) {
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 == 0 || o->nu1 > 64 || o->nu2 > 64) {
+        *err = "smoothing steps must be in 0..64 with nu1 + nu2 > 0";
+        return false;
+    }
+    if (o->cycle < 0 || o->cycle > 1 || o->p_sweep < 0 || o->p_sweep > 1 || o->precision < 0 ||
+        o->precision > 1 || o->block_order < 0 || o->block_order > 2) {
+        *err = "invalid option value";
+        return false;
+    }
+    if (!(o->omega > 0.0 && o->omega < 2.0)) {
+        *err = "omega must lie in (0, 2)";
+        return false;
+    }
+    if (!(o->coarse_rtol > 0.0) || o->coarse_maxit < 1 || o->coarse_maxit > 100000) {
+        *err = "invalid coarse solver settings";
+        return false;
+    }
+    return true;
+}
+
+// Builds the host hierarchy and computes the workspace layout (when ws is
+// NULL only the size).
+hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* opts) {
+    std::string err;
+    if (!mesh) return fail(c, HHG_EINVAL, "mesh is NULL");
+    if (R < 2 || R > 10) return fail(c, HHG_EINVAL, "n_refine must lie in 2..10");
+    hhg_opts o;
+    hhg_default_opts(&o);
+    if (opts) o = *opts;
+    if (!opts_ok(&o, &err)) return fail(c, HHG_EINVAL, err);
+    if (!validate_mesh(mesh, &c->mi, &err)) return fail(c, HHG_EINVAL, err);
+    c->opts = o;
+    c->R = R;
+    c->L = R - 2;
+    c->H.resize(c->L + 1);
+    for (int l = 0; l <= c->L; ++l)
+        if (!build_level(c->mi, l + 2, o.block_order, &c->H[l], &err))
+            return fail(c, HHG_EINVAL, err);
+    for (int l = 0; l < c->L; ++l) {
+        link_levels(&c->H[l], c->H[l + 1]);
+        for (int32_t t : c->H[l].rif_fine)
+            if (t < 0) return fail(c, HHG_EINVAL, "internal error: coarse interface vertex missing");
+    }
+    if (!build_coarse(c->mi, c->H[0], &c->CH, &err)) return fail(c, HHG_EINVAL, err);
+    if (c->CH.nd > 4096) return fail(c, HHG_EINVAL, "coarse system larger than 4096 unknowns");
+    return HHG_OK;
+}
+
+size_t layout(hhg_ctx* c, char* ws) {
+    Carver cv(ws);
+    const int nl = c->L + 1;
+    c->A.assign(nl, DevLevelArrays{});
+    const bool mixed = c->opts.precision == 1;
+    int maxblocks = 1;
+    for (int l = 0; l < nl; ++l) {
+        HostLevel& h = c->H[l];
+        DevLevelArrays& a = c->A[l];
+        a.slab_base = cv.take<int32_t>(h.slab_base.size());
+        a.vtiles = cv.take<Tile>(std::max<size_t>(1, h.vtiles.size()));
+        a.ctiles = cv.take<Tile>(std::max<size_t>(1, h.ctiles.size()));
+        a.if_self = cv.take<int32_t>(std::max(1, h.nif));
+        a.if_nb = cv.take<int32_t>(std::max<size_t>(1, h.if_nb.size()));
+        a.if_sid = cv.take<int32_t>(std::max(1, h.nif));
+        a.if_cptr = cv.take<int32_t>(h.if_cptr.size());
+        a.if_copy = cv.take<int32_t>(std::max<size_t>(1, h.if_copy.size()));
+        a.if_flag = cv.take<int32_t>(std::max(1, h.nif));
+        a.rif_fine = cv.take<int32_t>(std::max(1, h.nif));
+        a.st64 = cv.take<double>(h.st.size());
+        a.gst64 = cv.take<double>(h.gst.size());
+        a.nu64 = cv.take<double>(h.nm);
+        a.st32 = cv.take<float>(h.st.size());
+        a.gst32 = cv.take<float>(h.gst.size());
+        a.nu32 = cv.take<float>(h.nm);
+        a.slot_node = cv.take<int32_t>(h.len);
+        a.node_slot = cv.take<int32_t>(h.N);
+        const size_t v4 = 4 * (size_t)h.len;
+        a.r64 = cv.take<double>(v4);
+        a.t64 = cv.take<double>(v4);
+        a.x64 = a.b64 = nullptr;
+        if (l < c->L || true) {
+            a.x64 = cv.take<double>(v4);
+            a.b64 = cv.take<double>(v4);
+        }
+        a.x32 = a.b32 = a.r32 = a.t32 = nullptr;
+        if (mixed) {
+            a.x32 = cv.take<float>(v4);
+            a.b32 = cv.take<float>(v4);
+            a.r32 = cv.take<float>(v4);
+            a.t32 = cv.take<float>(v4);
+        }
+        const int nb = (int)h.vtiles.size() + (h.nif + TPB - 1) / TPB;
+        maxblocks = std::max(maxblocks, nb);
+        maxblocks = std::max(maxblocks, (int)h.ctiles.size());
+    }
+    c->npartials = maxblocks;
+    c->partials = cv.take<double>(maxblocks);
+    c->gpart = cv.take<double>(maxblocks);
+    c->scal = cv.take<double>(64);
+    // coarse system
+    CoarseHost& C = c->CH;
+    CoarseDev& d = c->cd;
+    d.nd = C.nd;
+    d.nfv = C.nfv;
+    d.N = C.N;
+    d.rowptr = cv.take<int32_t>(C.rowptr.size());
+    d.col = cv.take<int32_t>(std::max<size_t>(1, C.col.size()));
+    d.val = cv.take<double>(std::max<size_t>(1, C.val.size()));
+    d.ainv = cv.take<double>(std::max<size_t>(1, C.ainv.size()));
+    d.pdinv = cv.take<double>(C.N);
+    d.mass = cv.take<double>(C.N);
+    d.vel_node = cv.take<int32_t>(std::max(1, C.nfv));
+    d.node_vidx = cv.take<int32_t>(C.N);
+    d.node_slot = cv.take<int32_t>(C.N);
+    d.node_cptr = cv.take<int32_t>(C.node_cptr.size());
+    d.node_copy = cv.take<int32_t>(C.node_copy.size());
+    d.gscratch = cv.take<double>((size_t)9 * C.nd);
+    return cv.off + 256;
+}
+
+template <typename T>
+void fill_view(hhg_ctx* c, int l, LevelDev<T>& v) {
+    HostLevel& h = c->H[l];
+    DevLevelArrays& a = c->A[l];
+    v.n = h.n;
+    v.nm = h.nm;
+    v.mstride = h.mstride;
+    v.len = h.len;
+    v.slab_base = a.slab_base;
+    v.vtiles = a.vtiles;
+    v.n_vtiles = (int32_t)h.vtiles.size();
+    v.ctiles = a.ctiles;
+    v.n_ctiles = (int32_t)h.ctiles.size();
+    v.nif = h.nif;
+    v.if_self = a.if_self;
+    v.if_nb = a.if_nb;
+    v.if_sid = a.if_sid;
+    v.if_cptr = a.if_cptr;
+    v.if_copy = a.if_copy;
+    v.if_flag = a.if_flag;
+    for (int q = 0; q < 5; ++q) v.col_start[q] = h.col_start[q];
+    for (int q = 0; q < 4; ++q) v.vel_end[q] = h.vel_end[q];
+    v.rif_fine = a.rif_fine;
+}
+
+template <typename T>
+hhg_status upload(hhg_ctx* c, T* dst, const void* src, size_t count) {
+    if (count == 0) return HHG_OK;
+    HIPCHECK(c, hipMemcpy(dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return HHG_OK;
+}
+
+hhg_status upload_stencils(hhg_ctx* c) {
+    for (int l = 0; l <= c->L; ++l) {
+        HostLevel& h = c->H[l];
+        DevLevelArrays& a = c->A[l];
+        std::vector<double> nu(h.nm);
+        for (int m = 0; m < h.nm; ++m) nu[m] = c->mi.macros[m].nu;
+        std::vector<float> st32(h.st.begin(), h.st.end()), gst32(h.gst.begin(), h.gst.end()),
+            nu32(nu.begin(), nu.end());
+        hhg_status s;
+        if ((s = upload<double>(c, a.st64, h.st.data(), h.st.size())) != HHG_OK) return s;
+        if ((s = upload<double>(c, a.gst64, h.gst.data(), h.gst.size())) != HHG_OK) return s;
+        if ((s = upload<double>(c, a.nu64, nu.data(), nu.size())) != HHG_OK) return s;
+        if ((s = upload<float>(c, a.st32, st32.data(), st32.size())) != HHG_OK) return s;
+        if ((s = upload<float>(c, a.gst32, gst32.data(), gst32.size())) != HHG_OK) return s;
+        if ((s = upload<float>(c, a.nu32, nu32.data(), nu32.size())) != HHG_OK) return s;
+        c->D64[l].st = a.st64;
+        c->D64[l].gst = a.gst64;
+        c->D64[l].macro_nu = a.nu64;
+        c->D32[l].st = a.st32;
+        c->D32[l].gst = a.gst32;
+        c->D32[l].macro_nu = a.nu32;
+        double msum = 0.0;
+        for (int64_t v = 0; v < h.N; ++v) {
+            int sid = h.node_sid[v];
+            const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
+                                        : &h.st[(size_t)sid * ST_SIZE];
+            msum += rec[ST_MASS];
+        }
+        c->inv_mass[l] = 1.0 / msum;
+    }
+    CoarseHost& C = c->CH;
+    hhg_status s;
+    if ((s = upload<double>(c, (double*)c->cd.val, C.val.data(), C.val.size())) != HHG_OK) return s;
+    if ((s = upload<double>(c, (double*)c->cd.ainv, C.ainv.data(), C.ainv.size())) != HHG_OK)
+        return s;
+    if ((s = upload<double>(c, (double*)c->cd.pdinv, C.pdinv.data(), C.pdinv.size())) != HHG_OK)
+        return s;
+    if ((s = upload<double>(c, (double*)c->cd.mass, C.mass.data(), C.mass.size())) != HHG_OK)
+        return s;
+    c->cd.inv_mass = c->inv_mass[0];
+    return HHG_OK;
+}
+
+hhg_status upload_all(hhg_ctx* c) {
+    const int nl = c->L + 1;
+    c->D64.assign(nl, LevelDev<double>{});
+    c->D32.assign(nl, LevelDev<float>{});
+    c->inv_mass.assign(nl, 0.0);
+    for (int l = 0; l < nl; ++l) {
+        HostLevel& h = c->H[l];
+        DevLevelArrays& a = c->A[l];
+        hhg_status s;
+#define UP(T, dst, vec) \
+    if ((s = upload<T>(c, dst, vec.data(), vec.size())) != HHG_OK) return s;
+        UP(int32_t, a.slab_base, h.slab_base);
+        UP(Tile, a.vtiles, h.vtiles);
+        UP(Tile, a.ctiles, h.ctiles);
+        UP(int32_t, a.if_self, h.if_self);
+        UP(int32_t, a.if_nb, h.if_nb);
+        UP(int32_t, a.if_sid, h.if_sid);
+        UP(int32_t, a.if_cptr, h.if_cptr);
+        UP(int32_t, a.if_copy, h.if_copy);
+        UP(int32_t, a.if_flag, h.if_flag);
+        if (!h.rif_fine.empty()) UP(int32_t, a.rif_fine, h.rif_fine);
+        UP(int32_t, a.slot_node, h.slot_node);
+        UP(int32_t, a.node_slot, h.node_slot);
+        fill_view(c, l, c->D64[l]);
+        fill_view(c, l, c->D32[l]);
+    }
+    CoarseHost& C = c->CH;
+    CoarseDev& d = c->cd;
+    std::vector<int32_t> vidx(C.N, -1);
+    for (int i = 0; i < C.nfv; ++i) vidx[C.vel_node[i]] = i;
+    hhg_status s;
+    UP(int32_t, (int32_t*)d.rowptr, C.rowptr);
+    UP(int32_t, (int32_t*)d.col, C.col);
+    UP(int32_t, (int32_t*)d.vel_node, C.vel_node);
+    UP(int32_t, (int32_t*)d.node_vidx, vidx);
+    UP(int32_t, (int32_t*)d.node_slot, C.node_slot);
+    UP(int32_t, (int32_t*)d.node_cptr, C.node_cptr);
+    UP(int32_t, (int32_t*)d.node_copy, C.node_copy);
+#undef UP
+    d.maxit = c->opts.coarse_maxit;
+    d.tol = c->opts.coarse_rtol;
+    d.project = c->mi.project ? 1 : 0;
+    c->coarse_smem = (size_t)9 * C.nd * sizeof(double);
+    d.use_lds = c->coarse_smem <= 60 * 1024 ? 1 : 0;
+    if (!d.use_lds) c->coarse_smem = 0;
+    if ((s = upload_stencils(c)) != HHG_OK) return s;
+    // algorithmic bytes of the timed kernel classes on the finest level
+    HostLevel& h = c->H[c->L];
+    double Nc[4] = {0, 0, 0, 0}, Nfc[4] = {0, 0, 0, 0}, Nf = 0;
+    for (int64_t v = 0; v < h.N; ++v) {
+        int X = (int)(v % h.lat[0]), Y = (int)((v / h.lat[0]) % h.lat[1]),
+            Z = (int)(v / ((int64_t)h.lat[0] * h.lat[1]));
+        int col = (X + Y + Z) & 3;
+        Nc[col] += 1;
+        if (!h.node_dir[v]) {
+            Nfc[col] += 1;
+            Nf += 1;
+        }
+    }
+    const double Nall = (double)h.N;
+    const double vs = c->opts.precision == 1 ? 4.0 : 8.0;
+    for (int col = 0; col < 4; ++col) {
+        const double nbr = Nc[(col + 1) & 3] + Nc[(col + 3) & 3];
+        c->bytes_vel[col] = vs * 3.0 * (nbr + 2.0 * Nfc[col]);
+        c->bytes_pres[col] = vs * (nbr + 3.0 * Nc[col]);
+    }
+    c->bytes_ru = vs * (Nall + 6.0 * Nf);
+    c->bytes_bp = vs * (3.0 * Nall + 2.0 * Nall);
+    c->bytes_res = vs * (4.0 * Nall + 2.0 * (3.0 * Nf + Nall));
+    return HHG_OK;
+}
+
+// ------------------------------------------------------------------ timing
+hipEvent_t next_event(hhg_ctx* c) {
+    if (c->evused == c->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->evpool.push_back(e);
+    }
+    return c->evpool[c->evused++];
+}
+
+struct Timed {
+    hhg_ctx* c;
+    int cls;
+    hipStream_t s;
+    TimerPair tp{nullptr, nullptr};
+    bool on;
+    Timed(hhg_ctx* c_, int cls_, hipStream_t s_, bool finest, double bytes)
+        : c(c_), cls(cls_), s(s_), on(c_->timing && finest) {
+        if (!on) return;
+        tp.a = next_event(c);
+        tp.b = next_event(c);
+        if (!tp.a || !tp.b) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(tp.a, s);
+        c->tbytes[cls] += bytes;
+    }
+    ~Timed() {
+        if (!on) return;
+        (void)hipEventRecord(tp.b, s);
+        c->tpairs[cls].push_back(tp);
+    }
+};
+
+inline int grid_for(size_t n) { return (int)std::min<size_t>((n + TPB - 1) / TPB, 8192); }
+
+// ------------------------------------------------------------------ operators
+template <typename T>
+LevelDev<T>& view(hhg_ctx* c, int l);
+template <>
+LevelDev<double>& view<double>(hhg_ctx* c, int l) {
+    return c->D64[l];
+}
+template <>
+LevelDev<float>& view<float>(hhg_ctx* c, int l) {
+    return c->D32[l];
+}
+
+template <typename T>
+void vecs(hhg_ctx* c, int l, T** x, T** b, T** r, T** t);
+template <>
+void vecs<double>(hhg_ctx* c, int l, double** x, double** b, double** r, double** t) {
+    DevLevelArrays& a = c->A[l];
+    *x = a.x64;
+    *b = a.b64;
+    *r = a.r64;
+    *t = a.t64;
+}
+template <>
+void vecs<float>(hhg_ctx* c, int l, float** x, float** b, float** r, float** t) {
+    DevLevelArrays& a = c->A[l];
+    *x = a.x32;
+    *b = a.b32;
+    *r = a.r32;
+    *t = a.t32;
+}
+
+template <typename T, int MODE>
+void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    const bool finest = l == c->L;
+    double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
+    Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
+             bytes);
+    hipLaunchKernelGGL((k_full<T, MODE>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials);
+}
+
+template <typename T>
+void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
+    const int grid = v.n_vtiles + (cnt + TPB - 1) / TPB;
+    const bool finest = l == c->L;
+    if (vel) {
+        Timed tm(c, HHG_K_VEL, s, finest, c->bytes_vel[col]);
+        hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0));
+    } else {
+        Timed tm(c, HHG_K_PRES, s, finest, c->bytes_pres[col]);
+        hipLaunchKernelGGL((k_colour<T, false>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
+                           (T)c->opts.omega);
+    }
+}
+
+// one inexact Uzawa step (eq. Uzawa_smooth) in place
+template <typename T>
+void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
+    full_pass<T, MODE_RU>(c, l, x, b, t, s);
+    // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
+    // colour 3 right after the first would recompute identical values)
+    static const int vorder[7] = {0, 1, 2, 3, 2, 1, 0};
+    for (int q = 0; q < 7; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
+    full_pass<T, MODE_BP>(c, l, x, b, t, s);
+    for (int col = 0; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
+    if (c->opts.p_sweep == 1)
+        for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, false, x, t, s);
+}
+
+template <typename T>
+void fill(T* x, size_t n, T val, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(TPB), 0, s, x, n, val);
+}
+
+template <typename T>
+void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    {
+        Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
+        hipLaunchKernelGGL((k_full<T, MODE_RES>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
+                           c->partials);
+    }
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials, grid, out, 1);
+}
+
+template <typename T>
+void restrict_to(hhg_ctx* c, int l, const T* rf, T* bc, hipStream_t s) {
+    LevelDev<T>& C = view<T>(c, l - 1);
+    LevelDev<T>& F = view<T>(c, l);
+    const int grid = C.n_vtiles + (C.nif + TPB - 1) / TPB;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid), dim3(TPB), 0, s, C, F, rf, bc);
+}
+
+template <typename T>
+void prolong_add(hhg_ctx* c, int l, const T* ec, T* xf, hipStream_t s) {
+    LevelDev<T>& C = view<T>(c, l - 1);
+    LevelDev<T>& F = view<T>(c, l);
+    hipLaunchKernelGGL(k_prolong<T>, dim3(F.n_ctiles), dim3(TPB), 0, s, F, C, ec, xf);
+}
+
+template <typename T>
+void coarse_solve(hhg_ctx* c, const T* b, T* x, hipStream_t s) {
+    const size_t len = (size_t)c->H[0].len;
+    hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(CTPB), c->coarse_smem, s, c->cd, b, len, x, len,
+                       c->scal + 8);
+}
+
+template <typename T>
+void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
+    if (!c->mi.project) return;
+    LevelDev<T>& v = view<T>(c, l);
+    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    const size_t len = (size_t)v.len;
+    hipLaunchKernelGGL(k_mass_dot<T>, dim3(grid), dim3(TPB), 0, s, v, x + 3 * len, c->partials);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials, grid, c->scal + 4, 0);
+    hipLaunchKernelGGL(k_sub_mean<T>, dim3(grid_for(len)), dim3(TPB), 0, s, x + 3 * len, len,
+                       c->scal + 4, c->inv_mass[l]);
+}
+
+template <typename T>
+void vcycle(hhg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
+    T *xl, *bl, *rl, *tl;
+    vecs<T>(c, l, &xl, &bl, &rl, &tl);
+    if (l == 0) {
+        // x += K_0^-1 (b - K_0 x)
+        full_pass<T, MODE_RES>(c, 0, x, b, rl, s);
+        coarse_solve<T>(c, rl, tl, s);
+        const size_t n4 = 4 * (size_t)c->H[0].len;
+        hipLaunchKernelGGL(k_add<T>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, (const T*)tl, n4);
+        return;
+    }
+    const int extra = c->opts.cycle == 1 ? 2 * (c->L - l) : 0;
+    for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
+    full_pass<T, MODE_RES>(c, l, x, b, rl, s);
+    T *xc, *bc, *rc, *tc;
+    vecs<T>(c, l - 1, &xc, &bc, &rc, &tc);
+    restrict_to<T>(c, l, rl, bc, s);
+    if (l - 1 == 0) {
+        coarse_solve<T>(c, bc, xc, s);
+    } else {
+        fill<T>(xc, 4 * (size_t)c->H[l - 1].len, T(0), s);
+        vcycle<T>(c, l - 1, xc, bc, s);
+    }
+    prolong_add<T>(c, l, xc, x, s);
+    for (int q = 0; q < c->opts.nu2 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
+}
+
+}  // namespace
+
+// ============================================================== ABI
+extern "C" {
+
+void hhg_default_opts(hhg_opts* o) {
+    if (!o) return;
+    o->nu1 = 3;
+    o->nu2 = 3;
+    o->cycle = 0;
+    o->p_sweep = 0;
+    o->omega = 0.3;
+    o->precision = 0;
+    o->coarse_rtol = 1e-14;
+    o->coarse_maxit = 500;
+    o->block_order = 1;
+}
+
+const char* hhg_global_error(void) { return g_error.c_str(); }
+const char* hhg_last_error(const hhg_ctx* c) { return c ? c->err.c_str() : g_error.c_str(); }
+
+hhg_status hhg_plan(const hhg_mesh* mesh, int32_t R, const hhg_opts* opts, size_t* bytes) {
+    if (!bytes) return fail(nullptr, HHG_EINVAL, "workspace_bytes is NULL");
+    std::unique_ptr<hhg_ctx> c(new hhg_ctx());
+    hhg_status s = build_host(c.get(), mesh, R, opts);
+    if (s != HHG_OK) return s;
+    *bytes = layout(c.get(), nullptr);
+    return HHG_OK;
+}
+
+hhg_status hhg_create(const hhg_mesh* mesh, int32_t R, const hhg_opts* opts, void* ws, size_t bytes,
+                      hhg_ctx** out) {
+    if (!out) return fail(nullptr, HHG_EINVAL, "ctx output pointer is NULL");
+    *out = nullptr;
+    std::unique_ptr<hhg_ctx> c(new hhg_ctx());
+    hhg_status s = build_host(c.get(), mesh, R, opts);
+    if (s != HHG_OK) return s;
+    const size_t need = layout(c.get(), nullptr);
+    if (ws) {
+        if (bytes < need)
+            return fail(nullptr, HHG_ENOMEM,
+                        "workspace too small: need " + std::to_string(need) + " bytes");
+        if (((uintptr_t)ws) % 256 != 0) return fail(nullptr, HHG_EINVAL, "workspace not 256-byte aligned");
+        c->ws = (char*)ws;
+        c->ws_bytes = bytes;
+        layout(c.get(), c->ws);
+        if ((s = upload_all(c.get())) != HHG_OK) {
+            g_error = c->err;
+            return s;
+        }
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail(nullptr, HHG_EDEVICE, hipGetErrorString(e));
+        c->device = true;
+    }
+    *out = c.release();
+    return HHG_OK;
+}
+
+void hhg_destroy(hhg_ctx* c) {
+    if (!c) return;
+    for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int32_t hhg_num_levels(const hhg_ctx* c) { return c ? c->L + 1 : 0; }
+int64_t hhg_vec_len(const hhg_ctx* c, int32_t l) {
+    return (c && l >= 0 && l <= c->L) ? c->H[l].len : -1;
+}
+int64_t hhg_num_nodes(const hhg_ctx* c, int32_t l) {
+    return (c && l >= 0 && l <= c->L) ? c->H[l].N : -1;
+}
+int64_t hhg_num_dofs(const hhg_ctx* c, int32_t l) {
+    return (c && l >= 0 && l <= c->L) ? 3 * c->H[l].nfree + c->H[l].N : -1;
+}
+int64_t hhg_num_interface(const hhg_ctx* c, int32_t l) {
+    return (c && l >= 0 && l <= c->L) ? c->H[l].nif : -1;
+}
+
+hhg_status hhg_node_info(const hhg_ctx* c, int32_t l, int32_t* ijk, int8_t* dir) {
+    if (!c || l < 0 || l > c->L) return fail(nullptr, HHG_EINVAL, "bad context or level");
+    const HostLevel& h = c->H[l];
+    for (int64_t v = 0; v < h.N; ++v) {
+        if (ijk) {
+            ijk[3 * v + 0] = (int32_t)(v % h.lat[0]);
+            ijk[3 * v + 1] = (int32_t)((v / h.lat[0]) % h.lat[1]);
+            ijk[3 * v + 2] = (int32_t)(v / ((int64_t)h.lat[0] * h.lat[1]));
+        }
+        if (dir) dir[v] = h.node_dir[v];
+    }
+    return HHG_OK;
+}
+
+hhg_status hhg_mass_weights(const hhg_ctx* c, int32_t l, double* m) {
+    if (!c || l < 0 || l > c->L || !m) return fail(nullptr, HHG_EINVAL, "bad context, level or array");
+    const HostLevel& h = c->H[l];
+    for (int64_t v = 0; v < h.N; ++v) {
+        const int sid = h.node_sid[v];
+        const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
+                                    : &h.st[(size_t)sid * ST_SIZE];
+        m[v] = rec[ST_MASS];
+    }
+    return HHG_OK;
+}
+
+#define CHECK_DEV(c)                                                                     \
+    do {                                                                                 \
+        if (!(c)) return fail(nullptr, HHG_EINVAL, "context is NULL");                   \
+        if (!(c)->device) return fail(c, HHG_EINVAL, "host-only context (no workspace)"); \
+    } while (0)
+#define CHECK_LEVEL(c, l) \
+    if ((l) < 0 || (l) > (c)->L) return fail(c, HHG_EINVAL, "level out of range")
+#define CHECK_PTR(c, p) \
+    if (!(p)) return fail(c, HHG_EINVAL, #p " is NULL")
+#define LAUNCH_CHECK(c)                                                              \
+    do {                                                                             \
+        hipError_t e_ = hipGetLastError();                                           \
+        if (e_ != hipSuccess) return fail(c, HHG_EDEVICE, hipGetErrorString(e_));    \
+    } while (0)
+
+hhg_status hhg_scatter(hhg_ctx* c, int32_t l, const double* nodal, int32_t nf, void* x,
+                       hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, nodal);
+    CHECK_PTR(c, x);
+    if (nf < 1 || nf > 4) return fail(c, HHG_EINVAL, "nfields must be 1..4");
+    const HostLevel& h = c->H[l];
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(h.len)), dim3(TPB), 0, (hipStream_t)stream,
+                       c->A[l].slot_node, (size_t)h.len, nf, nodal, (size_t)h.N, (double*)x);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_gather(hhg_ctx* c, int32_t l, const void* x, int32_t nf, double* nodal,
+                      hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, nodal);
+    CHECK_PTR(c, x);
+    if (nf < 1 || nf > 4) return fail(c, HHG_EINVAL, "nfields must be 1..4");
+    const HostLevel& h = c->H[l];
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(h.N)), dim3(TPB), 0, (hipStream_t)stream,
+                       c->A[l].node_slot, (size_t)h.N, nf, (const double*)x, (size_t)h.len, nodal);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_exchange(hhg_ctx* c, int32_t l, void* x, int32_t nf, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    if (nf < 1 || nf > 4) return fail(c, HHG_EINVAL, "nfields must be 1..4");
+    const HostLevel& h = c->H[l];
+    if (h.nif > 0)
+        hipLaunchKernelGGL(k_exchange<double>, dim3((h.nif + TPB - 1) / TPB), dim3(TPB), 0,
+                           (hipStream_t)stream, c->D64[l], nf, (double*)x);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_rhs(hhg_ctx* c, const void* f, void* rhs, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, f);
+    CHECK_PTR(c, rhs);
+    if (f == rhs) return fail(c, HHG_EINVAL, "f and rhs must not alias");
+    full_pass<double, MODE_RHS>(c, c->L, (const double*)f, nullptr, (double*)rhs,
+                                (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_apply(hhg_ctx* c, int32_t l, const void* x, void* y, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, y);
+    if (x == y) return fail(c, HHG_EINVAL, "x and y must not alias");
+    full_pass<double, MODE_APPLY>(c, l, (const double*)x, nullptr, (double*)y, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_residual(hhg_ctx* c, int32_t l, const void* x, const void* b, void* r,
+                        double* h_norm, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, b);
+    CHECK_PTR(c, r);
+    if (r == x || r == b) return fail(c, HHG_EINVAL, "r must not alias x or b");
+    hipStream_t s = (hipStream_t)stream;
+    residual_norm<double>(c, l, (const double*)x, (const double*)b, (double*)r, c->scal, s);
+    LAUNCH_CHECK(c);
+    if (h_norm) {
+        HIPCHECK(c, hipMemcpyAsync(h_norm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
+    return HHG_OK;
+}
+
+hhg_status hhg_smooth(hhg_ctx* c, int32_t l, void* x, const void* b, int32_t steps,
+                      hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, b);
+    if (steps < 0 || steps > 1000) return fail(c, HHG_EINVAL, "steps must be 0..1000");
+    for (int q = 0; q < steps; ++q)
+        uzawa_step<double>(c, l, (double*)x, (const double*)b, c->A[l].t64, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_restrict(hhg_ctx* c, int32_t l, const void* rf, void* bc, hhg_stream stream) {
+    CHECK_DEV(c);
+    if (l < 1 || l > c->L) return fail(c, HHG_EINVAL, "level must be 1..L");
+    CHECK_PTR(c, rf);
+    CHECK_PTR(c, bc);
+    restrict_to<double>(c, l, (const double*)rf, (double*)bc, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_prolong_add(hhg_ctx* c, int32_t l, const void* ec, void* xf, hhg_stream stream) {
+    CHECK_DEV(c);
+    if (l < 1 || l > c->L) return fail(c, HHG_EINVAL, "level must be 1..L");
+    CHECK_PTR(c, ec);
+    CHECK_PTR(c, xf);
+    prolong_add<double>(c, l, (const double*)ec, (double*)xf, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_coarse_solve(hhg_ctx* c, const void* b0, void* x0, int32_t* iters, double* relres,
+                            hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, b0);
+    CHECK_PTR(c, x0);
+    if (b0 == x0) return fail(c, HHG_EINVAL, "b0 and x0 must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    coarse_solve<double>(c, (const double*)b0, (double*)x0, s);
+    LAUNCH_CHECK(c);
+    if (iters || relres) {
+        double st[2];
+        HIPCHECK(c, hipMemcpyAsync(st, c->scal + 8, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+        if (iters) *iters = (int32_t)st[0];
+        if (relres) *relres = st[1];
+    }
+    return HHG_OK;
+}
+
+hhg_status hhg_project(hhg_ctx* c, int32_t l, void* x, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    project<double>(c, l, (double*)x, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// one solver iteration on the finest level; on entry of the mixed variant
+// r64_L must hold b - K x and scal[0] its norm
+void cycle_fp64(hhg_ctx* c, double* x, const double* b, hipStream_t s) {
+    vcycle<double>(c, c->L, x, b, s);
+    project<double>(c, c->L, x, s);
+}
+
+void cycle_mixed(hhg_ctx* c, double* x, hipStream_t s) {
+    const int L = c->L;
+    DevLevelArrays& a = c->A[L];
+    const size_t n4 = 4 * (size_t)c->H[L].len;
+    hipLaunchKernelGGL(k_scale_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, a.r64, c->scal,
+                       a.b32, n4);
+    fill<float>(a.x32, n4, 0.0f, s);
+    vcycle<float>(c, L, a.x32, a.b32, s);
+    hipLaunchKernelGGL(k_axpy_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, c->scal, a.x32,
+                       n4);
+    project<double>(c, L, x, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+hhg_status hhg_vcycle(hhg_ctx* c, void* x, const void* b, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, b);
+    if (x == b) return fail(c, HHG_EINVAL, "x and b must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->opts.precision == 1) {
+        residual_norm<double>(c, c->L, (const double*)x, (const double*)b, c->A[c->L].r64, c->scal, s);
+        cycle_mixed(c, (double*)x, s);
+    } else {
+        cycle_fp64(c, (double*)x, (const double*)b, s);
+    }
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t max_cycles,
+                     hhg_solve_info* info, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, xv);
+    CHECK_PTR(c, bv);
+    if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");
+    if (!(rtol > 0.0) || max_cycles < 0 || max_cycles > 255)
+        return fail(c, HHG_EINVAL, "need rtol > 0 and 0 <= max_cycles <= 255");
+    hipStream_t s = (hipStream_t)stream;
+    double* x = (double*)xv;
+    const double* b = (const double*)bv;
+    hhg_solve_info loc;
+    hhg_solve_info* I = info ? info : &loc;
+    std::memset(I, 0, sizeof(*I));
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    double* r = c->A[c->L].r64;
+    residual_norm<double>(c, c->L, x, b, r, c->scal, s);
+    double nrm;
+    HIPCHECK(c, hipMemcpyAsync(&nrm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(c, hipStreamSynchronize(s));
+    I->r0 = nrm;
+    I->res_hist[0] = nrm;
+    I->r_final = nrm;
+    I->rel_res = nrm > 0 ? 1.0 : 0.0;
+    if (!std::isfinite(nrm)) {
+        I->status = HHG_ENAN;
+        return fail(c, HHG_ENAN, "initial residual is not finite");
+    }
+    if (nrm == 0.0) {
+        I->status = HHG_OK;
+        return HHG_OK;
+    }
+    const double r0 = nrm;
+    double prev = nrm;
+    int stagn = 0;
+    hhg_status st = HHG_ENOCONV;
+    if (e0) (void)hipEventRecord(e0, s);
+    int k = 0;
+    for (k = 1; k <= max_cycles; ++k) {
+        if (c->opts.precision == 1)
+            cycle_mixed(c, x, s);
+        else
+            cycle_fp64(c, x, b, s);
+        residual_norm<double>(c, c->L, x, b, r, c->scal, s);
+        HIPCHECK(c, hipMemcpyAsync(&nrm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+        I->res_hist[k] = nrm;
+        I->cycles = k;
+        I->r_final = nrm;
+        I->rel_res = nrm / r0;
+        if (!std::isfinite(nrm)) {
+            st = HHG_ENAN;
+            break;
+        }
+        const double rho = nrm / prev;
+        I->rho_max = std::max(I->rho_max, rho);
+        prev = nrm;
+        if (nrm <= rtol * r0) {
+            st = HHG_OK;
+            break;
+        }
+        if (nrm > 1e3 * r0) break;               // divergence
+        stagn = rho > 0.99 ? stagn + 1 : 0;      // stagnation
+        if (stagn >= 5) break;
+    }
+    if (e1) (void)hipEventRecord(e1, s);
+    if (e0 && e1) {
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        I->t_solve_ms = ms;
+    }
+    if (I->cycles > 0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    I->status = st;
+    c->evused = c->timing ? c->evused : 0;
+    LAUNCH_CHECK(c);
+    if (st == HHG_ENAN) return fail(c, HHG_ENAN, "residual norm is not finite");
+    if (st == HHG_ENOCONV) return fail(c, HHG_ENOCONV, "tolerance not reached");
+    return HHG_OK;
+}
+
+hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, double* dnu,
+                    void* df, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, lam);
+    CHECK_PTR(c, dnu);
+    hipStream_t s = (hipStream_t)stream;
+    LevelDev<double>& v = c->D64[c->L];
+    hipLaunchKernelGGL(k_grad_nu, dim3(v.n_ctiles), dim3(TPB), 0, s, v, (const double*)x,
+                       (const double*)lam, (const double*)f, c->gpart);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(v.nm), dim3(TPB), 0, s, c->A[c->L].ctiles, v.n_ctiles,
+                       c->gpart, dnu);
+    if (df) {
+        if (df == lam) return fail(c, HHG_EINVAL, "dJ_df must not alias lambda");
+        full_pass<double, MODE_GRADF>(c, c->L, (const double*)lam, nullptr, (double*)df, s);
+    }
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
+    if (!c) return fail(nullptr, HHG_EINVAL, "context is NULL");
+    CHECK_PTR(c, nu);
+    for (size_t m = 0; m < c->mi.macros.size(); ++m)
+        if (!std::isfinite(nu[m]) || nu[m] <= 0.0)
+            return fail(c, HHG_EINVAL, "viscosity must be finite and positive");
+    for (size_t m = 0; m < c->mi.macros.size(); ++m) c->mi.macros[m].nu = nu[m];
+    std::string err;
+    for (int l = 0; l <= c->L; ++l)
+        if (!compute_stencils(c->mi, &c->H[l], &err)) return fail(c, HHG_EINVAL, err);
+    if (!build_coarse(c->mi, c->H[0], &c->CH, &err)) return fail(c, HHG_EINVAL, err);
+    if (!c->device) return HHG_OK;
+    hhg_status st = upload_stencils(c);
+    if (st != HHG_OK) return st;
+    HIPCHECK(c, hipDeviceSynchronize());
+    return HHG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// lattice index of macro-local vertex (i, j, k) of macro m at level h
+int64_t lattice_of(const hhg_ctx* c, const HostLevel& h, int m, int i, int j, int k) {
+    const MacroInfo& M = c->mi.macros[m];
+    int X[3] = {M.o[0] * h.n, M.o[1] * h.n, M.o[2] * h.n};
+    X[M.ax[0]] += i + j + k;
+    X[M.ax[1]] += j + k;
+    X[M.ax[2]] += k;
+    return X[0] + (int64_t)h.lat[0] * (X[1] + (int64_t)h.lat[1] * X[2]);
+}
+
+const int CK_LOFF[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0},
+                            {0, 1, 0},  {0, -1, 0}, {0, -1, 1}, {0, 1, -1}, {-1, 0, 1},
+                            {1, 0, -1}, {0, 0, 1},  {0, 0, -1}, {1, -1, 1}, {-1, 1, -1}};
+const int CK_GDIR[15][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {0, 1, 1},
+                            {0, -1, -1}, {1, 0, 1},  {-1, 0, -1}, {1, 1, 1},  {-1, -1, -1}};
+
+#define CK(cond, msg)                                                                  \
+    do {                                                                               \
+        if (!(cond)) {                                                                 \
+            *err = std::string("layout check, level ") + std::to_string(l) + ": " + msg; \
+            return false;                                                              \
+        }                                                                              \
+    } while (0)
+
+bool check_level(const hhg_ctx* c, int l, std::string* err) {
+    const HostLevel& h = c->H[l];
+    const int n = h.n;
+    const int* sb = h.slab_base.data();
+    auto slot_ok = [&](int s, int m) {
+        return s >= (int64_t)m * h.mstride && s < (int64_t)(m + 1) * h.mstride && s < h.len;
+    };
+    // interior tiles: every interior vertex exactly once, all 15 taps exact
+    std::vector<uint8_t> seen(h.len, 0);
+    for (const Tile& t : h.vtiles) {
+        if (t.macro < 0) continue;
+        const int m = t.macro, k = t.k, mm = n - k;
+        CK(k >= 1 && k <= n - 1, "interior tile outside slabs 1..n-1");
+        for (int lane = 0; lane < TPB; ++lane) {
+            LanePos P = decode_lane(t, n, 1, mm - 2, lane);
+            if (!P.ok) continue;
+            const int j = P.j;
+            CK(j >= 1 && j <= mm - 2 && P.q < ((mm + 4 - j) >> 2), "lane decoded outside its slab");
+            Rows R;
+            make_rows(sb, n, (int)(m * h.mstride), j, k, R);
+            for (int cc = 0; cc < 4; ++cc) {
+                const int i = 4 * P.q + ((cc + 2 * j + k) & 3);
+                if (i < 1 || i > mm - 1 - j) continue;
+                int64_t lat = lattice_of(c, h, m, i, j, k);
+                int X = (int)(lat % h.lat[0]), Y = (int)((lat / h.lat[0]) % h.lat[1]),
+                    Z = (int)(lat / ((int64_t)h.lat[0] * h.lat[1]));
+                CK(((X + Y + Z) & 3) == cc, "colour sweep picks a vertex of another colour");
+            }
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * P.q + r;
+                if (i < 1 || i > mm - 1 - j) continue;
+                int s[15], a[7];
+                nbr_slots(R, i, s);
+                axis_slots(R, i, a);
+                const int ax[7] = {0, 1, 2, 3, 4, 7, 8};
+                for (int q = 0; q < 7; ++q) CK(a[q] == s[ax[q]], "axis taps differ from full taps");
+                for (int q = 0; q < 15; ++q) {
+                    CK(slot_ok(s[q], m), "tap slot outside the macro");
+                    CK(h.slot_node[s[q]] ==
+                           lattice_of(c, h, m, i + CK_LOFF[q][0], j + CK_LOFF[q][1], k + CK_LOFF[q][2]),
+                       "tap slot holds the wrong vertex");
+                }
+                CK(seen[s[0]] == 0, "interior vertex visited twice");
+                seen[s[0]] = 1;
+            }
+        }
+    }
+    for (int m = 0; m < h.nm; ++m)
+        for (int k = 1; k < n; ++k)
+            for (int j = 1; j <= n - k - 2; ++j)
+                for (int i = 1; i <= n - k - 1 - j; ++i)
+                    CK(seen[local_slot(h, m, i, j, k)] == 1, "interior vertex not covered");
+    // closure tiles: every closure vertex exactly once; grad taps; prolongation
+    std::fill(seen.begin(), seen.end(), 0);
+    for (const Tile& t : h.ctiles) {
+        if (t.macro < 0) continue;
+        const int m = t.macro, k = t.k, mm = n - k;
+        for (int lane = 0; lane < TPB; ++lane) {
+            LanePos P = decode_lane(t, n, 0, mm, lane);
+            if (!P.ok) continue;
+            const int j = P.j;
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * P.q + r;
+                if (i > mm - j) continue;
+                const int sf = slot_of(sb, n, (int)(m * h.mstride), i, j, k);
+                CK(sf == local_slot(h, m, i, j, k), "closure slot mismatch");
+                CK(seen[sf] == 0, "closure vertex visited twice");
+                seen[sf] = 1;
+                for (int q = 0; q < 15; ++q) {
+                    const int ii = i + CK_LOFF[q][0], jj = j + CK_LOFF[q][1], kk = k + CK_LOFF[q][2];
+                    const int sq = slot_checked(sb, n, (int)(m * h.mstride), ii, jj, kk);
+                    const bool inside = ii >= 0 && jj >= 0 && kk >= 0 && ii + jj + kk <= n;
+                    CK((sq >= 0) == inside, "closure tap validity");
+                    if (inside)
+                        CK(slot_ok(sq, m) && h.slot_node[sq] == lattice_of(c, h, m, ii, jj, kk),
+                           "closure tap holds the wrong vertex");
+                }
+                if (l == 0) continue;
+                const HostLevel& hc = c->H[l - 1];
+                const int mbc = (int)(m * hc.mstride);
+                const int pi = i & 1, pj = j & 1, pk = k & 1;
+                if ((pi | pj | pk) == 0) {
+                    const int sc = slot_of(hc.slab_base.data(), hc.n, mbc, i >> 1, j >> 1, k >> 1);
+                    CK(hc.slot_node[sc] == lattice_of(c, hc, m, i >> 1, j >> 1, k >> 1),
+                       "prolongation source");
+                } else {
+                    int di, dj, dk;
+                    parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        const int I = i + sg * di, J = j + sg * dj, K = k + sg * dk;
+                        CK((I % 2 == 0) && (J % 2 == 0) && (K % 2 == 0) && I >= 0 && J >= 0 &&
+                               K >= 0 && I + J + K <= n,
+                           "prolongation endpoint not a coarse closure vertex");
+                        const int sc = slot_of(hc.slab_base.data(), hc.n, mbc, I >> 1, J >> 1, K >> 1);
+                        CK(sc >= 0 && sc < hc.len &&
+                               hc.slot_node[sc] == lattice_of(c, hc, m, I >> 1, J >> 1, K >> 1),
+                           "prolongation endpoint slot");
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t s = 0; s < h.len; ++s)
+        CK((h.slot_node[s] >= 0) == (seen[s] == 1), "closure tiles and slot map disagree");
+    // interface vertices
+    for (int cc = 0; cc < 4; ++cc) {
+        CK(h.col_start[cc] <= h.vel_end[cc] && h.vel_end[cc] <= h.col_start[cc + 1], "colour ranges");
+        for (int t = h.col_start[cc]; t < h.col_start[cc + 1]; ++t) {
+            int64_t lat = h.if_lat[t];
+            int X = (int)(lat % h.lat[0]), Y = (int)((lat / h.lat[0]) % h.lat[1]),
+                Z = (int)(lat / ((int64_t)h.lat[0] * h.lat[1]));
+            CK(((X + Y + Z) & 3) == cc, "interface colour");
+            CK((h.if_flag[t] & 1) == (t >= h.vel_end[cc] ? 1 : 0), "interface Dirichlet order");
+            CK(h.slot_node[h.if_self[t]] == lat, "interface self slot");
+            for (int q = h.if_cptr[t]; q < h.if_cptr[t + 1]; ++q)
+                CK(h.if_copy[q] >= 0 && h.if_copy[q] < h.len && h.slot_node[h.if_copy[q]] == lat,
+                   "interface copy slot");
+            const double* rec = &h.st[(size_t)h.if_sid[t] * ST_SIZE];
+            for (int g = 1; g < 15; ++g) {
+                const int sn = h.if_nb[(size_t)(g - 1) * h.nif + t];
+                CK(sn >= 0 && sn < h.len, "interface neighbour slot out of range");
+                if (sn == h.if_self[t]) {
+                    const int blocks[9] = {ST_A, ST_C, ST_M, ST_B, ST_B + 15, ST_B + 30,
+                                           ST_BT, ST_BT + 15, ST_BT + 30};
+                    for (int bq : blocks) CK(rec[bq + g] == 0.0, "absent neighbour with a coefficient");
+                } else {
+                    int64_t want = (X + CK_GDIR[g][0]) +
+                                   (int64_t)h.lat[0] * ((Y + CK_GDIR[g][1]) +
+                                                        (int64_t)h.lat[1] * (Z + CK_GDIR[g][2]));
+                    CK(h.slot_node[sn] == want, "interface neighbour holds the wrong vertex");
+                }
+            }
+            if (l < c->L) {
+                const HostLevel& hf = c->H[l + 1];
+                const int tf = h.rif_fine[t];
+                CK(tf >= 0 && tf < hf.nif, "restriction map out of range");
+                int64_t lf = 2 * X + (int64_t)hf.lat[0] * (2 * Y + (int64_t)hf.lat[1] * 2 * Z);
+                CK(hf.if_lat[tf] == lf, "restriction map vertex");
+            }
+        }
+    }
+    CK(h.col_start[4] == h.nif, "colour ranges do not cover the interface list");
+    // restriction of interior coarse vertices: fine taps around (2i, 2j, 2k)
+    if (l < c->L) {
+        const HostLevel& hf = c->H[l + 1];
+        for (const Tile& t : h.vtiles) {
+            if (t.macro < 0) continue;
+            const int m = t.macro, k = t.k, mm = n - k;
+            for (int lane = 0; lane < TPB; ++lane) {
+                LanePos P = decode_lane(t, n, 1, mm - 2, lane);
+                if (!P.ok) continue;
+                Rows RF;
+                make_rows(hf.slab_base.data(), hf.n, (int)(m * hf.mstride), 2 * P.j, 2 * k, RF);
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * P.q + r;
+                    if (i < 1 || i > mm - 1 - P.j) continue;
+                    int s[15];
+                    nbr_slots(RF, 2 * i, s);
+                    for (int q = 0; q < 15; ++q)
+                        CK(s[q] >= 0 && s[q] < hf.len &&
+                               hf.slot_node[s[q]] == lattice_of(c, hf, m, 2 * i + CK_LOFF[q][0],
+                                                                2 * P.j + CK_LOFF[q][1],
+                                                                2 * k + CK_LOFF[q][2]),
+                           "restriction tap");
+                }
+            }
+        }
+    }
+    // grids fit the reduction buffers
+    CK((int)h.vtiles.size() + (h.nif + TPB - 1) / TPB <= c->npartials, "partials too small");
+    CK((int)h.ctiles.size() <= c->npartials, "gradient partials too small");
+    return true;
+}
+#undef CK
+
+}  // namespace
+
+extern "C" hhg_status hhg_check_layout(const hhg_ctx* c) {
+    if (!c) return fail(nullptr, HHG_EINVAL, "context is NULL");
+    std::string err;
+    for (int l = 0; l <= c->L; ++l)
+        if (!check_level(c, l, &err)) return fail(const_cast<hhg_ctx*>(c), HHG_EINVAL, err);
+    return HHG_OK;
+}
+
+extern "C" {
+
+hhg_status hhg_set_timing(hhg_ctx* c, int32_t on) {
+    CHECK_DEV(c);
+    c->timing = on != 0;
+    for (int q = 0; q < HHG_K_NCLASS; ++q) {
+        c->tpairs[q].clear();
+        c->tbytes[q] = 0.0;
+    }
+    c->evused = 0;
+    return HHG_OK;
+}
+
+hhg_status hhg_kernel_time(hhg_ctx* c, int32_t cls, int64_t* launches, double* ms, double* bytes) {
+    CHECK_DEV(c);
+    if (cls < 0 || cls >= HHG_K_NCLASS) return fail(c, HHG_EINVAL, "kernel class out of range");
+    double tot = 0.0;
+    for (const TimerPair& p : c->tpairs[cls]) {
+        HIPCHECK(c, hipEventSynchronize(p.b));
+        float t = 0.f;
+        HIPCHECK(c, hipEventElapsedTime(&t, p.a, p.b));
+        tot += t;
+    }
+    if (launches) *launches = (int64_t)c->tpairs[cls].size();
+    if (ms) *ms = tot;
+    if (bytes) *bytes = c->tbytes[cls];
+    return HHG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Host-side construction of the refined hierarchy: mesh validation, per-macro
+// layout, interface vertices (face / edge / corner primitives) with their
+// neighbour tables and stencils, workgroup tile tables and the level-0
+// system.  Pure C++; the device upload lives in hhg.hip.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hhg.h"
+#include "hhg_internal.hpp"
+
+namespace hhg {
+
+struct MacroInfo {
+    int o[3];        // origin (integer macro coordinates of vertex 0)
+    int ax[3];       // Kuhn path axes a, b, c
+    double nu;
+    int8_t bc[4];    // tag of the face opposite vertex f
+};
+
+struct MeshInfo {
+    std::vector<MacroInfo> macros;
+    int ext[3];      // bounding box extents (macro units), origin at 0
+    bool project;    // pressure has a null space (no natural face)
+};
+
+bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err);
+
+// (macro, zero-pattern of the barycentric coordinates) of every macro closure
+// that contains a vertex; vertices with equal keys have equal stencils and
+// equal neighbour routing.
+using Key = std::vector<std::pair<int32_t, int32_t>>;
+
+struct HostLevel {
+    int R = 0, n = 0, nm = 0;
+    int64_t mstride = 0, len = 0;
+    int lat[3] = {0, 0, 0};
+    int64_t N = 0;
+    std::vector<int32_t> slab_base;
+    std::vector<Tile> vtiles, ctiles;
+    // interface vertices, sorted by (colour, Dirichlet flag, primary slot)
+    int32_t nif = 0;
+    std::vector<int32_t> if_self, if_nb, if_sid, if_cptr, if_copy, if_flag;
+    std::vector<int64_t> if_lat;
+    int32_t col_start[5] = {0, 0, 0, 0, 0};
+    int32_t vel_end[4] = {0, 0, 0, 0};
+    std::vector<Key> keys;                 // interface stencil id - nm -> key
+    std::vector<double> st;                // (nm + keys) * ST_SIZE
+    std::vector<double> st_vol_global;     // nm * ST_SIZE, volume stencils in global order
+    std::vector<double> gst;               // nm * 16 * GR_SIZE
+    std::vector<int32_t> slot_node;        // [len] lattice node or -1 (padding)
+    std::vector<int32_t> node_slot;        // [N] primary slot
+    std::vector<int32_t> node_sid;         // [N] stencil id (interface) or -(m+1) (volume of m)
+    std::vector<int8_t> node_dir;          // [N] velocity Dirichlet
+    std::vector<int32_t> rif_fine;         // [nif] index in the finer level's interface list
+    int64_t nfree = 0;                     // free velocity vertices
+};
+
+// Slot of macro-local vertex (i, j, k): tetrahedral slabs k, rows j, each row
+// split into 4 sub-rows by i mod 4 (row length m+1-j padded to a multiple of 4).
+inline int32_t R4(int32_t L) {
+    int32_t a = L >> 2, b = L & 3;
+    return 4 * (a + 1) * (2 * a + b);
+}
+inline int64_t local_slot(const HostLevel& L, int m, int i, int j, int k) {
+    int mm = L.n - k;
+    int32_t Q = (mm + 4 - j) >> 2;
+    return (int64_t)m * L.mstride + L.slab_base[k] + R4(mm + 1) - R4(mm + 1 - j) + (i & 3) * Q +
+           (i >> 2);
+}
+
+bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std::string* err);
+bool compute_stencils(const MeshInfo& mi, HostLevel* L, std::string* err);
+void link_levels(HostLevel* coarse, const HostLevel& fine);
+
+// Level-0 system in compact numbering: free velocity vertices x 3, then the
+// pressure of every vertex.
+struct CoarseHost {
+    int32_t nfv = 0, N = 0, nd = 0;
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> val;
+    std::vector<double> ainv;       // [nfv][nfv] inverse of the free-free A block
+    std::vector<double> pdinv;      // [N] 1 / (sum |T|/4/nu_T)
+    std::vector<double> mass;       // [N] int phi_i
+    std::vector<int32_t> vel_node;  // [nfv] lattice node of compact velocity vertex
+    std::vector<int32_t> node_slot; // [N]
+    std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
+};
+bool build_coarse(const MeshInfo& mi, const HostLevel& L0, CoarseHost* out, std::string* err);
+
+}  // namespace hhg

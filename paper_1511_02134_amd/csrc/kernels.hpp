@@ -1,0 +1,861 @@
+// Device kernels of the Uzawa multigrid (gfx950).  Included once, by hhg.hip.
+//
+// Work decomposition.  Every level is processed by two kinds of workgroups in
+// the same launch:
+//  * volume tiles: 256 lanes over the rows of one slab k of one macro.  Rows
+//    j and jh-j of the slab are folded into one row of constant width W so
+//    that the triangular slab fills whole wavefronts; a lane owns one quad
+//    (4 consecutive i of a row).  Every sub-row (i mod 4) is contiguous, so
+//    a colour sweep (one node per quad) and every neighbour access of a wave
+//    is a unit-stride load.
+//  * interface blocks: 256 vertices of the interface list (vertices on macro
+//    faces, edges and corners), addressed through their neighbour table; the
+//    new value is written into every macro copy of the vertex, which is the
+//    ghost exchange (Section 3.4) fused into the update.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hhg_internal.hpp"
+
+namespace hhg {
+
+constexpr int TPB = 256;
+
+__host__ __device__ __forceinline__ int R4d(int L) {
+    int a = L >> 2, b = L & 3;
+    return 4 * (a + 1) * (2 * a + b);
+}
+__host__ __device__ __forceinline__ int at(int base, int Q, int i) { return base + (i & 3) * Q + (i >> 2); }
+
+// Row bases and sub-row lengths around row (j, k) of a macro:
+// 0:(j,k) 1:(j+1,k) 2:(j-1,k) 3:(j-1,k+1) 4:(j+1,k-1) 5:(j,k+1) 6:(j,k-1)
+struct Rows {
+    int b[7];
+    int Q[7];
+};
+
+__host__ __device__ __forceinline__ void make_rows(const int* __restrict__ sb, int n, int mb, int j, int k,
+                                          Rows& R) {
+    const int mm = n - k;
+    R.Q[0] = (mm + 4 - j) >> 2;
+    R.b[0] = mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j);
+    R.Q[1] = (mm + 3 - j) >> 2;
+    R.b[1] = R.b[0] + 4 * R.Q[0];
+    R.Q[2] = (mm + 5 - j) >> 2;
+    R.b[2] = R.b[0] - 4 * R.Q[2];
+    R.Q[5] = (mm + 3 - j) >> 2;
+    R.b[5] = mb + sb[k + 1] + R4d(mm) - R4d(mm - j);
+    R.Q[3] = (mm + 4 - j) >> 2;
+    R.b[3] = R.b[5] - 4 * R.Q[3];
+    R.Q[6] = (mm + 5 - j) >> 2;
+    R.b[6] = mb + sb[k - 1] + R4d(mm + 2) - R4d(mm + 2 - j);
+    R.Q[4] = (mm + 4 - j) >> 2;
+    R.b[4] = R.b[6] + 4 * R.Q[6];
+}
+
+// slots of the centre and the 14 neighbours in macro-local offset order
+__host__ __device__ __forceinline__ void nbr_slots(const Rows& R, int i, int s[15]) {
+    s[0] = at(R.b[0], R.Q[0], i);
+    s[1] = at(R.b[0], R.Q[0], i + 1);
+    s[2] = at(R.b[0], R.Q[0], i - 1);
+    s[3] = at(R.b[1], R.Q[1], i - 1);
+    s[4] = at(R.b[2], R.Q[2], i + 1);
+    s[5] = at(R.b[1], R.Q[1], i);
+    s[6] = at(R.b[2], R.Q[2], i);
+    s[7] = at(R.b[3], R.Q[3], i);
+    s[8] = at(R.b[4], R.Q[4], i);
+    s[9] = at(R.b[5], R.Q[5], i - 1);
+    s[10] = at(R.b[6], R.Q[6], i + 1);
+    s[11] = at(R.b[5], R.Q[5], i);
+    s[12] = at(R.b[6], R.Q[6], i);
+    s[13] = at(R.b[3], R.Q[3], i + 1);
+    s[14] = at(R.b[4], R.Q[4], i - 1);
+}
+
+// the 7 taps of A and C (centre, +-e_a, +-e_b, +-e_c) in local order
+__host__ __device__ __forceinline__ void axis_slots(const Rows& R, int i, int s[7]) {
+    s[0] = at(R.b[0], R.Q[0], i);
+    s[1] = at(R.b[0], R.Q[0], i + 1);
+    s[2] = at(R.b[0], R.Q[0], i - 1);
+    s[3] = at(R.b[1], R.Q[1], i - 1);
+    s[4] = at(R.b[2], R.Q[2], i + 1);
+    s[5] = at(R.b[3], R.Q[3], i);
+    s[6] = at(R.b[4], R.Q[4], i);
+}
+
+// Lane -> (row j, quad q) of a folded slab; rows jl..jh are paired (jl+p, jh-p).
+struct LanePos {
+    int j, q;
+    bool ok;
+};
+__host__ __device__ __forceinline__ LanePos decode_lane(const Tile& T, int n, int jl, int jh, int lane) {
+    LanePos P{0, 0, false};
+    const int mm = n - T.k;
+    const int t = T.t0 + lane;
+    const int p = (int)(((float)t + 0.5f) * (1.0f / (float)T.W));
+    const int q = t - p * T.W;
+    const int npairs = (jh - jl + 2) >> 1;
+    if (p >= npairs) return P;
+    const int ja = jl + p, jb = jh - p;
+    const int Qa = (mm + 4 - ja) >> 2;
+    if (q < Qa) {
+        P.j = ja;
+        P.q = q;
+        P.ok = true;
+    } else if (jb > ja) {
+        const int q2 = q - Qa;
+        if (q2 < ((mm + 4 - jb) >> 2)) {
+            P.j = jb;
+            P.q = q2;
+            P.ok = true;
+        }
+    }
+    return P;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+// sum over a 256-thread block, result valid in thread 0
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Colour sweeps (Section 3.5): one launch updates every vertex of colour c.
+// Velocity: u_k = (ru_k - sum_{y != x} A_xy u_k(y)) / A_xx, ru = f - B^T p
+// precomputed with the pressure frozen; three components at once.
+// Pressure: p += omega (bp - (C p)_x) / C_xx with bp = B u - g.
+// ---------------------------------------------------------------------------
+template <typename T, bool VEL>
+__global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
+                                                const T* __restrict__ rhs, T omega) {
+    const size_t len = (size_t)L.len;
+    if ((int)blockIdx.x < L.n_vtiles) {
+        const Tile tl = L.vtiles[blockIdx.x];
+        if (tl.macro < 0) return;
+        const int n = L.n, k = tl.k, mm = n - k;
+        const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+        if (!P.ok) return;
+        const int j = P.j;
+        const int i = 4 * P.q + ((c + 2 * j + k) & 3);
+        if (i < 1 || i > mm - 1 - j) return;
+        Rows R;
+        make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+        int s[7];
+        axis_slots(R, i, s);
+        const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+        if (VEL) {
+            const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
+                    a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                T* u = x + f * len;
+                T v = rhs[f * len + s[0]] -
+                      (a1 * u[s[1]] + a2 * u[s[2]] + a3 * u[s[3]] + a4 * u[s[4]] + a7 * u[s[5]] +
+                       a8 * u[s[6]]);
+                u[s[0]] = v * ia;
+            }
+        } else {
+            T* p = x + 3 * len;
+            const T cp = st[ST_C + 0] * p[s[0]] + st[ST_C + 1] * p[s[1]] + st[ST_C + 2] * p[s[2]] +
+                         st[ST_C + 3] * p[s[3]] + st[ST_C + 4] * p[s[4]] + st[ST_C + 7] * p[s[5]] +
+                         st[ST_C + 8] * p[s[6]];
+            p[s[0]] += omega * (rhs[3 * len + s[0]] - cp) * st[ST_INVC];
+        }
+        return;
+    }
+    const int t0 = L.col_start[c];
+    const int t = t0 + ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+    const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
+    if (t >= tend) return;
+    const int nif = L.nif;
+    const int self = L.if_self[t];
+    const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+    int nb[6];
+#pragma unroll
+    for (int g = 0; g < 6; ++g) nb[g] = L.if_nb[g * nif + t];
+    const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+    if (VEL) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T* u = x + f * len;
+            T acc = T(0);
+#pragma unroll
+            for (int g = 0; g < 6; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
+            const T v = (rhs[f * len + self] - acc) * st[ST_INVA];
+            for (int q = c0; q < c1; ++q) u[L.if_copy[q]] = v;
+        }
+    } else {
+        T* p = x + 3 * len;
+        T cp = st[ST_C] * p[self];
+#pragma unroll
+        for (int g = 0; g < 6; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
+        const T v = p[self] + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
+        for (int q = c0; q < c1; ++q) p[L.if_copy[q]] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Full passes over every vertex (volume interior + interface), one template
+// for the operators that read all 15 taps:
+//   MODE_APPLY   y = K x                         (Dirichlet velocity rows 0)
+//   MODE_RES     r = b - K x, sum r^2 into per-block partials
+//   MODE_RU      t_k = b_k - (B^T p)_k  (k = 0..2; Dirichlet rows 0)
+//   MODE_BP      t_3 = (B u) - b_3
+//   MODE_RHS     y = (M f on free rows, sum_k G_k f_k)    (in: f in fields 0..2)
+//   MODE_GRADF   y_k = M lam_k + GT_k lam_p                (in: lambda)
+// ---------------------------------------------------------------------------
+enum { MODE_APPLY = 0, MODE_RES = 1, MODE_RU = 2, MODE_BP = 3, MODE_RHS = 4, MODE_GRADF = 5 };
+
+template <typename T, int MODE>
+__device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
+                                          const T* __restrict__ x, const T* __restrict__ b,
+                                          size_t len, T out[4]) {
+    if (MODE == MODE_RU) {
+        const T* p = x + 3 * len;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T acc = T(0);
+#pragma unroll
+            for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * p[s[g]];
+            out[f] = dir ? T(0) : b[f * len + s[0]] - acc;
+        }
+        return;
+    }
+    if (MODE == MODE_BP) {
+        T acc = T(0);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int g = 0; g < 15; ++g) acc += st[ST_B + 15 * f + g] * x[f * len + s[g]];
+        out[3] = acc - b[3 * len + s[0]];
+        return;
+    }
+    if (MODE == MODE_RHS || MODE == MODE_GRADF) {
+        const T* pl = x + 3 * len;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T m = T(0);
+#pragma unroll
+            for (int g = 0; g < 15; ++g) m += st[ST_M + g] * x[f * len + s[g]];
+            if (MODE == MODE_RHS) {
+                out[f] = dir ? T(0) : m;
+            } else {
+                T gt = T(0);
+#pragma unroll
+                for (int g = 0; g < 15; ++g) gt += st[ST_GT + 15 * f + g] * pl[s[g]];
+                out[f] = m + gt;
+            }
+        }
+        if (MODE == MODE_RHS) {
+            T acc = T(0);
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int g = 0; g < 15; ++g) acc += st[ST_G + 15 * f + g] * x[f * len + s[g]];
+            out[3] = acc;
+        }
+        return;
+    }
+    // MODE_APPLY / MODE_RES
+    const T* p = x + 3 * len;
+    T bu = T(0);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* u = x + f * len;
+        T au = T(0), btp = T(0);
+#pragma unroll
+        for (int g = 0; g < 15; ++g) {
+            const T uv = u[s[g]];
+            au += st[ST_A + g] * uv;
+            btp += st[ST_BT + 15 * f + g] * p[s[g]];
+            bu += st[ST_B + 15 * f + g] * uv;
+        }
+        const T ku = au + btp;
+        out[f] = dir ? T(0) : (MODE == MODE_RES ? b[f * len + s[0]] - ku : ku);
+    }
+    T cp = T(0);
+#pragma unroll
+    for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * p[s[g]];
+    const T kp = bu - cp;
+    out[3] = MODE == MODE_RES ? b[3 * len + s[0]] - kp : kp;
+}
+
+template <int MODE>
+__device__ __forceinline__ void mode_fields(int& f0, int& f1) {
+    f0 = 0;
+    f1 = 4;
+    if (MODE == MODE_RU || MODE == MODE_GRADF) f1 = 3;
+    if (MODE == MODE_BP) f0 = 3;
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
+                                              const T* __restrict__ b, T* __restrict__ y,
+                                              double* __restrict__ partials) {
+    __shared__ double sh[4];
+    const size_t len = (size_t)L.len;
+    int f0, f1;
+    mode_fields<MODE>(f0, f1);
+    double ss = 0.0;
+    if ((int)blockIdx.x < L.n_vtiles) {
+        const Tile tl = L.vtiles[blockIdx.x];
+        if (tl.macro >= 0) {
+            const int n = L.n, k = tl.k, mm = n - k;
+            const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+            if (P.ok) {
+                const int j = P.j;
+                Rows R;
+                make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+                const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+#pragma unroll 1
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * P.q + r;
+                    if (i < 1 || i > mm - 1 - j) continue;
+                    int s[15];
+                    nbr_slots(R, i, s);
+                    T out[4];
+                    eval_node<T, MODE>(st, s, false, x, b, len, out);
+                    for (int f = f0; f < f1; ++f) {
+                        y[f * len + s[0]] = out[f];
+                        if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
+                    }
+                }
+            }
+        }
+    } else {
+        const int t = ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+        if (t < L.nif) {
+            const int nif = L.nif;
+            int s[15];
+            s[0] = L.if_self[t];
+#pragma unroll
+            for (int g = 1; g < 15; ++g) s[g] = L.if_nb[(g - 1) * nif + t];
+            const bool dir = (L.if_flag[t] & 1) != 0;
+            const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+            T out[4];
+            eval_node<T, MODE>(st, s, dir, x, b, len, out);
+            const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+            for (int f = f0; f < f1; ++f) {
+                for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
+                if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
+            }
+        }
+    }
+    if (MODE == MODE_RES) {
+        const double tot = block_sum256(ss, sh);
+        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Restriction r_c = P^T r_f (weights 1 at the coincident vertex, 1/2 at its 14
+// neighbours); velocity Dirichlet rows of the coarse level are zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
+                                                  const T* __restrict__ rf, T* __restrict__ bc) {
+    const size_t lc = (size_t)C.len, lf = (size_t)F.len;
+    if ((int)blockIdx.x < C.n_vtiles) {
+        const Tile tl = C.vtiles[blockIdx.x];
+        if (tl.macro < 0) return;
+        const int n = C.n, k = tl.k, mm = n - k;
+        const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+        if (!P.ok) return;
+        const int j = P.j;
+        Rows RC, RF;
+        make_rows(C.slab_base, n, (int)(tl.macro * C.mstride), j, k, RC);
+        make_rows(F.slab_base, F.n, (int)(tl.macro * F.mstride), 2 * j, 2 * k, RF);
+#pragma unroll 1
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * P.q + r;
+            if (i < 1 || i > mm - 1 - j) continue;
+            int s[15];
+            nbr_slots(RF, 2 * i, s);
+            const int sc = at(RC.b[0], RC.Q[0], i);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const T* v = rf + f * lf;
+                T acc = T(0);
+#pragma unroll
+                for (int g = 1; g < 15; ++g) acc += v[s[g]];
+                bc[f * lc + sc] = v[s[0]] + T(0.5) * acc;
+            }
+        }
+        return;
+    }
+    const int t = ((int)blockIdx.x - C.n_vtiles) * TPB + (int)threadIdx.x;
+    if (t >= C.nif) return;
+    const int tf = C.rif_fine[t];
+    const int nif = F.nif;
+    const int self = F.if_self[tf];
+    int nb[14];
+#pragma unroll
+    for (int g = 0; g < 14; ++g) nb[g] = F.if_nb[g * nif + tf];
+    const bool dir = (C.if_flag[t] & 1) != 0;
+    const int c0 = C.if_cptr[t], c1 = C.if_cptr[t + 1];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const T* v = rf + f * lf;
+        T acc = T(0);
+#pragma unroll
+        for (int g = 0; g < 14; ++g)
+            if (nb[g] != self) acc += v[nb[g]];
+        T val = v[self] + T(0.5) * acc;
+        if (f < 3 && dir) val = T(0);
+        for (int q = c0; q < c1; ++q) bc[f * lc + C.if_copy[q]] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation x_f += P e_c over every closure vertex of every macro: a fine
+// vertex with even local index copies the coarse value, any other vertex is
+// the midpoint of a coarse edge along the local direction given by its parity
+// pattern.  Copies stay identical because every copy averages the same two
+// coarse values.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int slot_of(const int* __restrict__ sb, int n, int mb, int i, int j,
+                                       int k) {
+    const int mm = n - k;
+    return mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j) + (i & 3) * ((mm + 4 - j) >> 2) + (i >> 2);
+}
+
+// local edge direction whose midpoints have the parity pattern pi | pj<<1 | pk<<2
+__host__ __device__ __forceinline__ void parity_dir(int pat, int* di, int* dj, int* dk) {
+    switch (pat) {
+        case 1: *di = 1; *dj = 0; *dk = 0; break;     // (1,0,0)
+        case 2: *di = 0; *dj = 1; *dk = 0; break;     // (0,1,0)
+        case 4: *di = 0; *dj = 0; *dk = 1; break;     // (0,0,1)
+        case 3: *di = -1; *dj = 1; *dk = 0; break;    // (-1,1,0)
+        case 6: *di = 0; *dj = -1; *dk = 1; break;    // (0,-1,1)
+        case 5: *di = -1; *dj = 0; *dk = 1; break;    // (-1,0,1)
+        default: *di = 1; *dj = -1; *dk = 1; break;   // (1,-1,1)
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
+                                                 const T* __restrict__ ec, T* __restrict__ xf) {
+    const size_t lc = (size_t)C.len, lf = (size_t)F.len;
+    const Tile tl = F.ctiles[blockIdx.x];
+    if (tl.macro < 0) return;
+    const int n = F.n, k = tl.k, mm = n - k;
+    const LanePos P = decode_lane(tl, n, 0, mm, threadIdx.x);
+    if (!P.ok) return;
+    const int j = P.j;
+    const int mbf = (int)(tl.macro * F.mstride), mbc = (int)(tl.macro * C.mstride);
+    const int b0 = mbf + F.slab_base[k] + R4d(mm + 1) - R4d(mm + 1 - j), Q0 = (mm + 4 - j) >> 2;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * P.q + r;
+        if (i > mm - j) continue;
+        const int sf = at(b0, Q0, i);
+        const int pi = i & 1, pj = j & 1, pk = k & 1;
+        if ((pi | pj | pk) == 0) {
+            const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) xf[f * lf + sf] += ec[f * lc + sc];
+            continue;
+        }
+        int di, dj, dk;
+        parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
+        const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
+        const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            xf[f * lf + sf] += T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Viscosity gradient: per macro e, sum over its closure vertices x of
+//   lam_u(x) . (A_e u)(x) + nu_e^-2 lam_p(x) ((C_e p)(x) + (G_e f)(x))
+// with the one-sided unit-viscosity stencils of e; the caller negates.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int slot_checked(const int* __restrict__ sb, int n, int mb, int i, int j,
+                                            int k) {
+    if (i < 0 || j < 0 || k < 0 || i + j + k > n) return -1;
+    return slot_of(sb, n, mb, i, j, k);
+}
+__device__ constexpr int LOFFD[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {-1, 1, 0}, {1, -1, 0},
+                                         {0, 1, 0},  {0, -1, 0}, {0, -1, 1}, {0, 1, -1}, {-1, 0, 1},
+                                         {1, 0, -1}, {0, 0, 1},  {0, 0, -1}, {1, -1, 1}, {-1, 1, -1}};
+
+__global__ void __launch_bounds__(TPB) k_grad_nu(LevelDev<double> L, const double* __restrict__ x,
+                                                 const double* __restrict__ lam,
+                                                 const double* __restrict__ f, double* partials) {
+    __shared__ double sh[4];
+    const size_t len = (size_t)L.len;
+    double acc = 0.0;
+    const Tile tl = L.ctiles[blockIdx.x];
+    if (tl.macro >= 0) {
+        const int n = L.n, k = tl.k, mm = n - k;
+        const LanePos P = decode_lane(tl, n, 0, mm, threadIdx.x);
+        if (P.ok) {
+            const int j = P.j, m = tl.macro;
+            const int mb = (int)(m * L.mstride);
+            const double inu2 = 1.0 / (L.macro_nu[m] * L.macro_nu[m]);
+#pragma unroll 1
+            for (int r = 0; r < 4; ++r) {
+                const int i = 4 * P.q + r;
+                if (i > mm - j) continue;
+                const int pat = (mm - j - i == 0 ? 1 : 0) | (i == 0 ? 2 : 0) | (j == 0 ? 4 : 0) |
+                                (k == 0 ? 8 : 0);
+                const double* gs = L.gst + ((size_t)m * 16 + pat) * GR_SIZE;
+                int s[15];
+#pragma unroll
+                for (int g = 0; g < 15; ++g)
+                    s[g] = slot_checked(L.slab_base, n, mb, i + LOFFD[g][0], j + LOFFD[g][1],
+                                        k + LOFFD[g][2]);
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double au = 0.0;
+#pragma unroll
+                    for (int g = 0; g < 15; ++g)
+                        if (s[g] >= 0) au += gs[GR_A + g] * x[c * len + s[g]];
+                    v += lam[c * len + s[0]] * au;
+                }
+                double cp = 0.0;
+#pragma unroll
+                for (int g = 0; g < 15; ++g)
+                    if (s[g] >= 0) {
+                        cp += gs[GR_C + g] * x[3 * len + s[g]];
+                        if (f)
+                            for (int c = 0; c < 3; ++c)
+                                cp += gs[GR_G + 15 * c + g] * f[c * len + s[g]];
+                    }
+                v += inu2 * lam[3 * len + s[0]] * cp;
+                acc += v;
+            }
+        }
+    }
+    const double tot = block_sum256(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// per-macro reduction of the gradient partials (one block per macro)
+__global__ void k_grad_reduce(const Tile* __restrict__ tiles, int ntiles,
+                              const double* __restrict__ partials, double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int m = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < ntiles; b += TPB)
+        if (tiles[b].macro == m) acc += partials[b];
+    const double tot = block_sum256(acc, sh);
+    if (threadIdx.x == 0) out[m] = -tot;
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_reduce_sum(const double* __restrict__ partials, int n, double* __restrict__ out,
+                             int sqrt_out) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += TPB) acc += partials[b];
+    const double tot = block_sum256(acc, sh);
+    if (threadIdx.x == 0) out[0] = sqrt_out ? sqrt(tot) : tot;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, size_t n, T v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+template <typename T>
+__global__ void k_add(T* __restrict__ x, const T* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] += y[i];
+}
+
+// y = x / s (s = device scalar), FP64 -> T
+template <typename T>
+__global__ void k_scale_cast(const double* __restrict__ x, const double* __restrict__ s,
+                             T* __restrict__ y, size_t n) {
+    const double inv = s[0] > 0.0 ? 1.0 / s[0] : 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (T)(x[i] * inv);
+}
+
+// x += s * e (s = device scalar), T -> FP64
+template <typename T>
+__global__ void k_axpy_cast(double* __restrict__ x, const double* __restrict__ s,
+                            const T* __restrict__ e, size_t n) {
+    const double sc = s[0];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] += sc * (double)e[i];
+}
+
+// weighted pressure sum sum_i m_i p_i over unique vertices (block partials)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __restrict__ p,
+                                                  double* __restrict__ partials) {
+    __shared__ double sh[4];
+    double acc = 0.0;
+    if ((int)blockIdx.x < L.n_vtiles) {
+        const Tile tl = L.vtiles[blockIdx.x];
+        if (tl.macro >= 0) {
+            const int n = L.n, k = tl.k, mm = n - k;
+            const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+            if (P.ok) {
+                const int j = P.j;
+                const int b0 = (int)(tl.macro * L.mstride) + L.slab_base[k] + R4d(mm + 1) -
+                               R4d(mm + 1 - j);
+                const int Q0 = (mm + 4 - j) >> 2;
+                const double w = (double)L.st[(size_t)tl.macro * ST_SIZE + ST_MASS];
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * P.q + r;
+                    if (i < 1 || i > mm - 1 - j) continue;
+                    acc += w * (double)p[at(b0, Q0, i)];
+                }
+            }
+        }
+    } else {
+        const int t = ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+        if (t < L.nif)
+            acc = (double)L.st[(size_t)L.if_sid[t] * ST_SIZE + ST_MASS] * (double)p[L.if_self[t]];
+    }
+    const double tot = block_sum256(acc, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+// p -= mean, mean = (sum_i m_i p_i) / (sum_i m_i) from a device scalar
+template <typename T>
+__global__ void k_sub_mean(T* __restrict__ p, size_t n, const double* __restrict__ wsum,
+                           double inv_mass) {
+    const T mean = (T)(wsum[0] * inv_mass);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] -= mean;
+}
+
+// layout conversion and ghost exchange
+__global__ void k_scatter(const int* __restrict__ slot_node, size_t len, int nfields,
+                          const double* __restrict__ nodal, size_t N, double* __restrict__ x) {
+    for (size_t s = blockIdx.x * (size_t)blockDim.x + threadIdx.x; s < len;
+         s += (size_t)gridDim.x * blockDim.x) {
+        const int v = slot_node[s];
+        for (int f = 0; f < nfields; ++f) x[f * len + s] = v >= 0 ? nodal[f * N + v] : 0.0;
+    }
+}
+__global__ void k_gather(const int* __restrict__ node_slot, size_t N, int nfields,
+                         const double* __restrict__ x, size_t len, double* __restrict__ nodal) {
+    for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < N;
+         v += (size_t)gridDim.x * blockDim.x) {
+        const int s = node_slot[v];
+        for (int f = 0; f < nfields; ++f) nodal[f * N + v] = x[f * len + s];
+    }
+}
+template <typename T>
+__global__ void k_exchange(LevelDev<T> L, int nfields, T* __restrict__ x) {
+    const int t = blockIdx.x * TPB + threadIdx.x;
+    if (t >= L.nif) return;
+    const size_t len = (size_t)L.len;
+    const int self = L.if_self[t];
+    for (int f = 0; f < nfields; ++f) {
+        const T v = x[f * len + self];
+        for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q) x[f * len + L.if_copy[q]] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse grid (Section 3.7): block-diagonal preconditioned MINRES on the
+// level-0 Stokes system in one workgroup.  The preconditioner is
+// diag(A_0^-1 (dense inverse, per velocity component), lumped mass weighted
+// by 1/nu); the recurrence is the standard preconditioned MINRES (Lanczos in
+// the preconditioner inner product with Givens rotations).
+// ---------------------------------------------------------------------------
+struct CoarseDev {
+    int nd, nfv, N, maxit, project;
+    double tol, inv_mass;
+    const int* rowptr;
+    const int* col;
+    const double* val;
+    const double* ainv;     // symmetric [nfv][nfv]
+    const double* pdinv;    // [N]
+    const double* mass;     // [N]
+    const int* vel_node;    // [nfv]
+    const int* node_vidx;   // [N] compact velocity index or -1
+    const int* node_slot;   // [N]
+    const int* node_cptr;   // [N+1]
+    const int* node_copy;
+    double* gscratch;       // 9 * nd doubles when the vectors do not fit in LDS
+    int use_lds;
+};
+
+constexpr int CTPB = 1024;
+
+__device__ __forceinline__ double csum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += red[q];
+    return t;
+}
+
+__device__ void coarse_precond(const CoarseDev& cd, const double* __restrict__ v,
+                               double* __restrict__ z) {
+    const int nfv = cd.nfv;
+    for (int i = threadIdx.x; i < cd.nd; i += blockDim.x) {
+        if (i < 3 * nfv) {
+            const int c = i / nfv, r = i - c * nfv;
+            const double* vv = v + c * nfv;
+            double acc = 0.0;
+            for (int q = 0; q < nfv; ++q) acc += cd.ainv[(size_t)q * nfv + r] * vv[q];
+            z[i] = acc;
+        } else {
+            z[i] = cd.pdinv[i - 3 * nfv] * v[i];
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restrict__ b, size_t blen,
+                                                 T* __restrict__ x, size_t xlen,
+                                                 double* __restrict__ stats) {
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const int nd = cd.nd, nfv = cd.nfv, N = cd.N;
+    double* base = cd.use_lds ? smem : cd.gscratch;
+    double* vo = base;
+    double* v = vo + nd;
+    double* z = v + nd;
+    double* zn = z + nd;
+    double* q = zn + nd;
+    double* wo = q + nd;
+    double* w = wo + nd;
+    double* xs = w + nd;
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+        double bi;
+        if (i < 3 * nfv) {
+            const int c = i / nfv;
+            bi = (double)b[c * blen + cd.node_slot[cd.vel_node[i - c * nfv]]];
+        } else {
+            bi = (double)b[3 * blen + cd.node_slot[i - 3 * nfv]];
+        }
+        v[i] = bi;
+        vo[i] = 0.0;
+        wo[i] = 0.0;
+        w[i] = 0.0;
+        xs[i] = 0.0;
+    }
+    __syncthreads();
+    double part = 0.0;
+    if (cd.project) {
+        // K_0 is singular (constant pressure); make the right-hand side
+        // consistent the way the mean-zero constraint does: b_p -= mu m with
+        // mu = (sum_i b_p,i) / (sum_i m_i), the Lagrange multiplier of
+        // sum_i m_i p_i = 0.  Rounding in the restricted residual would
+        // otherwise leave a small inconsistent part that MINRES cannot remove.
+        for (int i = threadIdx.x; i < N; i += blockDim.x) part += v[3 * nfv + i];
+        const double mu = csum(part, red) * cd.inv_mass;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) v[3 * nfv + i] -= mu * cd.mass[i];
+        __syncthreads();
+        part = 0.0;
+    }
+    coarse_precond(cd, v, z);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) part += z[i] * v[i];
+    double gamma = sqrt(fmax(csum(part, red), 0.0));
+    const double gamma1 = gamma;
+    double eta = gamma, gamma_old = 1.0;
+    double c0 = 1.0, c1 = 1.0, s0 = 0.0, s1 = 0.0;
+    int it = 0;
+    double rel = 0.0;
+    if (gamma1 > 0.0) {
+        for (it = 1; it <= cd.maxit; ++it) {
+            const double ig = 1.0 / gamma;
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) z[i] *= ig;
+            __syncthreads();
+            part = 0.0;
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+                double acc = 0.0;
+                for (int e = cd.rowptr[i]; e < cd.rowptr[i + 1]; ++e) acc += cd.val[e] * z[cd.col[e]];
+                q[i] = acc;
+                part += acc * z[i];
+            }
+            const double delta = csum(part, red);
+            const double a = delta / gamma, bq = gamma / gamma_old;
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) q[i] = q[i] - a * v[i] - bq * vo[i];
+            __syncthreads();
+            coarse_precond(cd, q, zn);
+            __syncthreads();
+            part = 0.0;
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) part += zn[i] * q[i];
+            const double gnew = sqrt(fmax(csum(part, red), 0.0));
+            const double al0 = c1 * delta - c0 * s1 * gamma;
+            const double al1 = sqrt(al0 * al0 + gnew * gnew);
+            const double al2 = s1 * delta + c0 * c1 * gamma;
+            const double al3 = s0 * gamma;
+            c0 = c1;
+            s0 = s1;
+            c1 = al0 / al1;
+            s1 = gnew / al1;
+            const double ce = c1 * eta;
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+                const double wn = (z[i] - al3 * wo[i] - al2 * w[i]) / al1;
+                wo[i] = wn;   // becomes the new w after the swap below
+                xs[i] += ce * wn;
+            }
+            __syncthreads();
+            eta = -s1 * eta;
+            // rotate buffers: (vo, v, q) <- (v, q, vo); (z, zn) swap; (wo, w) swap
+            double* t0 = vo;
+            vo = v;
+            v = q;
+            q = t0;
+            double* t1 = z;
+            z = zn;
+            zn = t1;
+            double* t2 = wo;
+            wo = w;
+            w = t2;
+            gamma_old = gamma;
+            gamma = gnew;
+            rel = fabs(eta) / gamma1;
+            if (rel <= cd.tol || gnew == 0.0) break;
+        }
+        if (it > cd.maxit) it = cd.maxit;
+    }
+    // zero-mean pressure
+    if (cd.project) {
+        part = 0.0;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) part += cd.mass[i] * xs[3 * nfv + i];
+        const double mean = csum(part, red) * cd.inv_mass;
+        for (int i = threadIdx.x; i < N; i += blockDim.x) xs[3 * nfv + i] -= mean;
+        __syncthreads();
+    }
+    for (int vtx = threadIdx.x; vtx < N; vtx += blockDim.x) {
+        const int iv = cd.node_vidx[vtx];
+        T val[4];
+        for (int c = 0; c < 3; ++c) val[c] = iv >= 0 ? (T)xs[c * nfv + iv] : T(0);
+        val[3] = (T)xs[3 * nfv + vtx];
+        for (int e = cd.node_cptr[vtx]; e < cd.node_cptr[vtx + 1]; ++e) {
+            const int s = cd.node_copy[e];
+            for (int c = 0; c < 4; ++c) x[c * xlen + s] = val[c];
+        }
+    }
+    if (threadIdx.x == 0 && stats) {
+        stats[0] = (double)it;
+        stats[1] = rel;
+    }
+}
+
+}  // namespace hhg

@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI (no GPU): exported symbols, argument and mesh
+validation, and the hierarchy the library builds compared with the oracle's
+mesh (counts, Dirichlet sets, lattice order)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+import paper_1511_02134_amd as P
+from oracle import build_hierarchy
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_function():
+    header = open(os.path.join(ROOT, "include", "hhg.h")).read()
+    declared = set(re.findall(r"\b(hhg_[a-z_]+)\s*\(", header))
+    assert declared == set(P.ABI_FUNCTIONS)
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _mesh(cid=1):
+    return W.WORKLOADS[cid].mesh()
+
+
+def _expect_einval(xyz, tet, nu, tags, R=3, **opts):
+    with pytest.raises(P.HHGError) as e:
+        P.plan(xyz, tet, nu, tags, R, **opts)
+    assert e.value.status == P.HHG_EINVAL
+    return str(e.value)
+
+
+def test_plan_rejects_malformed_meshes():
+    xyz, tet, nu, tags = _mesh()
+    assert P.plan(xyz, tet, nu, tags, 3) > 0
+    bad = tet.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]                       # breaks the Kuhn path
+    assert "Kuhn" in _expect_einval(xyz, bad, nu, tags)
+    bad = tet.copy()
+    bad[0] = bad[0][::-1]                                 # reversed (negative steps)
+    _expect_einval(xyz, bad, nu, tags)
+    bad = tet.copy()
+    bad[0, 0] = 99                                        # vertex id out of range
+    _expect_einval(xyz, bad, nu, tags)
+    _expect_einval(xyz, tet[1:], nu[1:], tags[1:])        # does not tile the box
+    t2 = tags.copy()
+    t2[t2 == 1] = 0                                       # boundary face tagged interior
+    _expect_einval(xyz, tet, nu, t2)
+    t3 = tags.copy()
+    inner = np.argwhere(tags == 0)[0]
+    t3[tuple(inner)] = 1                                  # interior face tagged boundary
+    _expect_einval(xyz, tet, nu, t3)
+    t4 = tags.copy()
+    t4[0, 0] = 7
+    _expect_einval(xyz, tet, nu, t4)
+    n2 = nu.copy()
+    n2[2] = -1.0
+    _expect_einval(xyz, tet, n2, tags)
+    n2[2] = np.nan
+    _expect_einval(xyz, tet, n2, tags)
+    x2 = xyz.copy()
+    x2[0, 0] = 0.5                                        # not on the integer lattice
+    _expect_einval(x2, tet, nu, tags)
+
+
+def test_plan_rejects_bad_arguments():
+    xyz, tet, nu, tags = _mesh()
+    for R in (1, 11, -3):
+        _expect_einval(xyz, tet, nu, tags, R=R)
+    _expect_einval(xyz, tet, nu, tags, omega=0.0)
+    _expect_einval(xyz, tet, nu, tags, nu1=0, nu2=0)
+    _expect_einval(xyz, tet, nu, tags, precision=3)
+    _expect_einval(xyz, tet, nu, tags, coarse_maxit=0)
+
+
+def test_host_context_rejects_device_calls():
+    xyz, tet, nu, tags = _mesh()
+    s = P.Solver(xyz, tet, nu, tags, 3, host_only=True)
+    st = P.lib.hhg_apply(s.ctx, 0, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert st == P.HHG_EINVAL
+    assert b"host-only" in P.lib.hhg_last_error(s.ctx)
+    st = P.lib.hhg_solve(s.ctx, ctypes.c_void_p(16), ctypes.c_void_p(32), 1e-8, 5, None, None)
+    assert st == P.HHG_EINVAL
+
+
+@pytest.mark.parametrize("cid", [1, 4, 5])
+def test_hierarchy_matches_oracle_mesh(cid):
+    """Vertex counts, DoFs and velocity Dirichlet sets of every level agree
+    with the oracle's independently refined mesh."""
+    R = 4
+    cfg = W.WORKLOADS[cid].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, R, host_only=True)
+    H = build_hierarchy(xyz, tet, nu, tags, R)
+    assert s.levels == len(H.levels)
+    for l, lv in enumerate(H.levels):
+        assert s.num_nodes(l) == lv.N
+        assert s.num_dofs(l) == lv.ndofs()
+        ijk, d = s.node_info(l)
+        assert np.array_equal(ijk, lv.X)
+        assert np.array_equal(d, lv.dirichlet)
+        # interface vertices = vertices on macro faces: at least the box surface
+        assert s.num_interface(l) >= np.count_nonzero(
+            np.any((lv.X == 0) | (lv.X == np.array(lv.shape) - 1), axis=1))
+        assert np.allclose(s.mass_weights(l), lv.mass, rtol=1e-13, atol=0)
+        # duplicated copies make the layout a little longer than the lattice
+        assert s.vec_len(l) >= lv.N
+
+
+@pytest.mark.parametrize("cid,R,order", [(1, 5, 1), (4, 4, 1), (5, 4, 1), (4, 4, 0), (4, 4, 2),
+                                         (5, 2, 1), (4, 3, 2)])
+def test_kernel_index_arithmetic_on_host(cid, R, order):
+    """The device index code (compiled for the host) reaches exactly the
+    intended vertices on every level: no access outside a macro, every vertex
+    once per sweep, colour sweeps touch only their colour."""
+    cfg = W.WORKLOADS[cid].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    P.Solver(xyz, tet, nu, tags, R, host_only=True, block_order=order).check_layout()
