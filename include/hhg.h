@@ -90,6 +90,10 @@ typedef struct {
     int32_t block_order;  /* workgroup -> tile order: 0 natural, 1 XCD-aware (default),
                              2 reversed (a schedule permutation used to test that
                              results do not depend on workgroup order) */
+    int32_t coarse_prec;  /* pressure block of the coarse MINRES preconditioner:
+                             0 exact Schur complement B A^-1 B^T + C (dense,
+                             default), 1 lumped mass weighted by 1/nu (the
+                             paper's choice, more iterations) */
 } hhg_opts;
 
 /* Result of hhg_solve. */
@@ -186,8 +190,9 @@ hhg_status hhg_restrict(hhg_ctx* ctx, int32_t level, const void* d_r_fine, void*
 hhg_status hhg_prolong_add(hhg_ctx* ctx, int32_t level, const void* d_e_coarse,
                            void* d_x_fine, hhg_stream stream);
 /* Level-0 solve (Section 3.7): block-diagonal preconditioned MINRES on the
- * whole coarse Stokes system, preconditioner diag(A_0^-1, lumped 1/nu-weighted
- * mass), run to opts.coarse_rtol, pressure projected to zero mean when the
+ * whole coarse Stokes system, preconditioner diag(A_0^-1, S_0^-1) with S_0 the
+ * exact Schur complement or the lumped 1/nu-weighted mass (opts.coarse_prec),
+ * run to opts.coarse_rtol, pressure projected to zero mean when the
  * pressure has a null space.  x0 = K_0^-1 b0.  iters / relres (host, may be
  * NULL) synchronise the stream. */
 hhg_status hhg_coarse_solve(hhg_ctx* ctx, const void* d_b0, void* d_x0, int32_t* iters,

@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("cycle", ctypes.c_int32),
                 ("p_sweep", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
-                ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32)]
+                ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32),
+                ("coarse_prec", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

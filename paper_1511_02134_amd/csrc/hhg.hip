@@ -19,6 +19,9 @@ namespace {
 
 thread_local std::string g_error;
 
+// leading interface blocks of a launch: ceil(count / TPB), padded to a multiple of 8
+inline int iface_blocks(int count) { return ((count + TPB - 1) / TPB + 7) / 8 * 8; }
+
 struct Carver {
     char* base;
     size_t off = 0;
@@ -38,6 +41,7 @@ struct DevLevelArrays {
     double *st64, *gst64, *nu64;
     float *st32, *gst32, *nu32;
     int32_t *slot_node, *node_slot;
+    int32_t* ctile_macro0;   // [nm+1] first natural closure tile of each macro
     // work vectors (4 fields each)
     double *x64, *b64, *r64, *t64;
     float *x32, *b32, *r32, *t32;
@@ -109,7 +113,8 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
         *err = "omega must lie in (0, 2)";
         return false;
     }
-    if (!(o->coarse_rtol > 0.0) || o->coarse_maxit < 1 || o->coarse_maxit > 100000) {
+    if (!(o->coarse_rtol > 0.0) || o->coarse_maxit < 1 || o->coarse_maxit > 100000 ||
+        o->coarse_prec < 0 || o->coarse_prec > 1) {
         *err = "invalid coarse solver settings";
         return false;
     }
@@ -170,6 +175,7 @@ size_t layout(hhg_ctx* c, char* ws) {
         a.gst32 = cv.take<float>(h.gst.size());
         a.nu32 = cv.take<float>(h.nm);
         a.slot_node = cv.take<int32_t>(h.len);
+        a.ctile_macro0 = cv.take<int32_t>(h.nm + 1);
         a.node_slot = cv.take<int32_t>(h.N);
         const size_t v4 = 4 * (size_t)h.len;
         a.r64 = cv.take<double>(v4);
@@ -186,7 +192,7 @@ size_t layout(hhg_ctx* c, char* ws) {
             a.r32 = cv.take<float>(v4);
             a.t32 = cv.take<float>(v4);
         }
-        const int nb = (int)h.vtiles.size() + (h.nif + TPB - 1) / TPB;
+        const int nb = (int)h.vtiles.size() + iface_blocks(h.nif);
         maxblocks = std::max(maxblocks, nb);
         maxblocks = std::max(maxblocks, (int)h.ctiles.size());
     }
@@ -205,6 +211,7 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.val = cv.take<double>(std::max<size_t>(1, C.val.size()));
     d.ainv = cv.take<double>(std::max<size_t>(1, C.ainv.size()));
     d.pdinv = cv.take<double>(C.N);
+    d.sinv = cv.take<double>((size_t)C.N * C.N);
     d.mass = cv.take<double>(C.N);
     d.vel_node = cv.take<int32_t>(std::max(1, C.nfv));
     d.node_vidx = cv.take<int32_t>(C.N);
@@ -226,6 +233,8 @@ void fill_view(hhg_ctx* c, int l, LevelDev<T>& v) {
     v.slab_base = a.slab_base;
     v.vtiles = a.vtiles;
     v.n_vtiles = (int32_t)h.vtiles.size();
+    v.nv_nat = 0;
+    for (const Tile& t : h.vtiles) v.nv_nat += t.macro >= 0 ? 1 : 0;
     v.ctiles = a.ctiles;
     v.n_ctiles = (int32_t)h.ctiles.size();
     v.nif = h.nif;
@@ -284,6 +293,8 @@ hhg_status upload_stencils(hhg_ctx* c) {
         return s;
     if ((s = upload<double>(c, (double*)c->cd.pdinv, C.pdinv.data(), C.pdinv.size())) != HHG_OK)
         return s;
+    if ((s = upload<double>(c, (double*)c->cd.sinv, C.sinv.data(), C.sinv.size())) != HHG_OK)
+        return s;
     if ((s = upload<double>(c, (double*)c->cd.mass, C.mass.data(), C.mass.size())) != HHG_OK)
         return s;
     c->cd.inv_mass = c->inv_mass[0];
@@ -313,6 +324,13 @@ hhg_status upload_all(hhg_ctx* c) {
         if (!h.rif_fine.empty()) UP(int32_t, a.rif_fine, h.rif_fine);
         UP(int32_t, a.slot_node, h.slot_node);
         UP(int32_t, a.node_slot, h.node_slot);
+        {
+            std::vector<int32_t> m0(h.nm + 1, 0);
+            for (const Tile& t : h.ctiles)
+                if (t.macro >= 0) m0[t.macro + 1]++;
+            for (int m = 0; m < h.nm; ++m) m0[m + 1] += m0[m];
+            UP(int32_t, a.ctile_macro0, m0);
+        }
         fill_view(c, l, c->D64[l]);
         fill_view(c, l, c->D32[l]);
     }
@@ -332,6 +350,7 @@ hhg_status upload_all(hhg_ctx* c) {
     d.maxit = c->opts.coarse_maxit;
     d.tol = c->opts.coarse_rtol;
     d.project = c->mi.project ? 1 : 0;
+    d.schur = c->opts.coarse_prec == 0 ? 1 : 0;
     c->coarse_smem = (size_t)9 * C.nd * sizeof(double);
     d.use_lds = c->coarse_smem <= 60 * 1024 ? 1 : 0;
     if (!d.use_lds) c->coarse_smem = 0;
@@ -433,27 +452,29 @@ void vecs<float>(hhg_ctx* c, int l, float** x, float** b, float** r, float** t) 
 template <typename T, int MODE>
 void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
-    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
     Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
              bytes);
-    hipLaunchKernelGGL((k_full<T, MODE>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials);
+    hipLaunchKernelGGL((k_full<T, MODE>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials, ib);
 }
 
 template <typename T>
 void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
-    const int grid = v.n_vtiles + (cnt + TPB - 1) / TPB;
+    const int ib = iface_blocks(cnt);
+    const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     if (vel) {
         Timed tm(c, HHG_K_VEL, s, finest, c->bytes_vel[col]);
-        hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0));
+        hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0), ib);
     } else {
         Timed tm(c, HHG_K_PRES, s, finest, c->bytes_pres[col]);
         hipLaunchKernelGGL((k_colour<T, false>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
-                           (T)c->opts.omega);
+                           (T)c->opts.omega, ib);
     }
 }
 
@@ -479,21 +500,24 @@ void fill(T* x, size_t n, T val, hipStream_t s) {
 template <typename T>
 void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
-    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + v.n_vtiles;
     {
         Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
         hipLaunchKernelGGL((k_full<T, MODE_RES>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
-                           c->partials);
+                           c->partials, ib);
     }
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials, grid, out, 1);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+                       v.nv_nat + (v.nif + TPB - 1) / TPB, out, 1);
 }
 
 template <typename T>
 void restrict_to(hhg_ctx* c, int l, const T* rf, T* bc, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
-    const int grid = C.n_vtiles + (C.nif + TPB - 1) / TPB;
-    hipLaunchKernelGGL(k_restrict<T>, dim3(grid), dim3(TPB), 0, s, C, F, rf, bc);
+    const int ib = iface_blocks(C.nif);
+    const int grid = ib + C.n_vtiles;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(grid), dim3(TPB), 0, s, C, F, rf, bc, ib);
 }
 
 template <typename T>
@@ -514,10 +538,12 @@ template <typename T>
 void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
     if (!c->mi.project) return;
     LevelDev<T>& v = view<T>(c, l);
-    const int grid = v.n_vtiles + (v.nif + TPB - 1) / TPB;
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + v.n_vtiles;
     const size_t len = (size_t)v.len;
-    hipLaunchKernelGGL(k_mass_dot<T>, dim3(grid), dim3(TPB), 0, s, v, x + 3 * len, c->partials);
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials, grid, c->scal + 4, 0);
+    hipLaunchKernelGGL(k_mass_dot<T>, dim3(grid), dim3(TPB), 0, s, v, x + 3 * len, c->partials, ib);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+                       v.nv_nat + (v.nif + TPB - 1) / TPB, c->scal + 4, 0);
     hipLaunchKernelGGL(k_sub_mean<T>, dim3(grid_for(len)), dim3(TPB), 0, s, x + 3 * len, len,
                        c->scal + 4, c->inv_mass[l]);
 }
@@ -566,6 +592,7 @@ void hhg_default_opts(hhg_opts* o) {
     o->coarse_rtol = 1e-14;
     o->coarse_maxit = 500;
     o->block_order = 1;
+    o->coarse_prec = 0;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }
@@ -946,7 +973,7 @@ hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, d
     LevelDev<double>& v = c->D64[c->L];
     hipLaunchKernelGGL(k_grad_nu, dim3(v.n_ctiles), dim3(TPB), 0, s, v, (const double*)x,
                        (const double*)lam, (const double*)f, c->gpart);
-    hipLaunchKernelGGL(k_grad_reduce, dim3(v.nm), dim3(TPB), 0, s, c->A[c->L].ctiles, v.n_ctiles,
+    hipLaunchKernelGGL(k_grad_reduce, dim3(v.nm), dim3(TPB), 0, s, c->A[c->L].ctile_macro0,
                        c->gpart, dnu);
     if (df) {
         if (df == lam) return fail(c, HHG_EINVAL, "dJ_df must not alias lambda");

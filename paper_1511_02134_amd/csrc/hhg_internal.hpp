@@ -62,6 +62,9 @@ struct Tile {
     int32_t k;      // slab
     int32_t t0;     // first lane of the tile in the slab's fold
     int32_t W;      // fold width (quads per row pair)
+    int32_t nat;    // index in natural (macro, slab, lane) order; reductions
+                    // write their partial sums there, so sums do not depend
+                    // on the workgroup order
 };
 
 // Device view of one level (all pointers into the workspace).
@@ -74,6 +77,8 @@ struct LevelDev {
     const int32_t* slab_base;  // [n+2]
     const Tile* vtiles;    // interior tiles (launch order)
     int32_t n_vtiles;      // including padding
+    int32_t nv_nat;        // interior tiles without padding (partials of the
+                           // interface blocks follow them)
     const Tile* ctiles;    // closure tiles (launch order)
     int32_t n_ctiles;
     // interface vertices (every vertex on a macro face, edge or corner)

@@ -339,7 +339,8 @@ static std::vector<Tile> make_tiles(int n, int nm, bool interior, int order) {
                 W = std::max(W, w);
             }
             int lanes = npairs * W;
-            for (int t0 = 0; t0 < lanes; t0 += 256) tiles.push_back({m, k, t0, W});
+            for (int t0 = 0; t0 < lanes; t0 += 256)
+                tiles.push_back({m, k, t0, W, (int32_t)tiles.size()});
         }
     }
     const int T = (int)tiles.size();
@@ -355,7 +356,7 @@ static std::vector<Tile> make_tiles(int n, int nm, bool interior, int order) {
     out.resize(T8);
     for (int b = 0; b < T8; ++b) {
         int t = (b % 8) * chunk + b / 8;
-        out[b] = t < T ? tiles[t] : Tile{-1, 0, 0, 1};
+        out[b] = t < T ? tiles[t] : Tile{-1, 0, 0, 1, -1};
     }
     return out;
 }
@@ -721,6 +722,88 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, CoarseHost* out, std::
             C.ainv[(size_t)i * nfv + c] = s / Lc[(size_t)i * nfv + i];
         }
     }
+    // Exact Schur complement S = sum_k B_k A^-1 B_k^T + C of the level-0
+    // system (dense); a rank-one term alpha m m^T on the constant pressure
+    // makes it SPD when the pressure has a null space.  Its inverse is the
+    // pressure block of the block-diagonal MINRES preconditioner.
+    {
+        std::vector<double> Bk((size_t)N * nfv), BA((size_t)N * nfv), S((size_t)N * N, 0.0);
+        for (int k = 0; k < 3; ++k) {
+            std::fill(Bk.begin(), Bk.end(), 0.0);
+            for (int v = 0; v < N; ++v) {
+                const int row = 3 * nfv + v;
+                for (int e = C.rowptr[row]; e < C.rowptr[row + 1]; ++e) {
+                    const int col = C.col[e];
+                    if (col >= k * nfv && col < (k + 1) * nfv) Bk[(size_t)v * nfv + (col - k * nfv)] = C.val[e];
+                }
+            }
+            for (int v = 0; v < N; ++v)
+                for (int j = 0; j < nfv; ++j) {
+                    double acc = 0.0;
+                    for (int q = 0; q < nfv; ++q) acc += Bk[(size_t)v * nfv + q] * C.ainv[(size_t)q * nfv + j];
+                    BA[(size_t)v * nfv + j] = acc;
+                }
+            for (int v = 0; v < N; ++v)
+                for (int w = 0; w < N; ++w) {
+                    double acc = 0.0;
+                    for (int q = 0; q < nfv; ++q) acc += BA[(size_t)v * nfv + q] * Bk[(size_t)w * nfv + q];
+                    S[(size_t)v * N + w] += acc;
+                }
+        }
+        for (int v = 0; v < N; ++v) {
+            const int row = 3 * nfv + v;
+            for (int e = C.rowptr[row]; e < C.rowptr[row + 1]; ++e)
+                if (C.col[e] >= 3 * nfv) S[(size_t)v * N + (C.col[e] - 3 * nfv)] -= C.val[e];
+        }
+        std::vector<double> mvec(N);
+        double mm = 0.0, tr = 0.0;
+        for (int v = 0; v < N; ++v) {
+            mvec[v] = rec_of(v)[ST_MASS];
+            mm += mvec[v] * mvec[v];
+            tr += S[(size_t)v * N + v];
+        }
+        if (mi.project) {
+            const double alpha = tr / mm;
+            for (int v = 0; v < N; ++v)
+                for (int w = 0; w < N; ++w) S[(size_t)v * N + w] += alpha * mvec[v] * mvec[w];
+        }
+        // symmetrise round-off, then invert by Cholesky
+        for (int v = 0; v < N; ++v)
+            for (int w = 0; w < v; ++w) {
+                const double a = 0.5 * (S[(size_t)v * N + w] + S[(size_t)w * N + v]);
+                S[(size_t)v * N + w] = S[(size_t)w * N + v] = a;
+            }
+        std::vector<double> Lf(S);
+        for (int j = 0; j < N; ++j) {
+            double d = Lf[(size_t)j * N + j];
+            for (int q = 0; q < j; ++q) d -= Lf[(size_t)j * N + q] * Lf[(size_t)j * N + q];
+            if (!(d > 0.0)) {
+                *err = "coarse Schur complement is not positive definite";
+                return false;
+            }
+            d = std::sqrt(d);
+            Lf[(size_t)j * N + j] = d;
+            for (int i = j + 1; i < N; ++i) {
+                double sacc = Lf[(size_t)i * N + j];
+                for (int q = 0; q < j; ++q) sacc -= Lf[(size_t)i * N + q] * Lf[(size_t)j * N + q];
+                Lf[(size_t)i * N + j] = sacc / d;
+            }
+        }
+        C.sinv.assign((size_t)N * N, 0.0);
+        std::vector<double> yv(N);
+        for (int c = 0; c < N; ++c) {
+            for (int i = 0; i < N; ++i) {
+                double sacc = (i == c) ? 1.0 : 0.0;
+                for (int q = 0; q < i; ++q) sacc -= Lf[(size_t)i * N + q] * yv[q];
+                yv[i] = sacc / Lf[(size_t)i * N + i];
+            }
+            for (int i = N - 1; i >= 0; --i) {
+                double sacc = yv[i];
+                for (int q = i + 1; q < N; ++q) sacc -= Lf[(size_t)q * N + i] * C.sinv[(size_t)q * N + c];
+                C.sinv[(size_t)i * N + c] = sacc / Lf[(size_t)i * N + i];
+            }
+        }
+    }
     C.pdinv.resize(N);
     C.mass.resize(N);
     C.node_slot.resize(N);
@@ -742,7 +825,6 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, CoarseHost* out, std::
         }
         C.node_cptr.push_back((int32_t)C.node_copy.size());
     }
-    (void)mi;
     return true;
 }
 

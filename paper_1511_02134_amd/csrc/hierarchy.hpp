@@ -84,6 +84,9 @@ struct CoarseHost {
     std::vector<double> val;
     std::vector<double> ainv;       // [nfv][nfv] inverse of the free-free A block
     std::vector<double> pdinv;      // [N] 1 / (sum |T|/4/nu_T)
+    std::vector<double> sinv;       // [N][N] inverse of the Schur complement
+                                    // B A^-1 B^T + C (+ a rank-one term on the
+                                    // pressure null space), symmetric
     std::vector<double> mass;       // [N] int phi_i
     std::vector<int32_t> vel_node;  // [nfv] lattice node of compact velocity vertex
     std::vector<int32_t> node_slot; // [N]

@@ -1,7 +1,9 @@
 // Device kernels of the Uzawa multigrid (gfx950).  Included once, by hhg.hip.
 //
 // Work decomposition.  Every level is processed by two kinds of workgroups in
-// the same launch:
+// the same launch; the interface blocks come first (their count padded to a
+// multiple of 8 so that volume tile b still runs on XCD b % 8), so that their
+// scattered accesses overlap the volume tiles instead of forming the tail:
 //  * volume tiles: 256 lanes over the rows of one slab k of one macro.  Rows
 //    j and jh-j of the slab are folded into one row of constant width W so
 //    that the triangular slab fills whole wavefronts; a lane owns one quad
@@ -136,10 +138,10 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // ---------------------------------------------------------------------------
 template <typename T, bool VEL>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
-                                                const T* __restrict__ rhs, T omega) {
+                                                const T* __restrict__ rhs, T omega, int ib) {
     const size_t len = (size_t)L.len;
-    if ((int)blockIdx.x < L.n_vtiles) {
-        const Tile tl = L.vtiles[blockIdx.x];
+    if ((int)blockIdx.x >= ib) {
+        const Tile tl = L.vtiles[blockIdx.x - ib];
         if (tl.macro < 0) return;
         const int n = L.n, k = tl.k, mm = n - k;
         const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         return;
     }
     const int t0 = L.col_start[c];
-    const int t = t0 + ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+    const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
     if (t >= tend) return;
     const int nif = L.nif;
@@ -300,14 +302,16 @@ __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
 template <typename T, int MODE>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b, T* __restrict__ y,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, int ib) {
     __shared__ double sh[4];
     const size_t len = (size_t)L.len;
     int f0, f1;
     mode_fields<MODE>(f0, f1);
     double ss = 0.0;
-    if ((int)blockIdx.x < L.n_vtiles) {
-        const Tile tl = L.vtiles[blockIdx.x];
+    int slot = -1;   // partial-sum slot of this block
+    if ((int)blockIdx.x >= ib) {
+        const Tile tl = L.vtiles[blockIdx.x - ib];
+        slot = tl.nat;
         if (tl.macro >= 0) {
             const int n = L.n, k = tl.k, mm = n - k;
             const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
@@ -332,7 +336,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             }
         }
     } else {
-        const int t = ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+        if ((int)blockIdx.x * TPB < L.nif) slot = L.nv_nat + (int)blockIdx.x;
+        const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif) {
             const int nif = L.nif;
             int s[15];
@@ -352,7 +357,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
     }
     if (MODE == MODE_RES) {
         const double tot = block_sum256(ss, sh);
-        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+        if (threadIdx.x == 0 && slot >= 0) partials[slot] = tot;
     }
 }
 
@@ -362,10 +367,11 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
-                                                  const T* __restrict__ rf, T* __restrict__ bc) {
+                                                  const T* __restrict__ rf, T* __restrict__ bc,
+                                                  int ib) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
-    if ((int)blockIdx.x < C.n_vtiles) {
-        const Tile tl = C.vtiles[blockIdx.x];
+    if ((int)blockIdx.x >= ib) {
+        const Tile tl = C.vtiles[blockIdx.x - ib];
         if (tl.macro < 0) return;
         const int n = C.n, k = tl.k, mm = n - k;
         const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
@@ -392,7 +398,7 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
         }
         return;
     }
-    const int t = ((int)blockIdx.x - C.n_vtiles) * TPB + (int)threadIdx.x;
+    const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
     if (t >= C.nif) return;
     const int tf = C.rif_fine[t];
     const int nif = F.nif;
@@ -539,17 +545,17 @@ __global__ void __launch_bounds__(TPB) k_grad_nu(LevelDev<double> L, const doubl
         }
     }
     const double tot = block_sum256(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0 && tl.nat >= 0) partials[tl.nat] = tot;
 }
 
-// per-macro reduction of the gradient partials (one block per macro)
-__global__ void k_grad_reduce(const Tile* __restrict__ tiles, int ntiles,
-                              const double* __restrict__ partials, double* __restrict__ out) {
+// Per-macro reduction of the gradient partials (one block per macro).  In
+// natural order the closure tiles of macro m are a contiguous range.
+__global__ void k_grad_reduce(const int* __restrict__ macro_tile0, const double* __restrict__ partials,
+                              double* __restrict__ out) {
     __shared__ double sh[4];
     const int m = blockIdx.x;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < ntiles; b += TPB)
-        if (tiles[b].macro == m) acc += partials[b];
+    for (int b = macro_tile0[m] + threadIdx.x; b < macro_tile0[m + 1]; b += TPB) acc += partials[b];
     const double tot = block_sum256(acc, sh);
     if (threadIdx.x == 0) out[m] = -tot;
 }
@@ -603,11 +609,13 @@ __global__ void k_axpy_cast(double* __restrict__ x, const double* __restrict__ s
 // weighted pressure sum sum_i m_i p_i over unique vertices (block partials)
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __restrict__ p,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, int ib) {
     __shared__ double sh[4];
     double acc = 0.0;
-    if ((int)blockIdx.x < L.n_vtiles) {
-        const Tile tl = L.vtiles[blockIdx.x];
+    int slot = -1;
+    if ((int)blockIdx.x >= ib) {
+        const Tile tl = L.vtiles[blockIdx.x - ib];
+        slot = tl.nat;
         if (tl.macro >= 0) {
             const int n = L.n, k = tl.k, mm = n - k;
             const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
@@ -625,12 +633,13 @@ __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __rest
             }
         }
     } else {
-        const int t = ((int)blockIdx.x - L.n_vtiles) * TPB + (int)threadIdx.x;
+        if ((int)blockIdx.x * TPB < L.nif) slot = L.nv_nat + (int)blockIdx.x;
+        const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif)
             acc = (double)L.st[(size_t)L.if_sid[t] * ST_SIZE + ST_MASS] * (double)p[L.if_self[t]];
     }
     const double tot = block_sum256(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    if (threadIdx.x == 0 && slot >= 0) partials[slot] = tot;
 }
 
 // p -= mean, mean = (sum_i m_i p_i) / (sum_i m_i) from a device scalar
@@ -687,6 +696,8 @@ struct CoarseDev {
     const double* val;
     const double* ainv;     // symmetric [nfv][nfv]
     const double* pdinv;    // [N]
+    const double* sinv;     // [N][N] symmetric, used when schur != 0
+    int schur;
     const double* mass;     // [N]
     const int* vel_node;    // [nfv]
     const int* node_vidx;   // [N] compact velocity index or -1
@@ -719,6 +730,12 @@ __device__ void coarse_precond(const CoarseDev& cd, const double* __restrict__ v
             const double* vv = v + c * nfv;
             double acc = 0.0;
             for (int q = 0; q < nfv; ++q) acc += cd.ainv[(size_t)q * nfv + r] * vv[q];
+            z[i] = acc;
+        } else if (cd.schur) {
+            const int r = i - 3 * nfv;
+            const double* vp = v + 3 * nfv;
+            double acc = 0.0;
+            for (int q = 0; q < cd.N; ++q) acc += cd.sinv[(size_t)q * cd.N + r] * vp[q];
             z[i] = acc;
         } else {
             z[i] = cd.pdinv[i - 3 * nfv] * v[i];

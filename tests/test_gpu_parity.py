@@ -122,15 +122,17 @@ def test_uzawa_step_matches_oracle(cid, R):
         assert _relerr(_host(s.gather(xd, l)), xo) < 1e-12, l
 
 
-@pytest.mark.parametrize("cid", [1, 4, 5])
-def test_coarse_solve_matches_dense(cid):
-    cfg, s, umg = _setup(cid, 3)
+@pytest.mark.parametrize("cid,prec", [(1, 0), (4, 0), (5, 0), (1, 1), (5, 1)])
+def test_coarse_solve_matches_dense(cid, prec):
+    """Both pressure preconditioners (exact Schur complement, lumped mass)."""
+    cfg, s, umg = _setup(cid, 3, coarse_prec=prec)
     lv = umg.H.levels[0]
     x = _rand_state(lv, 80)
     b = umg.apply(0, x)                  # compatible right-hand side
     xg, it, rel = s.coarse_solve(s.scatter(_dev(b), 0))
     xo = umg.coarse_solve(b)
     assert it < 500 and rel < 1e-13
+    print(f"coarse PMINRES: {it} iterations, preconditioned residual {rel:.1e}")
     assert _relerr(_host(s.gather(xg, 0)), xo) < 1e-11
 
 
