@@ -91,9 +91,9 @@ typedef struct {
                              2 reversed (a schedule permutation used to test that
                              results do not depend on workgroup order) */
     int32_t coarse_prec;  /* pressure block of the coarse MINRES preconditioner:
-                             0 exact Schur complement B A^-1 B^T + C (dense,
-                             default), 1 lumped mass weighted by 1/nu (the
-                             paper's choice, more iterations) */
+                             0 exact Schur complement B A^-1 B^T + C (dense;
+                             fewer iterations, each dearer), 1 lumped mass
+                             weighted by 1/nu (the paper's choice, default) */
 } hhg_opts;
 
 /* Result of hhg_solve. */

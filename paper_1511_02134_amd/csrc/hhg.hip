@@ -2,6 +2,7 @@
 // device upload and the multigrid driver (Sections 3.3 - 3.7).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -218,7 +219,7 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.node_slot = cv.take<int32_t>(C.N);
     d.node_cptr = cv.take<int32_t>(C.node_cptr.size());
     d.node_copy = cv.take<int32_t>(C.node_copy.size());
-    d.gscratch = cv.take<double>((size_t)9 * C.nd);
+    d.gscratch = cv.take<double>((size_t)8 * C.nd);
     return cv.off + 256;
 }
 
@@ -351,9 +352,40 @@ hhg_status upload_all(hhg_ctx* c) {
     d.tol = c->opts.coarse_rtol;
     d.project = c->mi.project ? 1 : 0;
     d.schur = c->opts.coarse_prec == 0 ? 1 : 0;
-    c->coarse_smem = (size_t)9 * C.nd * sizeof(double);
-    d.use_lds = c->coarse_smem <= 60 * 1024 ? 1 : 0;
-    if (!d.use_lds) c->coarse_smem = 0;
+    // dynamic LDS of the coarse kernel: vectors, then the CSR matrix, A^-1
+    // and S^-1, each only if it still fits into the device's per-workgroup LDS
+    {
+        int dev = 0, maxlds = 65536;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                    hipSuccess && v > 0)
+                maxlds = v;
+        }
+        const size_t budget = (size_t)maxlds - 1024;   // static LDS of the kernel
+        d.nnz = (int)C.val.size();
+        size_t used = 0;
+        const size_t vb = (size_t)8 * C.nd * sizeof(double);
+        const size_t cb = ((size_t)d.nnz + ((size_t)d.nnz + C.nd + 2) / 2) * sizeof(double);
+        const size_t ab = (size_t)C.nfv * C.nfv * sizeof(double);
+        const size_t sbytes = (size_t)C.N * C.N * sizeof(double);
+        d.vec_lds = used + vb <= budget;
+        if (d.vec_lds) used += vb;
+        d.csr_lds = used + cb <= budget;
+        if (d.csr_lds) used += cb;
+        d.ainv_lds = used + ab <= budget;
+        if (d.ainv_lds) used += ab;
+        d.sinv_lds = d.schur && used + sbytes <= budget;
+        if (d.sinv_lds) used += sbytes;
+        c->coarse_smem = used;
+        if (used > 65536) {
+            if (hipFuncSetAttribute((const void*)k_coarse<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)used) != hipSuccess ||
+                hipFuncSetAttribute((const void*)k_coarse<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)used) != hipSuccess)
+                return fail(c, HHG_EDEVICE, "cannot raise the LDS limit of the coarse kernel");
+        }
+    }
     if ((s = upload_stencils(c)) != HHG_OK) return s;
     // algorithmic bytes of the timed kernel classes on the finest level
     HostLevel& h = c->H[c->L];
@@ -592,7 +624,7 @@ void hhg_default_opts(hhg_opts* o) {
     o->coarse_rtol = 1e-14;
     o->coarse_maxit = 500;
     o->block_order = 1;
-    o->coarse_prec = 0;
+    o->coarse_prec = 1;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }

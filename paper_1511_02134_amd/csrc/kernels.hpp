@@ -691,6 +691,7 @@ __global__ void k_exchange(LevelDev<T> L, int nfields, T* __restrict__ x) {
 struct CoarseDev {
     int nd, nfv, N, maxit, project;
     double tol, inv_mass;
+    int nnz;
     const int* rowptr;
     const int* col;
     const double* val;
@@ -704,8 +705,10 @@ struct CoarseDev {
     const int* node_slot;   // [N]
     const int* node_cptr;   // [N+1]
     const int* node_copy;
-    double* gscratch;       // 9 * nd doubles when the vectors do not fit in LDS
-    int use_lds;
+    double* gscratch;       // 8 * nd doubles when the vectors do not fit in LDS
+    // what lives in the dynamic LDS (in this order): vectors, CSR (val, then
+    // col and row pointers), A^-1, S^-1
+    int vec_lds, csr_lds, ainv_lds, sinv_lds;
 };
 
 constexpr int CTPB = 1024;
@@ -721,26 +724,60 @@ __device__ __forceinline__ double csum(double v, double* red) {
     return t;
 }
 
-__device__ void coarse_precond(const CoarseDev& cd, const double* __restrict__ v,
-                               double* __restrict__ z) {
+// Products of the coarse solve: every row is handled by a segment of SEG
+// consecutive lanes that split its entries and combine them with shuffles,
+// so that all 1024 threads work and the dependent load chains stay short.
+constexpr int SEG = 8;
+
+__device__ __forceinline__ double seg_sum(double v) {
+#pragma unroll
+    for (int o = SEG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SEG);
+    return v;
+}
+
+// y_c = M x_c for nb right-hand sides of a dense symmetric M [n][n] stored
+// row-major (row r is contiguous)
+__device__ __forceinline__ void seg_gemv(const double* __restrict__ M, int n, int nb,
+                                         const double* __restrict__ x, double* __restrict__ y) {
+    const int sl = threadIdx.x % SEG, g = threadIdx.x / SEG, ng = blockDim.x / SEG;
+    for (int rr = g; rr < n * nb; rr += ng) {
+        const int c = rr / n, r = rr - c * n;
+        const double* xc = x + c * n;
+        double acc = 0.0;
+        for (int q = sl; q < n; q += SEG) acc += M[(size_t)r * n + q] * xc[q];
+        acc = seg_sum(acc);
+        if (sl == 0) y[rr] = acc;
+    }
+}
+
+__device__ void coarse_precond(const CoarseDev& cd, const double* ainv, const double* sinv,
+                               const double* __restrict__ v, double* __restrict__ z) {
     const int nfv = cd.nfv;
-    for (int i = threadIdx.x; i < cd.nd; i += blockDim.x) {
-        if (i < 3 * nfv) {
-            const int c = i / nfv, r = i - c * nfv;
-            const double* vv = v + c * nfv;
-            double acc = 0.0;
-            for (int q = 0; q < nfv; ++q) acc += cd.ainv[(size_t)q * nfv + r] * vv[q];
-            z[i] = acc;
-        } else if (cd.schur) {
-            const int r = i - 3 * nfv;
-            const double* vp = v + 3 * nfv;
-            double acc = 0.0;
-            for (int q = 0; q < cd.N; ++q) acc += cd.sinv[(size_t)q * cd.N + r] * vp[q];
-            z[i] = acc;
-        } else {
-            z[i] = cd.pdinv[i - 3 * nfv] * v[i];
+    seg_gemv(ainv, nfv, 3, v, z);    // the three velocity components at once
+    if (cd.schur) {
+        seg_gemv(sinv, cd.N, 1, v + 3 * nfv, z + 3 * nfv);
+    } else {
+        for (int i = threadIdx.x; i < cd.N; i += blockDim.x) z[3 * nfv + i] = cd.pdinv[i] * v[3 * nfv + i];
+    }
+}
+
+// q = K z s (CSR, z scaled by s on the fly); returns this thread's share of
+// (z s) . q
+__device__ __forceinline__ double coarse_matvec(const CoarseDev& cd, const int* rowptr, const int* col,
+                                                const double* val, const double* __restrict__ z,
+                                                double sc, double* __restrict__ q) {
+    const int sl = threadIdx.x % SEG, g = threadIdx.x / SEG, ng = blockDim.x / SEG;
+    double part = 0.0;
+    for (int i = g; i < cd.nd; i += ng) {
+        double acc = 0.0;
+        for (int e = rowptr[i] + sl; e < rowptr[i + 1]; e += SEG) acc += val[e] * z[col[e]];
+        acc = seg_sum(acc) * sc;
+        if (sl == 0) {
+            q[i] = acc;
+            part += acc * z[i] * sc;
         }
     }
+    return part;
 }
 
 template <typename T>
@@ -750,7 +787,39 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
     extern __shared__ double smem[];
     __shared__ double red[16];
     const int nd = cd.nd, nfv = cd.nfv, N = cd.N;
-    double* base = cd.use_lds ? smem : cd.gscratch;
+    // carve the dynamic LDS
+    double* lds = smem;
+    double* base = cd.vec_lds ? lds : cd.gscratch;
+    if (cd.vec_lds) lds += 8 * nd;
+    const double* val = cd.val;
+    const int* col = cd.col;
+    const int* rowptr = cd.rowptr;
+    if (cd.csr_lds) {
+        double* v_ = lds;
+        int* c_ = reinterpret_cast<int*>(v_ + cd.nnz);
+        int* r_ = c_ + cd.nnz;
+        for (int e = threadIdx.x; e < cd.nnz; e += blockDim.x) {
+            v_[e] = cd.val[e];
+            c_[e] = cd.col[e];
+        }
+        for (int i = threadIdx.x; i <= nd; i += blockDim.x) r_[i] = cd.rowptr[i];
+        val = v_;
+        col = c_;
+        rowptr = r_;
+        lds += cd.nnz + (cd.nnz + nd + 2) / 2;
+    }
+    const double* ainv = cd.ainv;
+    if (cd.ainv_lds) {
+        for (int e = threadIdx.x; e < nfv * nfv; e += blockDim.x) lds[e] = cd.ainv[e];
+        ainv = lds;
+        lds += (size_t)nfv * nfv;
+    }
+    const double* sinv = cd.sinv;
+    if (cd.sinv_lds) {
+        for (int e = threadIdx.x; e < N * N; e += blockDim.x) lds[e] = cd.sinv[e];
+        sinv = lds;
+        lds += (size_t)N * N;
+    }
     double* vo = base;
     double* v = vo + nd;
     double* z = v + nd;
@@ -787,7 +856,7 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
         __syncthreads();
         part = 0.0;
     }
-    coarse_precond(cd, v, z);
+    coarse_precond(cd, ainv, sinv, v, z);
     __syncthreads();
     for (int i = threadIdx.x; i < nd; i += blockDim.x) part += z[i] * v[i];
     double gamma = sqrt(fmax(csum(part, red), 0.0));
@@ -798,21 +867,16 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
     double rel = 0.0;
     if (gamma1 > 0.0) {
         for (it = 1; it <= cd.maxit; ++it) {
+            // z <- z / gamma is folded into the product; the scaled z is
+            // stored for the direction update below
             const double ig = 1.0 / gamma;
-            for (int i = threadIdx.x; i < nd; i += blockDim.x) z[i] *= ig;
-            __syncthreads();
-            part = 0.0;
-            for (int i = threadIdx.x; i < nd; i += blockDim.x) {
-                double acc = 0.0;
-                for (int e = cd.rowptr[i]; e < cd.rowptr[i + 1]; ++e) acc += cd.val[e] * z[cd.col[e]];
-                q[i] = acc;
-                part += acc * z[i];
-            }
+            part = coarse_matvec(cd, rowptr, col, val, z, ig, q);
             const double delta = csum(part, red);
+            for (int i = threadIdx.x; i < nd; i += blockDim.x) z[i] *= ig;
             const double a = delta / gamma, bq = gamma / gamma_old;
             for (int i = threadIdx.x; i < nd; i += blockDim.x) q[i] = q[i] - a * v[i] - bq * vo[i];
             __syncthreads();
-            coarse_precond(cd, q, zn);
+            coarse_precond(cd, ainv, sinv, q, zn);
             __syncthreads();
             part = 0.0;
             for (int i = threadIdx.x; i < nd; i += blockDim.x) part += zn[i] * q[i];
@@ -861,12 +925,12 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
     }
     for (int vtx = threadIdx.x; vtx < N; vtx += blockDim.x) {
         const int iv = cd.node_vidx[vtx];
-        T val[4];
-        for (int c = 0; c < 3; ++c) val[c] = iv >= 0 ? (T)xs[c * nfv + iv] : T(0);
-        val[3] = (T)xs[3 * nfv + vtx];
+        T val4[4];
+        for (int c = 0; c < 3; ++c) val4[c] = iv >= 0 ? (T)xs[c * nfv + iv] : T(0);
+        val4[3] = (T)xs[3 * nfv + vtx];
         for (int e = cd.node_cptr[vtx]; e < cd.node_cptr[vtx + 1]; ++e) {
-            const int s = cd.node_copy[e];
-            for (int c = 0; c < 4; ++c) x[c * xlen + s] = val[c];
+            const int sl = cd.node_copy[e];
+            for (int c = 0; c < 4; ++c) x[c * xlen + sl] = val4[c];
         }
     }
     if (threadIdx.x == 0 && stats) {
