@@ -94,6 +94,11 @@ typedef struct {
                              0 exact Schur complement B A^-1 B^T + C (dense;
                              fewer iterations, each dearer), 1 lumped mass
                              weighted by 1/nu (the paper's choice, default) */
+    int32_t coarse_solver; /* 0: exact, x0 = Z b0 with Z the inverse of the level-0
+                              system bordered by the mass-weighted mean constraint
+                              (computed once at set-up; one matrix-vector product
+                              per solve; default, at most 8192 level-0 unknowns);
+                              1: the block-diagonal preconditioned MINRES above */
 } hhg_opts;
 
 /* Result of hhg_solve. */
@@ -189,12 +194,16 @@ hhg_status hhg_restrict(hhg_ctx* ctx, int32_t level, const void* d_r_fine, void*
                         hhg_stream stream);
 hhg_status hhg_prolong_add(hhg_ctx* ctx, int32_t level, const void* d_e_coarse,
                            void* d_x_fine, hhg_stream stream);
-/* Level-0 solve (Section 3.7): block-diagonal preconditioned MINRES on the
- * whole coarse Stokes system, preconditioner diag(A_0^-1, S_0^-1) with S_0 the
- * exact Schur complement or the lumped 1/nu-weighted mass (opts.coarse_prec),
- * run to opts.coarse_rtol, pressure projected to zero mean when the
- * pressure has a null space.  x0 = K_0^-1 b0.  iters / relres (host, may be
- * NULL) synchronise the stream. */
+/* Level-0 solve (Section 3.7), x0 = K_0^-1 b0 with the pressure of zero mean
+ * when it has a null space (b0 is first made consistent by removing its
+ * component along the constant pressure, the Lagrange multiplier of the mean
+ * constraint).  opts.coarse_solver 0: one product with the precomputed
+ * inverse of the bordered system (exact up to rounding; iters = 1,
+ * relres = 0).  1: block-diagonal preconditioned MINRES on the whole coarse
+ * Stokes system, preconditioner diag(A_0^-1, S_0^-1) with S_0 the exact Schur
+ * complement or the lumped 1/nu-weighted mass (opts.coarse_prec), run to
+ * opts.coarse_rtol, then projected to zero mean.  iters / relres (host, may
+ * be NULL) synchronise the stream. */
 hhg_status hhg_coarse_solve(hhg_ctx* ctx, const void* d_b0, void* d_x0, int32_t* iters,
                             double* relres, hhg_stream stream);
 /* Pressure projection to zero mean, p -= (sum m_i p_i)/(sum m_i) with

@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
                 ("p_sweep", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32),
-                ("coarse_prec", ctypes.c_int32)]
+                ("coarse_prec", ctypes.c_int32), ("coarse_solver", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -83,6 +83,7 @@ struct hhg_ctx {
     // algorithmic bytes per launch (finest level) of the timed classes
     double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
     double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
+    double bytes_ru_fused[4] = {0, 0, 0, 0}, bytes_bp_fused[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -115,7 +116,7 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
         return false;
     }
     if (!(o->coarse_rtol > 0.0) || o->coarse_maxit < 1 || o->coarse_maxit > 100000 ||
-        o->coarse_prec < 0 || o->coarse_prec > 1) {
+        o->coarse_prec < 0 || o->coarse_prec > 1 || o->coarse_solver < 0 || o->coarse_solver > 1) {
         *err = "invalid coarse solver settings";
         return false;
     }
@@ -145,7 +146,8 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
         for (int32_t t : c->H[l].rif_fine)
             if (t < 0) return fail(c, HHG_EINVAL, "internal error: coarse interface vertex missing");
     }
-    if (!build_coarse(c->mi, c->H[0], &c->CH, &err)) return fail(c, HHG_EINVAL, err);
+    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, &c->CH, &err))
+        return fail(c, HHG_EINVAL, err);
     if (c->CH.nd > 4096) return fail(c, HHG_EINVAL, "coarse system larger than 4096 unknowns");
     return HHG_OK;
 }
@@ -193,7 +195,7 @@ size_t layout(hhg_ctx* c, char* ws) {
             a.r32 = cv.take<float>(v4);
             a.t32 = cv.take<float>(v4);
         }
-        const int nb = (int)h.vtiles.size() + iface_blocks(h.nif);
+        const int nb = full_blocks((int)h.vtiles.size()) + iface_blocks(h.nif);
         maxblocks = std::max(maxblocks, nb);
         maxblocks = std::max(maxblocks, (int)h.ctiles.size());
     }
@@ -220,6 +222,7 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.node_cptr = cv.take<int32_t>(C.node_cptr.size());
     d.node_copy = cv.take<int32_t>(C.node_copy.size());
     d.gscratch = cv.take<double>((size_t)8 * C.nd);
+    d.zinv = cv.take<double>(std::max<size_t>(1, C.zinv.size()));
     return cv.off + 256;
 }
 
@@ -295,6 +298,8 @@ hhg_status upload_stencils(hhg_ctx* c) {
     if ((s = upload<double>(c, (double*)c->cd.pdinv, C.pdinv.data(), C.pdinv.size())) != HHG_OK)
         return s;
     if ((s = upload<double>(c, (double*)c->cd.sinv, C.sinv.data(), C.sinv.size())) != HHG_OK)
+        return s;
+    if ((s = upload<double>(c, (double*)c->cd.zinv, C.zinv.data(), C.zinv.size())) != HHG_OK)
         return s;
     if ((s = upload<double>(c, (double*)c->cd.mass, C.mass.data(), C.mass.size())) != HHG_OK)
         return s;
@@ -409,6 +414,13 @@ hhg_status upload_all(hhg_ctx* c) {
     }
     c->bytes_ru = vs * (Nall + 6.0 * Nf);
     c->bytes_bp = vs * (3.0 * Nall + 2.0 * Nall);
+    for (int col = 0; col < 4; ++col) {
+        const double nbr = Nc[(col + 1) & 3] + Nc[(col + 3) & 3];
+        // + the colour's sweep: neighbours read, the colour written (its
+        // right-hand side stays in registers)
+        c->bytes_ru_fused[col] = c->bytes_ru + vs * 3.0 * (nbr + Nfc[col]);
+        c->bytes_bp_fused[col] = c->bytes_bp + vs * (nbr + 2.0 * Nc[col]);
+    }
     c->bytes_res = vs * (4.0 * Nall + 2.0 * (3.0 * Nf + Nall));
     return HHG_OK;
 }
@@ -481,16 +493,36 @@ void vecs<float>(hhg_ctx* c, int l, float** x, float** b, float** r, float** t) 
     *t = a.t32;
 }
 
+// volume blocks of a full pass in the given mode
+inline int full_vblocks(int mode, int n_vtiles) {
+    return quad_lanes(mode) ? n_vtiles : full_blocks(n_vtiles);
+}
+
 template <typename T, int MODE>
 void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int ib = iface_blocks(v.nif);
-    const int grid = ib + v.n_vtiles;
+    const int grid = ib + full_vblocks(MODE, v.n_vtiles);
     const bool finest = l == c->L;
     double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
     Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
              bytes);
-    hipLaunchKernelGGL((k_full<T, MODE>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials, ib);
+    hipLaunchKernelGGL((k_full<T, MODE, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials,
+                       ib, (T*)nullptr, -1, T(0));
+}
+
+// RU with the velocity sweep of colour col, or BP with the pressure sweep of
+// colour col, in one launch (x is updated in place, t receives the pass)
+template <typename T, int MODE>
+void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + full_blocks(v.n_vtiles);
+    const bool finest = l == c->L;
+    const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
+    Timed tm(c, HHG_K_APPLY, s, finest, bytes);
+    hipLaunchKernelGGL((k_full<T, MODE, true>), dim3(grid), dim3(TPB), 0, s, v, (const T*)x, b, t,
+                       c->partials, ib, x, col, (T)c->opts.omega);
 }
 
 template <typename T>
@@ -513,13 +545,15 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
 // one inexact Uzawa step (eq. Uzawa_smooth) in place
 template <typename T>
 void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
-    full_pass<T, MODE_RU>(c, l, x, b, t, s);
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
-    // colour 3 right after the first would recompute identical values)
-    static const int vorder[7] = {0, 1, 2, 3, 2, 1, 0};
-    for (int q = 0; q < 7; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
-    full_pass<T, MODE_BP>(c, l, x, b, t, s);
-    for (int col = 0; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
+    // colour 3 right after the first would recompute identical values); the
+    // first sweep runs inside the pass that forms f - B^T p
+    full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
+    static const int vorder[6] = {1, 2, 3, 2, 1, 0};
+    for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
+    // forward pressure sweep; colour 0 inside the pass that forms B u - g
+    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
+    for (int col = 1; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
     if (c->opts.p_sweep == 1)
         for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, false, x, t, s);
 }
@@ -533,11 +567,11 @@ template <typename T>
 void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int ib = iface_blocks(v.nif);
-    const int grid = ib + v.n_vtiles;
+    const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
     {
         Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
-        hipLaunchKernelGGL((k_full<T, MODE_RES>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
-                           c->partials, ib);
+        hipLaunchKernelGGL((k_full<T, MODE_RES, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
+                           c->partials, ib, (T*)nullptr, -1, T(0));
     }
     hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
                        v.nv_nat + (v.nif + TPB - 1) / TPB, out, 1);
@@ -548,7 +582,7 @@ void restrict_to(hhg_ctx* c, int l, const T* rf, T* bc, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
     const int ib = iface_blocks(C.nif);
-    const int grid = ib + C.n_vtiles;
+    const int grid = ib + full_blocks(C.n_vtiles);
     hipLaunchKernelGGL(k_restrict<T>, dim3(grid), dim3(TPB), 0, s, C, F, rf, bc, ib);
 }
 
@@ -556,12 +590,19 @@ template <typename T>
 void prolong_add(hhg_ctx* c, int l, const T* ec, T* xf, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
-    hipLaunchKernelGGL(k_prolong<T>, dim3(F.n_ctiles), dim3(TPB), 0, s, F, C, ec, xf);
+    hipLaunchKernelGGL(k_prolong<T>, dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s, F, C, ec, xf);
 }
 
 template <typename T>
 void coarse_solve(hhg_ctx* c, const T* b, T* x, hipStream_t s) {
     const size_t len = (size_t)c->H[0].len;
+    if (c->opts.coarse_solver == 0) {
+        const int rows = (c->cd.nd + TPB / 64 - 1) / (TPB / 64);
+        const int grid = std::max(rows, (c->cd.N + TPB - 1) / TPB);
+        hipLaunchKernelGGL(k_coarse_direct<T>, dim3(grid), dim3(TPB), c->cd.nd * sizeof(double), s,
+                           c->cd, b, len, x, len, c->scal + 8);
+        return;
+    }
     hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(CTPB), c->coarse_smem, s, c->cd, b, len, x, len,
                        c->scal + 8);
 }
@@ -625,6 +666,7 @@ void hhg_default_opts(hhg_opts* o) {
     o->coarse_maxit = 500;
     o->block_order = 1;
     o->coarse_prec = 1;
+    o->coarse_solver = 0;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }
@@ -1025,7 +1067,8 @@ hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
     std::string err;
     for (int l = 0; l <= c->L; ++l)
         if (!compute_stencils(c->mi, &c->H[l], &err)) return fail(c, HHG_EINVAL, err);
-    if (!build_coarse(c->mi, c->H[0], &c->CH, &err)) return fail(c, HHG_EINVAL, err);
+    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, &c->CH, &err))
+        return fail(c, HHG_EINVAL, err);
     if (!c->device) return HHG_OK;
     hhg_status st = upload_stencils(c);
     if (st != HHG_OK) return st;
@@ -1114,6 +1157,32 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
             for (int j = 1; j <= n - k - 2; ++j)
                 for (int i = 1; i <= n - k - 1 - j; ++i)
                     CK(seen[local_slot(h, m, i, j, k)] == 1, "interior vertex not covered");
+    // full-pass blocks: each real tile once per sub-row, on the tile's XCD,
+    // partial slots 4 nat + r distinct and below the reduction count (the
+    // prolongation maps its closure tiles the same way)
+    for (const std::vector<Tile>* tv : {&h.vtiles, &h.ctiles}) {
+        const std::vector<Tile>& tiles = *tv;
+        const int lead = tv == &h.vtiles ? iface_blocks(h.nif) : 0;
+        const int nvt = (int)tiles.size(), nfb = full_blocks(nvt);
+        std::vector<uint8_t> hit((size_t)nvt * 4, 0);
+        int nat_real = 0;
+        for (const Tile& t : tiles) nat_real += t.macro >= 0 ? 1 : 0;
+        std::vector<uint8_t> pslot((size_t)4 * nat_real, 0);
+        for (int v = 0; v < nfb; ++v) {
+            const int ti = full_tile(v), r = full_sub(v);
+            if (ti >= nvt) continue;
+            CK(((lead + v) & 7) == (ti & 7) || c->opts.block_order != 1,
+               "full-pass block off its tile's XCD");
+            CK(hit[(size_t)ti * 4 + r] == 0, "full-pass tile/sub-row visited twice");
+            hit[(size_t)ti * 4 + r] = 1;
+            const Tile& t = tiles[ti];
+            if (t.macro < 0) continue;
+            CK(t.nat >= 0 && t.nat < nat_real, "tile natural index out of range");
+            CK(pslot[(size_t)4 * t.nat + r] == 0, "partial slot used twice");
+            pslot[(size_t)4 * t.nat + r] = 1;
+        }
+        for (size_t q = 0; q < hit.size(); ++q) CK(hit[q] == 1, "full-pass tile/sub-row not covered");
+    }
     // closure tiles: every closure vertex exactly once; grad taps; prolongation
     std::fill(seen.begin(), seen.end(), 0);
     for (const Tile& t : h.ctiles) {
@@ -1231,7 +1300,7 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
         }
     }
     // grids fit the reduction buffers
-    CK((int)h.vtiles.size() + (h.nif + TPB - 1) / TPB <= c->npartials, "partials too small");
+    CK(full_blocks((int)h.vtiles.size()) + (h.nif + TPB - 1) / TPB <= c->npartials, "partials too small");
     CK((int)h.ctiles.size() <= c->npartials, "gradient partials too small");
     return true;
 }

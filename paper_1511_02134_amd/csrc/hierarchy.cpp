@@ -494,6 +494,7 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
     std::sort(nodes.begin(), nodes.end(), [](const Node& a, const Node& b) {
         if (a.colour != b.colour) return a.colour < b.colour;
         if (a.flag != b.flag) return a.flag < b.flag;
+        if (a.sid != b.sid) return a.sid < b.sid;   // wave-uniform stencil records
         return a.self < b.self;
     });
     const int nif = (int)nodes.size();
@@ -640,7 +641,45 @@ void link_levels(HostLevel* coarse, const HostLevel& fine) {
 }
 
 // ---------------------------------------------------------------------------
-bool build_coarse(const MeshInfo& mi, const HostLevel& L, CoarseHost* out, std::string* err) {
+// Inverse of a dense n x n matrix by Gauss-Jordan elimination with partial
+// pivoting (row-major, in place); false if it is numerically singular.
+static bool invert_dense(std::vector<double>& M, int n) {
+    std::vector<int> perm(n);
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    double scale = 0.0;
+    for (double v : M) scale = std::max(scale, std::fabs(v));
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(M[(size_t)r * n + c]) > std::fabs(M[(size_t)piv * n + c])) piv = r;
+        if (!(std::fabs(M[(size_t)piv * n + c]) > 1e-13 * scale)) return false;
+        if (piv != c) {
+            for (int q = 0; q < n; ++q) std::swap(M[(size_t)piv * n + q], M[(size_t)c * n + q]);
+            std::swap(perm[piv], perm[c]);
+        }
+        double* rc = &M[(size_t)c * n];
+        const double inv = 1.0 / rc[c];
+        rc[c] = 1.0;
+        for (int q = 0; q < n; ++q) rc[q] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double* rr = &M[(size_t)r * n];
+            const double f = rr[c];
+            if (f == 0.0) continue;
+            rr[c] = 0.0;
+            for (int q = 0; q < n; ++q) rr[q] -= f * rc[q];
+        }
+    }
+    // the row swaps act on the columns of the inverse: undo them
+    std::vector<double> out((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) out[(size_t)r * n + perm[c]] = M[(size_t)r * n + c];
+    M.swap(out);
+    return true;
+}
+
+bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, CoarseHost* out,
+                  std::string* err) {
     CoarseHost& C = *out;
     const int N = (int)L.N;
     C.N = N;
@@ -815,6 +854,36 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, CoarseHost* out, std::
                 C.sinv[(size_t)i * N + c] = sacc / Lf[(size_t)i * N + i];
             }
         }
+    }
+    // direct solver: the inverse of K_0 bordered by the constraint
+    // sum_i m_i p_i = 0 (only when the pressure has a null space); its leading
+    // nd x nd block maps any right-hand side to the mean-zero solution of the
+    // consistent part of it
+    C.zinv.clear();
+    if (direct) {
+        const int nd = C.nd;
+        if (nd > COARSE_DIRECT_MAX) {
+            *err = "level-0 system too large for the direct coarse solver (" + std::to_string(nd) +
+                   " unknowns); use the MINRES coarse solver";
+            return false;
+        }
+        const int nb = nd + (mi.project ? 1 : 0);
+        std::vector<double> K((size_t)nb * nb, 0.0);
+        for (int r = 0; r < nd; ++r)
+            for (int e = C.rowptr[r]; e < C.rowptr[r + 1]; ++e) K[(size_t)r * nb + C.col[e]] += C.val[e];
+        if (mi.project)
+            for (int v = 0; v < N; ++v) {
+                const double m = rec_of(v)[ST_MASS];
+                K[(size_t)(3 * nfv + v) * nb + nd] = m;
+                K[(size_t)nd * nb + 3 * nfv + v] = m;
+            }
+        if (!invert_dense(K, nb)) {
+            *err = "level-0 system is singular";
+            return false;
+        }
+        C.zinv.resize((size_t)nd * nd);
+        for (int r = 0; r < nd; ++r)
+            for (int q = 0; q < nd; ++q) C.zinv[(size_t)r * nd + q] = K[(size_t)r * nb + q];
     }
     C.pdinv.resize(N);
     C.mass.resize(N);

@@ -87,11 +87,15 @@ struct CoarseHost {
     std::vector<double> sinv;       // [N][N] inverse of the Schur complement
                                     // B A^-1 B^T + C (+ a rank-one term on the
                                     // pressure null space), symmetric
+    std::vector<double> zinv;       // [nd][nd] solution operator of the level-0
+                                    // system with the mean constraint (direct solver)
     std::vector<double> mass;       // [N] int phi_i
     std::vector<int32_t> vel_node;  // [nfv] lattice node of compact velocity vertex
     std::vector<int32_t> node_slot; // [N]
     std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
 };
-bool build_coarse(const MeshInfo& mi, const HostLevel& L0, CoarseHost* out, std::string* err);
+constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns of the direct solver
+bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, CoarseHost* out,
+                  std::string* err);
 
 }  // namespace hhg

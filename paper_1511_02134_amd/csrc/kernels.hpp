@@ -74,6 +74,13 @@ __host__ __device__ __forceinline__ void nbr_slots(const Rows& R, int i, int s[1
     s[14] = at(R.b[4], R.Q[4], i - 1);
 }
 
+// slot of macro-local vertex (i, j, k) in a macro whose array starts at mb
+__host__ __device__ __forceinline__ int slot_of(const int* __restrict__ sb, int n, int mb, int i, int j,
+                                       int k) {
+    const int mm = n - k;
+    return mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j) + (i & 3) * ((mm + 4 - j) >> 2) + (i >> 2);
+}
+
 // the 7 taps of A and C (centre, +-e_a, +-e_b, +-e_c) in local order
 __host__ __device__ __forceinline__ void axis_slots(const Rows& R, int i, int s[7]) {
     s[0] = at(R.b[0], R.Q[0], i);
@@ -136,6 +143,38 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // precomputed with the pressure frozen; three components at once.
 // Pressure: p += omega (bp - (C p)_x) / C_xx with bp = B u - g.
 // ---------------------------------------------------------------------------
+// One interface vertex t of a colour sweep with the stencil record st; the new
+// value goes to every macro copy (the ghost exchange fused into the update).
+template <typename T, bool VEL>
+__device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
+                                             T* __restrict__ x, const T* __restrict__ rhs, T omega) {
+    const size_t len = (size_t)L.len;
+    const int nif = L.nif;
+    const int self = L.if_self[t];
+    int nb[6];
+#pragma unroll
+    for (int g = 0; g < 6; ++g) nb[g] = L.if_nb[g * nif + t];
+    const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+    if (VEL) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T* u = x + f * len;
+            T acc = T(0);
+#pragma unroll
+            for (int g = 0; g < 6; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
+            const T v = (rhs[f * len + self] - acc) * st[ST_INVA];
+            for (int q = c0; q < c1; ++q) u[L.if_copy[q]] = v;
+        }
+    } else {
+        T* p = x + 3 * len;
+        T cp = st[ST_C] * p[self];
+#pragma unroll
+        for (int g = 0; g < 6; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
+        const T v = p[self] + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
+        for (int q = c0; q < c1; ++q) p[L.if_copy[q]] = v;
+    }
+}
+
 template <typename T, bool VEL>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
                                                 const T* __restrict__ rhs, T omega, int ib) {
@@ -178,31 +217,7 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
     if (t >= tend) return;
-    const int nif = L.nif;
-    const int self = L.if_self[t];
-    const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
-    int nb[6];
-#pragma unroll
-    for (int g = 0; g < 6; ++g) nb[g] = L.if_nb[g * nif + t];
-    const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
-    if (VEL) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            T* u = x + f * len;
-            T acc = T(0);
-#pragma unroll
-            for (int g = 0; g < 6; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
-            const T v = (rhs[f * len + self] - acc) * st[ST_INVA];
-            for (int q = c0; q < c1; ++q) u[L.if_copy[q]] = v;
-        }
-    } else {
-        T* p = x + 3 * len;
-        T cp = st[ST_C] * p[self];
-#pragma unroll
-        for (int g = 0; g < 6; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
-        const T v = p[self] + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
-        for (int q = c0; q < c1; ++q) p[L.if_copy[q]] = v;
-    }
+    iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,6 +231,14 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
 //   MODE_GRADF   y_k = M lam_k + GT_k lam_p                (in: lambda)
 // ---------------------------------------------------------------------------
 enum { MODE_APPLY = 0, MODE_RES = 1, MODE_RU = 2, MODE_BP = 3, MODE_RHS = 4, MODE_GRADF = 5 };
+
+// Load from a uniform field base at a 32-bit byte offset: the address is an
+// SGPR base plus one 32-bit VGPR per tap, shared by all fields (slot offsets
+// in bytes stay below 2^32; the host checks it).
+template <typename T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t boff) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
 
 template <typename T, int MODE>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
@@ -268,7 +291,13 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
         return;
     }
     // MODE_APPLY / MODE_RES
+    uint32_t o[15];
+#pragma unroll
+    for (int g = 0; g < 15; ++g) o[g] = (uint32_t)s[g] * (uint32_t)sizeof(T);
     const T* p = x + 3 * len;
+    T pv[15];
+#pragma unroll
+    for (int g = 0; g < 15; ++g) pv[g] = ldo(p, o[g]);
     T bu = T(0);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -276,19 +305,19 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
         T au = T(0), btp = T(0);
 #pragma unroll
         for (int g = 0; g < 15; ++g) {
-            const T uv = u[s[g]];
+            const T uv = ldo(u, o[g]);
             au += st[ST_A + g] * uv;
-            btp += st[ST_BT + 15 * f + g] * p[s[g]];
+            btp += st[ST_BT + 15 * f + g] * pv[g];
             bu += st[ST_B + 15 * f + g] * uv;
         }
         const T ku = au + btp;
-        out[f] = dir ? T(0) : (MODE == MODE_RES ? b[f * len + s[0]] - ku : ku);
+        out[f] = dir ? T(0) : (MODE == MODE_RES ? ldo(b + f * len, o[0]) - ku : ku);
     }
     T cp = T(0);
 #pragma unroll
-    for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * p[s[g]];
+    for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * pv[g];
     const T kp = bu - cp;
-    out[3] = MODE == MODE_RES ? b[3 * len + s[0]] - kp : kp;
+    out[3] = MODE == MODE_RES ? ldo(b + 3 * len, o[0]) - kp : kp;
 }
 
 template <int MODE>
@@ -299,17 +328,95 @@ __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
     if (MODE == MODE_BP) f0 = 3;
 }
 
-template <typename T, int MODE>
+// Volume blocks of a full pass: four per tile, one per sub-row r = i mod 4, so
+// that a lane owns one vertex and every tap of a wave is a unit-stride run.
+// Block v of the volume range takes tile 8 (v / 32) + v % 8 and sub-row
+// (v / 8) % 4: the four blocks of a tile run on the tile's XCD (tiles are
+// dealt to XCDs by index mod 8) and are dispatched close together.
+__host__ __device__ __forceinline__ int full_tile(int v) { return (v >> 5) * 8 + (v & 7); }
+__host__ __device__ __forceinline__ int full_sub(int v) { return (v >> 3) & 3; }
+__host__ __device__ __forceinline__ int full_blocks(int n_vtiles) { return 4 * ((n_vtiles + 7) / 8 * 8); }
+// The passes that read all four fields at every tap (K x, the residual, the
+// right-hand side and the forcing gradient) keep one block per tile and four
+// vertices per lane, evaluated one after another: one vertex per lane would
+// need every tap of all fields in flight at once (over 256 VGPRs).
+__host__ __device__ constexpr bool quad_lanes(int mode) { return mode == 0 || mode == 1 || mode >= 4; }
+
+// Colour-c update fused into a full pass (velocity Gauss-Seidel into the
+// B^T p pass, pressure relaxation into the B u pass): out[] holds the
+// node's freshly computed right-hand side, t the 7 axis taps (centre first).
+// The update reads only colours c -+ 1 (and, for the pressure, the vertex
+// itself) and writes colour c, which no other lane of the launch reads, so it
+// runs alongside the full pass.  Axis coefficients sit at record positions
+// 1, 2, 3, 4, 7, 8 in the local order of volume records and 1..6 in the
+// global direction order of interface records.
+template <typename T, int MODE, bool IFACE>
+__device__ __forceinline__ void fused_update(const T* __restrict__ st, const int* t, const T* x,
+                                             T* xw, size_t len, const T out[4], T omega,
+                                             int ncopy, const int* copies) {
+    constexpr int q5 = IFACE ? 5 : 7, q6 = IFACE ? 6 : 8;
+    if (MODE == MODE_RU) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const T* u = x + f * len;
+            const T v = out[f] - (st[ST_A + 1] * u[t[1]] + st[ST_A + 2] * u[t[2]] +
+                                  st[ST_A + 3] * u[t[3]] + st[ST_A + 4] * u[t[4]] +
+                                  st[ST_A + q5] * u[t[5]] + st[ST_A + q6] * u[t[6]]);
+            const T un = v * st[ST_INVA];
+            if (IFACE)
+                for (int q = 0; q < ncopy; ++q) xw[f * len + copies[q]] = un;
+            else
+                xw[f * len + t[0]] = un;
+        }
+    } else {
+        // the vertex's own pressure is read through xw, the pointer that
+        // writes it: nothing read through x changes during the launch
+        const T* p = x + 3 * len;
+        const T p0 = xw[3 * len + t[0]];
+        const T cp = st[ST_C] * p0 + st[ST_C + 1] * p[t[1]] + st[ST_C + 2] * p[t[2]] +
+                     st[ST_C + 3] * p[t[3]] + st[ST_C + 4] * p[t[4]] + st[ST_C + q5] * p[t[5]] +
+                     st[ST_C + q6] * p[t[6]];
+        const T pn = p0 + omega * (out[3] - cp) * st[ST_INVC];
+        if (IFACE)
+            for (int q = 0; q < ncopy; ++q) xw[3 * len + copies[q]] = pn;
+        else
+            xw[3 * len + t[0]] = pn;
+    }
+}
+
+// Interface vertex t of a full pass with the stencil record st; with FUSE the
+// colour-fc vertices (velocity: those without Dirichlet data) are also updated.
+template <typename T, int MODE, bool FUSE>
+__device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
+                                           const T* x, const T* __restrict__ b, T* xw,
+                                           size_t len, int fcol, T omega, T out[4]) {
+    const int nif = L.nif;
+    int s[15];
+    s[0] = L.if_self[t];
+#pragma unroll
+    for (int g = 1; g < 15; ++g) s[g] = L.if_nb[(g - 1) * nif + t];
+    const bool dir = (L.if_flag[t] & 1) != 0;
+    eval_node<T, MODE>(st, s, dir, x, b, len, out);
+    if (FUSE && t >= L.col_start[fcol] &&
+        t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
+        const int c0 = L.if_cptr[t];
+        fused_update<T, MODE, true>(st, s, x, xw, len, out, omega, L.if_cptr[t + 1] - c0,
+                                    L.if_copy + c0);
+    }
+}
+
+template <typename T, int MODE, bool FUSE>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
-                                              const T* __restrict__ b, T* __restrict__ y,
-                                              double* __restrict__ partials, int ib) {
+                                              const T* __restrict__ b,
+                                              T* __restrict__ y, double* __restrict__ partials,
+                                              int ib, T* xw, int fcol, T omega) {
     __shared__ double sh[4];
     const size_t len = (size_t)L.len;
     int f0, f1;
     mode_fields<MODE>(f0, f1);
     double ss = 0.0;
     int slot = -1;   // partial-sum slot of this block
-    if ((int)blockIdx.x >= ib) {
+    if (quad_lanes(MODE) && (int)blockIdx.x >= ib) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
         slot = tl.nat;
         if (tl.macro >= 0) {
@@ -335,19 +442,42 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 }
             }
         }
+    } else if ((int)blockIdx.x >= ib) {
+        const int v = (int)blockIdx.x - ib;
+        const int ti = full_tile(v), r = full_sub(v);
+        if (ti < L.n_vtiles) {
+            const Tile tl = L.vtiles[ti];
+            if (tl.macro >= 0) {
+                slot = 4 * tl.nat + r;
+                const int n = L.n, k = tl.k, mm = n - k;
+                const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+                const int j = P.j, i = 4 * P.q + r;
+                if (P.ok && i >= 1 && i <= mm - 1 - j) {
+                    Rows R;
+                    make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+                    const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+                    int s[15];
+                    nbr_slots(R, i, s);
+                    T out[4];
+                    eval_node<T, MODE>(st, s, false, x, b, len, out);
+                    for (int f = f0; f < f1; ++f) {
+                        y[f * len + s[0]] = out[f];
+                        if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
+                    }
+                    if (FUSE && ((i + 2 * j + 3 * k) & 3) == fcol) {
+                        const int t[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
+                        fused_update<T, MODE, false>(st, t, x, xw, len, out, omega, 0, nullptr);
+                    }
+                }
+            }
+        }
     } else {
-        if ((int)blockIdx.x * TPB < L.nif) slot = L.nv_nat + (int)blockIdx.x;
+        if ((int)blockIdx.x * TPB < L.nif) slot = (quad_lanes(MODE) ? 1 : 4) * L.nv_nat + (int)blockIdx.x;
         const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif) {
-            const int nif = L.nif;
-            int s[15];
-            s[0] = L.if_self[t];
-#pragma unroll
-            for (int g = 1; g < 15; ++g) s[g] = L.if_nb[(g - 1) * nif + t];
-            const bool dir = (L.if_flag[t] & 1) != 0;
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
             T out[4];
-            eval_node<T, MODE>(st, s, dir, x, b, len, out);
+            iface_full<T, MODE, FUSE>(L, st, t, x, b, xw, len, fcol, omega, out);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int f = f0; f < f1; ++f) {
                 for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
@@ -371,30 +501,28 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
                                                   int ib) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
     if ((int)blockIdx.x >= ib) {
-        const Tile tl = C.vtiles[blockIdx.x - ib];
+        // one coarse vertex per lane, blocks mapped as in the full passes
+        const int v = (int)blockIdx.x - ib;
+        const int ti = full_tile(v), r = full_sub(v);
+        if (ti >= C.n_vtiles) return;
+        const Tile tl = C.vtiles[ti];
         if (tl.macro < 0) return;
         const int n = C.n, k = tl.k, mm = n - k;
         const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
-        if (!P.ok) return;
-        const int j = P.j;
-        Rows RC, RF;
-        make_rows(C.slab_base, n, (int)(tl.macro * C.mstride), j, k, RC);
+        const int j = P.j, i = 4 * P.q + r;
+        if (!P.ok || i < 1 || i > mm - 1 - j) return;
+        Rows RF;
         make_rows(F.slab_base, F.n, (int)(tl.macro * F.mstride), 2 * j, 2 * k, RF);
-#pragma unroll 1
-        for (int r = 0; r < 4; ++r) {
-            const int i = 4 * P.q + r;
-            if (i < 1 || i > mm - 1 - j) continue;
-            int s[15];
-            nbr_slots(RF, 2 * i, s);
-            const int sc = at(RC.b[0], RC.Q[0], i);
+        int s[15];
+        nbr_slots(RF, 2 * i, s);
+        const int sc = slot_of(C.slab_base, n, (int)(tl.macro * C.mstride), i, j, k);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) {
-                const T* v = rf + f * lf;
-                T acc = T(0);
+        for (int f = 0; f < 4; ++f) {
+            const T* vf = rf + f * lf;
+            T acc = T(0);
 #pragma unroll
-                for (int g = 1; g < 15; ++g) acc += v[s[g]];
-                bc[f * lc + sc] = v[s[0]] + T(0.5) * acc;
-            }
+            for (int g = 1; g < 15; ++g) acc += vf[s[g]];
+            bc[f * lc + sc] = vf[s[0]] + T(0.5) * acc;
         }
         return;
     }
@@ -428,11 +556,6 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
 // pattern.  Copies stay identical because every copy averages the same two
 // coarse values.
 // ---------------------------------------------------------------------------
-__host__ __device__ __forceinline__ int slot_of(const int* __restrict__ sb, int n, int mb, int i, int j,
-                                       int k) {
-    const int mm = n - k;
-    return mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j) + (i & 3) * ((mm + 4 - j) >> 2) + (i >> 2);
-}
 
 // local edge direction whose midpoints have the parity pattern pi | pj<<1 | pk<<2
 __host__ __device__ __forceinline__ void parity_dir(int pat, int* di, int* dj, int* dk) {
@@ -451,34 +574,31 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
                                                  const T* __restrict__ ec, T* __restrict__ xf) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
-    const Tile tl = F.ctiles[blockIdx.x];
+    // one fine closure vertex per lane, blocks mapped as in the full passes
+    const int v = (int)blockIdx.x;
+    const int ti = full_tile(v), r = full_sub(v);
+    if (ti >= F.n_ctiles) return;
+    const Tile tl = F.ctiles[ti];
     if (tl.macro < 0) return;
     const int n = F.n, k = tl.k, mm = n - k;
     const LanePos P = decode_lane(tl, n, 0, mm, threadIdx.x);
-    if (!P.ok) return;
-    const int j = P.j;
+    const int j = P.j, i = 4 * P.q + r;
+    if (!P.ok || i > mm - j) return;
     const int mbf = (int)(tl.macro * F.mstride), mbc = (int)(tl.macro * C.mstride);
-    const int b0 = mbf + F.slab_base[k] + R4d(mm + 1) - R4d(mm + 1 - j), Q0 = (mm + 4 - j) >> 2;
-#pragma unroll 1
-    for (int r = 0; r < 4; ++r) {
-        const int i = 4 * P.q + r;
-        if (i > mm - j) continue;
-        const int sf = at(b0, Q0, i);
-        const int pi = i & 1, pj = j & 1, pk = k & 1;
-        if ((pi | pj | pk) == 0) {
-            const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
+    const int sf = slot_of(F.slab_base, n, mbf, i, j, k);
+    const int pi = i & 1, pj = j & 1, pk = k & 1;
+    if ((pi | pj | pk) == 0) {
+        const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
-            for (int f = 0; f < 4; ++f) xf[f * lf + sf] += ec[f * lc + sc];
-            continue;
-        }
-        int di, dj, dk;
-        parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
-        const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
-        const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
-#pragma unroll
-        for (int f = 0; f < 4; ++f)
-            xf[f * lf + sf] += T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+        for (int f = 0; f < 4; ++f) xf[f * lf + sf] += ec[f * lc + sc];
+        return;
     }
+    int di, dj, dk;
+    parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
+    const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
+    const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) xf[f * lf + sf] += T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -706,6 +826,7 @@ struct CoarseDev {
     const int* node_cptr;   // [N+1]
     const int* node_copy;
     double* gscratch;       // 8 * nd doubles when the vectors do not fit in LDS
+    const double* zinv;     // [nd][nd] solution operator (direct solver)
     // what lives in the dynamic LDS (in this order): vectors, CSR (val, then
     // col and row pointers), A^-1, S^-1
     int vec_lds, csr_lds, ainv_lds, sinv_lds;
@@ -936,6 +1057,57 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
     if (threadIdx.x == 0 && stats) {
         stats[0] = (double)it;
         stats[1] = rel;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Direct level-0 solve x0 = Z b0 with Z the leading block of the inverse of
+// the level-0 system bordered by the mean constraint: one wave per row of Z
+// (rows are contiguous), the gathered b0 staged in LDS by every workgroup.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_coarse_direct(CoarseDev cd, const T* __restrict__ b,
+                                                       size_t blen, T* __restrict__ x, size_t xlen,
+                                                       double* __restrict__ stats) {
+    extern __shared__ double bl[];
+    const int nd = cd.nd, nfv = cd.nfv, N = cd.N;
+    for (int i = threadIdx.x; i < nd; i += TPB) {
+        if (i < 3 * nfv) {
+            const int c = i / nfv;
+            bl[i] = (double)b[c * blen + cd.node_slot[cd.vel_node[i - c * nfv]]];
+        } else {
+            bl[i] = (double)b[3 * blen + cd.node_slot[i - 3 * nfv]];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int row = (int)blockIdx.x * (TPB / 64) + ((int)threadIdx.x >> 6);
+    if (row < nd) {
+        const double* z = cd.zinv + (size_t)row * nd;
+        double acc = 0.0;
+        for (int q = lane; q < nd; q += 64) acc += z[q] * bl[q];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            int comp, vtx;
+            if (row < 3 * nfv) {
+                comp = row / nfv;
+                vtx = cd.vel_node[row - comp * nfv];
+            } else {
+                comp = 3;
+                vtx = row - 3 * nfv;
+            }
+            for (int e = cd.node_cptr[vtx]; e < cd.node_cptr[vtx + 1]; ++e)
+                x[comp * xlen + cd.node_copy[e]] = (T)acc;
+        }
+    }
+    // velocity of the Dirichlet vertices: no correction
+    const int g = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    if (g < N && cd.node_vidx[g] < 0)
+        for (int e = cd.node_cptr[g]; e < cd.node_cptr[g + 1]; ++e)
+            for (int c = 0; c < 3; ++c) x[c * xlen + cd.node_copy[e]] = T(0);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && stats) {
+        stats[0] = 1.0;
+        stats[1] = 0.0;
     }
 }
 

@@ -76,6 +76,8 @@ def test_plan_rejects_bad_arguments():
     _expect_einval(xyz, tet, nu, tags, nu1=0, nu2=0)
     _expect_einval(xyz, tet, nu, tags, precision=3)
     _expect_einval(xyz, tet, nu, tags, coarse_maxit=0)
+    _expect_einval(xyz, tet, nu, tags, coarse_solver=2)
+    _expect_einval(xyz, tet, nu, tags, coarse_prec=2)
 
 
 def test_host_context_rejects_device_calls():

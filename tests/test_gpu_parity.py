@@ -122,18 +122,26 @@ def test_uzawa_step_matches_oracle(cid, R):
         assert _relerr(_host(s.gather(xd, l)), xo) < 1e-12, l
 
 
-@pytest.mark.parametrize("cid,prec", [(1, 0), (4, 0), (5, 0), (1, 1), (5, 1)])
-def test_coarse_solve_matches_dense(cid, prec):
-    """Both pressure preconditioners (exact Schur complement, lumped mass)."""
-    cfg, s, umg = _setup(cid, 3, coarse_prec=prec)
+@pytest.mark.parametrize("cid,solver,prec", [(1, 0, 1), (4, 0, 1), (5, 0, 1),
+                                             (1, 1, 0), (4, 1, 0), (5, 1, 0), (1, 1, 1), (5, 1, 1)])
+def test_coarse_solve_matches_dense(cid, solver, prec):
+    """Direct solver (bordered inverse) and MINRES with both pressure
+    preconditioners (exact Schur complement, lumped mass) against the
+    oracle's bordered dense solve; an inconsistent right-hand side checks that
+    its component along the constant pressure is removed."""
+    cfg, s, umg = _setup(cid, 3, coarse_prec=prec, coarse_solver=solver)
     lv = umg.H.levels[0]
     x = _rand_state(lv, 80)
     b = umg.apply(0, x)                  # compatible right-hand side
-    xg, it, rel = s.coarse_solve(s.scatter(_dev(b), 0))
-    xo = umg.coarse_solve(b)
-    assert it < 500 and rel < 1e-13
-    print(f"coarse PMINRES: {it} iterations, preconditioned residual {rel:.1e}")
-    assert _relerr(_host(s.gather(xg, 0)), xo) < 1e-11
+    for bb in (b, b + np.concatenate([np.zeros((3, lv.N)), np.full((1, lv.N), 0.1)])):
+        xg, it, rel = s.coarse_solve(s.scatter(_dev(bb), 0))
+        xo = umg.coarse_solve(bb)
+        if solver == 1:
+            assert it < 500 and rel < 1e-13
+            print(f"coarse PMINRES: {it} iterations, preconditioned residual {rel:.1e}")
+        else:
+            assert it == 1 and rel == 0.0
+        assert _relerr(_host(s.gather(xg, 0)), xo) < 1e-11
 
 
 @pytest.mark.parametrize("cid,R", CASES)
