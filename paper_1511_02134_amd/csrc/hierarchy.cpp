@@ -373,8 +373,10 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
     L.len = L.mstride * nm;
     for (int c = 0; c < 3; ++c) L.lat[c] = mi.ext[c] * n + 1;
     L.N = (int64_t)L.lat[0] * L.lat[1] * L.lat[2];
-    if (L.len >= (1LL << 31) || L.N >= (1LL << 31)) {
-        *err = "problem too large for 32-bit slot indices";
+    // slot indices are 32-bit, and the stencil loads address a field with a
+    // 32-bit byte offset (8-byte values)
+    if (L.len >= (1LL << 29) || L.N >= (1LL << 31)) {
+        *err = "problem too large for 32-bit slot offsets";
         return false;
     }
     L.slot_node.assign(L.len, -1);

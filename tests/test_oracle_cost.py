@@ -1,0 +1,39 @@
+"""Cost models against the values the paper prints (Section 4.1, 4.2, 5)."""
+import json
+import os
+
+import pytest
+
+from oracle import cost
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_cost_model.json")))
+
+
+def test_operator_counts_match_paper():
+    g = GOLD["op_count"]
+    for blk in ("A", "B", "C"):
+        assert cost.n_op(blk, g["L"], g["n_I"]) == pytest.approx(g[blk], abs=0.005), blk
+
+
+def test_operator_counts_follow_the_smoother():
+    """The per-level counts of the paper's sums are those of the variable
+    V(3,3) cycle: 2 A, 2 B, 1 C per Uzawa step plus the residual."""
+    L = 6
+    for l in range(L + 1):
+        c = cost.uzawa_ops_per_level(L, l)
+        assert c["A"] == 4 * (3 + 2 * (L - l)) + 1
+        assert c["B"] == 4 * (3 + 2 * (L - l)) + 2
+        assert 2 * c["C"] == c["B"]
+
+
+def test_tme_matches_paper():
+    assert cost.wu_per_smoothing_step() == pytest.approx(GOLD["tme"]["wu_per_smoothing_step"])
+    assert cost.e_tme(nu=2) == pytest.approx(GOLD["tme"]["E_TME"], abs=0.005)
+    # the limit is reached: more levels change nothing
+    assert cost.e_tme(nu=2, L_max=30) == pytest.approx(cost.e_tme(nu=2, L_max=60), rel=1e-12)
+
+
+def test_memory_matches_paper():
+    g = GOLD["memory"]
+    # the printed 13.63 "GB" are GiB
+    assert cost.memory_bytes(g["L"]) / 2 ** 30 == pytest.approx(g["m_t_GB"], abs=0.005)
