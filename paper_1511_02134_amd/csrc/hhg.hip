@@ -43,6 +43,9 @@ struct DevLevelArrays {
     float *st32, *gst32, *nu32;
     int32_t *slot_node, *node_slot;
     int32_t* ctile_macro0;   // [nm+1] first natural closure tile of each macro
+    int32_t *if_tap, *halo_slot, *comp_of_slot;
+    double* cx64;            // mirror of the level's iterate (4 fields x cstride)
+    float* cx32;
     // work vectors (4 fields each)
     double *x64, *b64, *r64, *t64;
     float *x32, *b32, *r32, *t32;
@@ -152,6 +155,15 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
     return HHG_OK;
 }
 
+// fields of the compact mirror are padded to 64 entries
+inline int64_t mirror_stride(int32_t ncomp) { return ((int64_t)ncomp + 63) / 64 * 64; }
+template <typename T>
+T* mirror_of(DevLevelArrays& a);
+template <>
+double* mirror_of<double>(DevLevelArrays& a) { return a.cx64; }
+template <>
+float* mirror_of<float>(DevLevelArrays& a) { return a.cx32; }
+
 size_t layout(hhg_ctx* c, char* ws) {
     Carver cv(ws);
     const int nl = c->L + 1;
@@ -180,6 +192,12 @@ size_t layout(hhg_ctx* c, char* ws) {
         a.slot_node = cv.take<int32_t>(h.len);
         a.ctile_macro0 = cv.take<int32_t>(h.nm + 1);
         a.node_slot = cv.take<int32_t>(h.N);
+        a.if_tap = cv.take<int32_t>(std::max<size_t>(1, h.if_tap.size()));
+        a.halo_slot = cv.take<int32_t>(std::max<size_t>(1, h.halo_slot.size()));
+        a.comp_of_slot = cv.take<int32_t>(h.len);
+        const size_t c4 = 4 * (size_t)mirror_stride(h.ncomp);
+        a.cx64 = cv.take<double>(c4);
+        a.cx32 = mixed ? cv.take<float>(c4) : nullptr;
         const size_t v4 = 4 * (size_t)h.len;
         a.r64 = cv.take<double>(v4);
         a.t64 = cv.take<double>(v4);
@@ -251,6 +269,12 @@ void fill_view(hhg_ctx* c, int l, LevelDev<T>& v) {
     for (int q = 0; q < 5; ++q) v.col_start[q] = h.col_start[q];
     for (int q = 0; q < 4; ++q) v.vel_end[q] = h.vel_end[q];
     v.rif_fine = a.rif_fine;
+    v.ncomp = h.ncomp;
+    v.cstride = mirror_stride(h.ncomp);
+    v.if_tap = a.if_tap;
+    v.halo_slot = a.halo_slot;
+    v.comp_of_slot = a.comp_of_slot;
+    v.cx = mirror_of<T>(a);
 }
 
 template <typename T>
@@ -330,6 +354,9 @@ hhg_status upload_all(hhg_ctx* c) {
         if (!h.rif_fine.empty()) UP(int32_t, a.rif_fine, h.rif_fine);
         UP(int32_t, a.slot_node, h.slot_node);
         UP(int32_t, a.node_slot, h.node_slot);
+        UP(int32_t, a.if_tap, h.if_tap);
+        UP(int32_t, a.halo_slot, h.halo_slot);
+        UP(int32_t, a.comp_of_slot, h.comp_of_slot);
         {
             std::vector<int32_t> m0(h.nm + 1, 0);
             for (const Tile& t : h.ctiles)
@@ -507,8 +534,34 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
     Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
              bytes);
-    hipLaunchKernelGGL((k_full<T, MODE, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y, c->partials,
-                       ib, (T*)nullptr, -1, T(0));
+    hipLaunchKernelGGL((k_full<T, MODE, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y,
+                       c->partials, ib, (T*)nullptr, -1, T(0));
+}
+
+// residual of the level's smoothed iterate: interface taps from its mirror
+template <typename T>
+void residual_mirror(hhg_ctx* c, int l, const T* x, const T* b, T* r, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
+    Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
+    hipLaunchKernelGGL((k_full<T, MODE_RES, false, true>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
+                       c->partials, ib, (T*)nullptr, -1, T(0));
+}
+
+// mirror of x taken afresh (entry points that smooth a caller's vector)
+template <typename T>
+void mirror_refresh(hhg_ctx* c, int l, const T* x, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    hipLaunchKernelGGL(k_mirror_gather<T>, dim3((v.ncomp + TPB - 1) / TPB), dim3(TPB), 0, s, v, x);
+}
+
+// x <- 0 together with its mirror
+template <typename T>
+void fill_iterate(hhg_ctx* c, int l, T* x, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const size_t n4 = 4 * (size_t)v.len, m4 = 4 * (size_t)v.cstride;
+    hipLaunchKernelGGL(k_fill2<T>, dim3(grid_for(n4 + m4)), dim3(TPB), 0, s, x, n4, v.cx, m4, T(0));
 }
 
 // RU with the velocity sweep of colour col, or BP with the pressure sweep of
@@ -521,8 +574,8 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
-    hipLaunchKernelGGL((k_full<T, MODE, true>), dim3(grid), dim3(TPB), 0, s, v, (const T*)x, b, t,
-                       c->partials, ib, x, col, (T)c->opts.omega);
+    hipLaunchKernelGGL((k_full<T, MODE, true, true>), dim3(grid), dim3(TPB), 0, s, v, (const T*)x, b,
+                       t, c->partials, ib, x, col, (T)c->opts.omega);
 }
 
 template <typename T>
@@ -563,15 +616,20 @@ void fill(T* x, size_t n, T val, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(TPB), 0, s, x, n, val);
 }
 
+// r = b - K x and ||r||_2 into *out; with mirror the interface taps come
+// from the level's mirror of x (which must then be current)
 template <typename T>
-void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out, hipStream_t s) {
+void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out, hipStream_t s,
+                   bool mirror = false) {
     LevelDev<T>& v = view<T>(c, l);
     const int ib = iface_blocks(v.nif);
-    const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
-    {
+    if (mirror) {
+        residual_mirror<T>(c, l, x, b, r, s);
+    } else {
+        const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
         Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
-        hipLaunchKernelGGL((k_full<T, MODE_RES, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
-                           c->partials, ib, (T*)nullptr, -1, T(0));
+        hipLaunchKernelGGL((k_full<T, MODE_RES, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b,
+                           r, c->partials, ib, (T*)nullptr, -1, T(0));
     }
     hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
                        v.nv_nat + (v.nif + TPB - 1) / TPB, out, 1);
@@ -617,8 +675,9 @@ void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
     hipLaunchKernelGGL(k_mass_dot<T>, dim3(grid), dim3(TPB), 0, s, v, x + 3 * len, c->partials, ib);
     hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
                        v.nv_nat + (v.nif + TPB - 1) / TPB, c->scal + 4, 0);
-    hipLaunchKernelGGL(k_sub_mean<T>, dim3(grid_for(len)), dim3(TPB), 0, s, x + 3 * len, len,
-                       c->scal + 4, c->inv_mass[l]);
+    const size_t cs = (size_t)v.cstride;
+    hipLaunchKernelGGL(k_sub_mean2<T>, dim3(grid_for(len + cs)), dim3(TPB), 0, s, x + 3 * len, len,
+                       v.cx + 3 * cs, cs, c->scal + 4, c->inv_mass[l]);
 }
 
 template <typename T>
@@ -633,16 +692,18 @@ void vcycle(hhg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
         hipLaunchKernelGGL(k_add<T>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, (const T*)tl, n4);
         return;
     }
+    // the mirror of x is current on entry (refreshed, filled, or written by
+    // the previous cycle's sweeps and projection) and the sweeps keep it so
     const int extra = c->opts.cycle == 1 ? 2 * (c->L - l) : 0;
     for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
-    full_pass<T, MODE_RES>(c, l, x, b, rl, s);
+    residual_mirror<T>(c, l, x, b, rl, s);
     T *xc, *bc, *rc, *tc;
     vecs<T>(c, l - 1, &xc, &bc, &rc, &tc);
     restrict_to<T>(c, l, rl, bc, s);
     if (l - 1 == 0) {
         coarse_solve<T>(c, bc, xc, s);
     } else {
-        fill<T>(xc, 4 * (size_t)c->H[l - 1].len, T(0), s);
+        fill_iterate<T>(c, l - 1, xc, s);
         vcycle<T>(c, l - 1, xc, bc, s);
     }
     prolong_add<T>(c, l, xc, x, s);
@@ -858,6 +919,7 @@ hhg_status hhg_smooth(hhg_ctx* c, int32_t l, void* x, const void* b, int32_t ste
     CHECK_PTR(c, x);
     CHECK_PTR(c, b);
     if (steps < 0 || steps > 1000) return fail(c, HHG_EINVAL, "steps must be 0..1000");
+    mirror_refresh<double>(c, l, (const double*)x, (hipStream_t)stream);
     for (int q = 0; q < steps; ++q)
         uzawa_step<double>(c, l, (double*)x, (const double*)b, c->A[l].t64, (hipStream_t)stream);
     LAUNCH_CHECK(c);
@@ -929,7 +991,7 @@ void cycle_mixed(hhg_ctx* c, double* x, hipStream_t s) {
     const size_t n4 = 4 * (size_t)c->H[L].len;
     hipLaunchKernelGGL(k_scale_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, a.r64, c->scal,
                        a.b32, n4);
-    fill<float>(a.x32, n4, 0.0f, s);
+    fill_iterate<float>(c, L, a.x32, s);
     vcycle<float>(c, L, a.x32, a.b32, s);
     hipLaunchKernelGGL(k_axpy_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, c->scal, a.x32,
                        n4);
@@ -950,6 +1012,7 @@ hhg_status hhg_vcycle(hhg_ctx* c, void* x, const void* b, hhg_stream stream) {
         residual_norm<double>(c, c->L, (const double*)x, (const double*)b, c->A[c->L].r64, c->scal, s);
         cycle_mixed(c, (double*)x, s);
     } else {
+        mirror_refresh<double>(c, c->L, (const double*)x, s);
         cycle_fp64(c, (double*)x, (const double*)b, s);
     }
     LAUNCH_CHECK(c);
@@ -993,13 +1056,17 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     int stagn = 0;
     hhg_status st = HHG_ENOCONV;
     if (e0) (void)hipEventRecord(e0, s);
+    // FP64 cycles smooth x itself: take its mirror once; the cycles and the
+    // projection keep it current, so the stopping test may use it too
+    const bool fp64 = c->opts.precision != 1;
+    if (fp64) mirror_refresh<double>(c, c->L, x, s);
     int k = 0;
     for (k = 1; k <= max_cycles; ++k) {
-        if (c->opts.precision == 1)
+        if (!fp64)
             cycle_mixed(c, x, s);
         else
             cycle_fp64(c, x, b, s);
-        residual_norm<double>(c, c->L, x, b, r, c->scal, s);
+        residual_norm<double>(c, c->L, x, b, r, c->scal, s, fp64);
         HIPCHECK(c, hipMemcpyAsync(&nrm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
         I->res_hist[k] = nrm;
@@ -1157,6 +1224,39 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
             for (int j = 1; j <= n - k - 2; ++j)
                 for (int i = 1; i <= n - k - 1 - j; ++i)
                     CK(seen[local_slot(h, m, i, j, k)] == 1, "interior vertex not covered");
+    // compact mirror: taps name the same vertex as the slot taps; every copy
+    // of an interface vertex and every halo slot maps to its entry; a slot
+    // with an entry passes the kernels' near-boundary test
+    {
+        const int nif = h.nif;
+        CK(h.ncomp == nif + (int)h.halo_slot.size(), "mirror size");
+        CK((int64_t)h.comp_of_slot.size() == h.len, "mirror slot table size");
+        auto slot_of_entry = [&](int e) { return e < nif ? h.if_self[e] : h.halo_slot[e - nif]; };
+        for (int t = 0; t < nif; ++t)
+            for (int g = 0; g < 14; ++g) {
+                const int e = h.if_tap[(size_t)g * nif + t];
+                CK(e >= 0 && e < h.ncomp, "mirror tap out of range");
+                CK(h.slot_node[slot_of_entry(e)] == h.slot_node[h.if_nb[(size_t)g * nif + t]],
+                   "mirror tap names another vertex");
+            }
+        for (int t = 0; t < nif; ++t)
+            for (int q = h.if_cptr[t]; q < h.if_cptr[t + 1]; ++q)
+                CK(h.comp_of_slot[h.if_copy[q]] == t, "interface copy without its mirror entry");
+        for (size_t e = 0; e < h.halo_slot.size(); ++e)
+            CK(h.comp_of_slot[h.halo_slot[e]] == nif + (int)e, "halo slot without its mirror entry");
+        int64_t with_entry = 0;
+        for (int m = 0; m < h.nm; ++m)
+            for (int k = 0; k <= n; ++k)
+                for (int j = 0; j <= n - k; ++j)
+                    for (int i = 0; i <= n - k - j; ++i) {
+                        const int64_t sl = local_slot(h, m, i, j, k);
+                        if (h.comp_of_slot[sl] < 0) continue;
+                        ++with_entry;
+                        CK(near_boundary(n, i, j, k), "mirror entry away from the macro boundary");
+                    }
+        CK(with_entry == (int64_t)h.if_copy.size() + (int64_t)h.halo_slot.size(),
+           "mirror entries on padding slots");
+    }
     // full-pass blocks: each real tile once per sub-row, on the tile's XCD,
     // partial slots 4 nat + r distinct and below the reduction count (the
     // prolongation maps its closure tiles the same way)

@@ -97,6 +97,14 @@ struct LevelDev {
     // index of the same vertex in the finer level's interface list
     const int32_t* rif_fine;
     const T* macro_nu;       // [nm]
+    // compact mirror of the smoothed iterate x: interface vertices (list
+    // order) then their volume neighbours; field f of entry e is cx[f * cstride + e]
+    int32_t ncomp;
+    int64_t cstride;
+    const int32_t* if_tap;       // [14][nif] mirror index of each neighbour
+    const int32_t* halo_slot;    // [ncomp - nif]
+    const int32_t* comp_of_slot; // [len] mirror index of a slot or -1
+    T* cx;
 };
 
 }  // namespace hhg

@@ -530,6 +530,41 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         while (e < L.col_start[c + 1] && L.if_flag[e] == 0) ++e;
         L.vel_end[c] = e;
     }
+    // Compact mirror: interface vertices keep their list index; the volume
+    // vertices they couple to follow.  Halo indices are handed out tap by tap
+    // within each run of equal (colour, flag, stencil record), so the lanes of
+    // a wave, which walk such a run in slot order, read one mirror run per tap.
+    {
+        std::vector<int32_t> comp(L.len, -1);
+        for (int t = 0; t < nif; ++t)
+            for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q) comp[L.if_copy[q]] = t;
+        std::vector<int> colour_of(nif, 0);
+        for (int c = 0; c < 4; ++c)
+            for (int t = L.col_start[c]; t < L.col_start[c + 1]; ++t) colour_of[t] = c;
+        L.if_tap.assign((size_t)14 * nif, 0);
+        L.halo_slot.clear();
+        int32_t next = nif;
+        for (int g0 = 0; g0 < nif;) {
+            int g1 = g0 + 1;
+            while (g1 < nif && colour_of[g1] == colour_of[g0] && L.if_flag[g1] == L.if_flag[g0] &&
+                   L.if_sid[g1] == L.if_sid[g0])
+                ++g1;
+            for (int g = 0; g < 14; ++g)
+                for (int t = g0; t < g1; ++t) {
+                    const int32_t sl = L.if_nb[(size_t)g * nif + t];
+                    int32_t ci = comp[sl];
+                    if (ci < 0) {
+                        ci = next++;
+                        comp[sl] = ci;
+                        L.halo_slot.push_back(sl);
+                    }
+                    L.if_tap[(size_t)g * nif + t] = ci;
+                }
+            g0 = g1;
+        }
+        L.ncomp = next;
+        L.comp_of_slot.swap(comp);
+    }
     L.nfree = 0;
     for (int64_t v = 0; v < L.N; ++v)
         if (L.node_slot[v] >= 0 && !L.node_dir[v]) ++L.nfree;

@@ -56,6 +56,12 @@ struct HostLevel {
     std::vector<int32_t> node_sid;         // [N] stencil id (interface) or -(m+1) (volume of m)
     std::vector<int8_t> node_dir;          // [N] velocity Dirichlet
     std::vector<int32_t> rif_fine;         // [nif] index in the finer level's interface list
+    // compact mirror of x: entries 0..nif-1 are the interface vertices (in
+    // list order), entries nif.. the volume vertices they couple to (halo)
+    int32_t ncomp = 0;
+    std::vector<int32_t> if_tap;           // [14][nif] mirror index of each neighbour
+    std::vector<int32_t> halo_slot;        // [ncomp - nif] slot of each halo vertex
+    std::vector<int32_t> comp_of_slot;     // [len] mirror index of a slot or -1
     int64_t nfree = 0;                     // free velocity vertices
 };
 

@@ -143,42 +143,55 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // precomputed with the pressure frozen; three components at once.
 // Pressure: p += omega (bp - (C p)_x) / C_xx with bp = B u - g.
 // ---------------------------------------------------------------------------
-// One interface vertex t of a colour sweep with the stencil record st; the new
-// value goes to every macro copy (the ghost exchange fused into the update).
+// A volume vertex at distance one from its macro's boundary may be a
+// neighbour of an interface vertex, and then has a mirror entry.
+__host__ __device__ __forceinline__ bool near_boundary(int n, int i, int j, int k) {
+    return i <= 1 || j <= 1 || k <= 1 || i + j + k >= n - 1;
+}
+
+// One interface vertex t of a colour sweep: its neighbours come from the
+// mirror (unit-stride runs), the new value goes to every macro copy of the
+// vertex (the ghost exchange fused into the update) and to the mirror.
 template <typename T, bool VEL>
 __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                              T* __restrict__ x, const T* __restrict__ rhs, T omega) {
-    const size_t len = (size_t)L.len;
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
     const int self = L.if_self[t];
+    T* cx = L.cx;
     int nb[6];
 #pragma unroll
-    for (int g = 0; g < 6; ++g) nb[g] = L.if_nb[g * nif + t];
+    for (int g = 0; g < 6; ++g) nb[g] = L.if_tap[g * nif + t];
     const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
     if (VEL) {
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            T* u = x + f * len;
+            const T* u = cx + f * cs;
             T acc = T(0);
 #pragma unroll
             for (int g = 0; g < 6; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
             const T v = (rhs[f * len + self] - acc) * st[ST_INVA];
-            for (int q = c0; q < c1; ++q) u[L.if_copy[q]] = v;
+            for (int q = c0; q < c1; ++q) x[f * len + L.if_copy[q]] = v;
+            cx[f * cs + t] = v;
         }
     } else {
-        T* p = x + 3 * len;
-        T cp = st[ST_C] * p[self];
+        const T* p = cx + 3 * cs;
+        const T p0 = p[t];
+        T cp = st[ST_C] * p0;
 #pragma unroll
         for (int g = 0; g < 6; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
-        const T v = p[self] + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
-        for (int q = c0; q < c1; ++q) p[L.if_copy[q]] = v;
+        const T v = p0 + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
+        for (int q = c0; q < c1; ++q) x[3 * len + L.if_copy[q]] = v;
+        cx[3 * cs + t] = v;
     }
 }
 
+// Colour sweeps keep the mirror of x current: a level's smoothing starts
+// with a current mirror (refreshed, filled or written by the prolongation).
 template <typename T, bool VEL>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
                                                 const T* __restrict__ rhs, T omega, int ib) {
-    const size_t len = (size_t)L.len;
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     if ((int)blockIdx.x >= ib) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
         if (tl.macro < 0) return;
@@ -193,6 +206,7 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         int s[7];
         axis_slots(R, i, s);
         const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+        const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
         if (VEL) {
             const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
                     a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
@@ -202,14 +216,18 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
                 T v = rhs[f * len + s[0]] -
                       (a1 * u[s[1]] + a2 * u[s[2]] + a3 * u[s[3]] + a4 * u[s[4]] + a7 * u[s[5]] +
                        a8 * u[s[6]]);
-                u[s[0]] = v * ia;
+                v *= ia;
+                u[s[0]] = v;
+                if (cm >= 0) L.cx[f * cs + cm] = v;
             }
         } else {
             T* p = x + 3 * len;
             const T cp = st[ST_C + 0] * p[s[0]] + st[ST_C + 1] * p[s[1]] + st[ST_C + 2] * p[s[2]] +
                          st[ST_C + 3] * p[s[3]] + st[ST_C + 4] * p[s[4]] + st[ST_C + 7] * p[s[5]] +
                          st[ST_C + 8] * p[s[6]];
-            p[s[0]] += omega * (rhs[3 * len + s[0]] - cp) * st[ST_INVC];
+            const T v = p[s[0]] + omega * (rhs[3 * len + s[0]] - cp) * st[ST_INVC];
+            p[s[0]] = v;
+            if (cm >= 0) L.cx[3 * cs + cm] = v;
         }
         return;
     }
@@ -240,18 +258,23 @@ __device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t boff) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
 }
 
+// One row of a full pass.  s[] are the 15 taps of x (centre first) in a
+// field of stride xs (a macro array, or the compact mirror for interface
+// vertices); the vertex's own entries of b sit at slot bslot of fields of
+// stride bs.
 template <typename T, int MODE>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
-                                          const T* __restrict__ x, const T* __restrict__ b,
-                                          size_t len, T out[4]) {
+                                          const T* __restrict__ x, size_t xs,
+                                          const T* __restrict__ b, size_t bs, int bslot,
+                                          T out[4]) {
     if (MODE == MODE_RU) {
-        const T* p = x + 3 * len;
+        const T* p = x + 3 * xs;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             T acc = T(0);
 #pragma unroll
             for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * p[s[g]];
-            out[f] = dir ? T(0) : b[f * len + s[0]] - acc;
+            out[f] = dir ? T(0) : b[f * bs + bslot] - acc;
         }
         return;
     }
@@ -260,17 +283,17 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
 #pragma unroll
         for (int f = 0; f < 3; ++f)
 #pragma unroll
-            for (int g = 0; g < 15; ++g) acc += st[ST_B + 15 * f + g] * x[f * len + s[g]];
-        out[3] = acc - b[3 * len + s[0]];
+            for (int g = 0; g < 15; ++g) acc += st[ST_B + 15 * f + g] * x[f * xs + s[g]];
+        out[3] = acc - b[3 * bs + bslot];
         return;
     }
     if (MODE == MODE_RHS || MODE == MODE_GRADF) {
-        const T* pl = x + 3 * len;
+        const T* pl = x + 3 * xs;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             T m = T(0);
 #pragma unroll
-            for (int g = 0; g < 15; ++g) m += st[ST_M + g] * x[f * len + s[g]];
+            for (int g = 0; g < 15; ++g) m += st[ST_M + g] * x[f * xs + s[g]];
             if (MODE == MODE_RHS) {
                 out[f] = dir ? T(0) : m;
             } else {
@@ -285,7 +308,7 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
 #pragma unroll
             for (int f = 0; f < 3; ++f)
 #pragma unroll
-                for (int g = 0; g < 15; ++g) acc += st[ST_G + 15 * f + g] * x[f * len + s[g]];
+                for (int g = 0; g < 15; ++g) acc += st[ST_G + 15 * f + g] * x[f * xs + s[g]];
             out[3] = acc;
         }
         return;
@@ -294,14 +317,14 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
     uint32_t o[15];
 #pragma unroll
     for (int g = 0; g < 15; ++g) o[g] = (uint32_t)s[g] * (uint32_t)sizeof(T);
-    const T* p = x + 3 * len;
+    const T* p = x + 3 * xs;
     T pv[15];
 #pragma unroll
     for (int g = 0; g < 15; ++g) pv[g] = ldo(p, o[g]);
     T bu = T(0);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const T* u = x + f * len;
+        const T* u = x + f * xs;
         T au = T(0), btp = T(0);
 #pragma unroll
         for (int g = 0; g < 15; ++g) {
@@ -311,13 +334,13 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
             bu += st[ST_B + 15 * f + g] * uv;
         }
         const T ku = au + btp;
-        out[f] = dir ? T(0) : (MODE == MODE_RES ? ldo(b + f * len, o[0]) - ku : ku);
+        out[f] = dir ? T(0) : (MODE == MODE_RES ? b[f * bs + bslot] - ku : ku);
     }
     T cp = T(0);
 #pragma unroll
     for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * pv[g];
     const T kp = bu - cp;
-    out[3] = MODE == MODE_RES ? ldo(b + 3 * len, o[0]) - kp : kp;
+    out[3] = MODE == MODE_RES ? b[3 * bs + bslot] - kp : kp;
 }
 
 template <int MODE>
@@ -326,6 +349,53 @@ __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
     f1 = 4;
     if (MODE == MODE_RU || MODE == MODE_GRADF) f1 = 3;
     if (MODE == MODE_BP) f0 = 3;
+}
+
+// Colour-c update fused into a full pass (velocity Gauss-Seidel into the
+// B^T p pass, pressure relaxation into the B u pass): out[] holds the
+// node's freshly computed right-hand side, tp the 7 axis taps (centre first)
+// into xr (stride rs).  The update reads only colours c -+ 1 (and, for the
+// pressure, the vertex itself) and writes colour c, which no other lane of
+// the launch reads, so it runs alongside the full pass.  Axis coefficients
+// sit at record positions 1, 2, 3, 4, 7, 8 in the local order of volume
+// records and 1..6 in the global direction order of interface records.
+// Volume vertices write their slot, interface vertices every copy; both
+// write mirror entry cm when there is one.
+template <typename T, int MODE, bool IFACE>
+__device__ __forceinline__ void fused_update(const T* __restrict__ st, const int* tp, const T* xr,
+                                             size_t rs, T* xw, size_t len, const T out[4], T omega,
+                                             int ncopy, const int* copies, T* cx, size_t cs, int cm) {
+    constexpr int q5 = IFACE ? 5 : 7, q6 = IFACE ? 6 : 8;
+    if (MODE == MODE_RU) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const T* u = xr + f * rs;
+            const T v = out[f] - (st[ST_A + 1] * u[tp[1]] + st[ST_A + 2] * u[tp[2]] +
+                                  st[ST_A + 3] * u[tp[3]] + st[ST_A + 4] * u[tp[4]] +
+                                  st[ST_A + q5] * u[tp[5]] + st[ST_A + q6] * u[tp[6]]);
+            const T un = v * st[ST_INVA];
+            if (IFACE)
+                for (int q = 0; q < ncopy; ++q) xw[f * len + copies[q]] = un;
+            else
+                xw[f * len + tp[0]] = un;
+            if (cm >= 0) cx[f * cs + cm] = un;
+        }
+    } else {
+        // the vertex's own pressure is read where it is written (the mirror
+        // entry of an interface vertex, the slot of a volume vertex through
+        // xw): nothing read through a restrict pointer changes
+        const T* p = xr + 3 * rs;
+        const T p0 = IFACE ? cx[3 * cs + cm] : xw[3 * len + tp[0]];
+        const T cp = st[ST_C] * p0 + st[ST_C + 1] * p[tp[1]] + st[ST_C + 2] * p[tp[2]] +
+                     st[ST_C + 3] * p[tp[3]] + st[ST_C + 4] * p[tp[4]] + st[ST_C + q5] * p[tp[5]] +
+                     st[ST_C + q6] * p[tp[6]];
+        const T pn = p0 + omega * (out[3] - cp) * st[ST_INVC];
+        if (IFACE)
+            for (int q = 0; q < ncopy; ++q) xw[3 * len + copies[q]] = pn;
+        else
+            xw[3 * len + tp[0]] = pn;
+        if (cm >= 0) cx[3 * cs + cm] = pn;
+    }
 }
 
 // Volume blocks of a full pass: four per tile, one per sub-row r = i mod 4, so
@@ -342,70 +412,33 @@ __host__ __device__ __forceinline__ int full_blocks(int n_vtiles) { return 4 * (
 // need every tap of all fields in flight at once (over 256 VGPRs).
 __host__ __device__ constexpr bool quad_lanes(int mode) { return mode == 0 || mode == 1 || mode >= 4; }
 
-// Colour-c update fused into a full pass (velocity Gauss-Seidel into the
-// B^T p pass, pressure relaxation into the B u pass): out[] holds the
-// node's freshly computed right-hand side, t the 7 axis taps (centre first).
-// The update reads only colours c -+ 1 (and, for the pressure, the vertex
-// itself) and writes colour c, which no other lane of the launch reads, so it
-// runs alongside the full pass.  Axis coefficients sit at record positions
-// 1, 2, 3, 4, 7, 8 in the local order of volume records and 1..6 in the
-// global direction order of interface records.
-template <typename T, int MODE, bool IFACE>
-__device__ __forceinline__ void fused_update(const T* __restrict__ st, const int* t, const T* x,
-                                             T* xw, size_t len, const T out[4], T omega,
-                                             int ncopy, const int* copies) {
-    constexpr int q5 = IFACE ? 5 : 7, q6 = IFACE ? 6 : 8;
-    if (MODE == MODE_RU) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            const T* u = x + f * len;
-            const T v = out[f] - (st[ST_A + 1] * u[t[1]] + st[ST_A + 2] * u[t[2]] +
-                                  st[ST_A + 3] * u[t[3]] + st[ST_A + 4] * u[t[4]] +
-                                  st[ST_A + q5] * u[t[5]] + st[ST_A + q6] * u[t[6]]);
-            const T un = v * st[ST_INVA];
-            if (IFACE)
-                for (int q = 0; q < ncopy; ++q) xw[f * len + copies[q]] = un;
-            else
-                xw[f * len + t[0]] = un;
-        }
-    } else {
-        // the vertex's own pressure is read through xw, the pointer that
-        // writes it: nothing read through x changes during the launch
-        const T* p = x + 3 * len;
-        const T p0 = xw[3 * len + t[0]];
-        const T cp = st[ST_C] * p0 + st[ST_C + 1] * p[t[1]] + st[ST_C + 2] * p[t[2]] +
-                     st[ST_C + 3] * p[t[3]] + st[ST_C + 4] * p[t[4]] + st[ST_C + q5] * p[t[5]] +
-                     st[ST_C + q6] * p[t[6]];
-        const T pn = p0 + omega * (out[3] - cp) * st[ST_INVC];
-        if (IFACE)
-            for (int q = 0; q < ncopy; ++q) xw[3 * len + copies[q]] = pn;
-        else
-            xw[3 * len + t[0]] = pn;
-    }
-}
-
-// Interface vertex t of a full pass with the stencil record st; with FUSE the
-// colour-fc vertices (velocity: those without Dirichlet data) are also updated.
-template <typename T, int MODE, bool FUSE>
+// Interface vertex t of a full pass with the stencil record st.  With MIRROR
+// its taps of x come from the mirror; with FUSE (which needs the mirror) the
+// colour-fc vertices (velocity: those without Dirichlet data) are updated too.
+template <typename T, int MODE, bool FUSE, bool MIRROR>
 __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
-                                           const T* x, const T* __restrict__ b, T* xw,
-                                           size_t len, int fcol, T omega, T out[4]) {
+                                           const T* __restrict__ x, const T* __restrict__ b, T* xw,
+                                           int fcol, T omega, T out[4]) {
+    static_assert(!FUSE || MIRROR, "fused updates keep the mirror current");
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
+    const int self = L.if_self[t];
     int s[15];
-    s[0] = L.if_self[t];
+    s[0] = MIRROR ? t : self;
+    const int32_t* taps = MIRROR ? L.if_tap : L.if_nb;
 #pragma unroll
-    for (int g = 1; g < 15; ++g) s[g] = L.if_nb[(g - 1) * nif + t];
+    for (int g = 1; g < 15; ++g) s[g] = taps[(g - 1) * nif + t];
     const bool dir = (L.if_flag[t] & 1) != 0;
-    eval_node<T, MODE>(st, s, dir, x, b, len, out);
+    eval_node<T, MODE>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out);
     if (FUSE && t >= L.col_start[fcol] &&
         t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
         const int c0 = L.if_cptr[t];
-        fused_update<T, MODE, true>(st, s, x, xw, len, out, omega, L.if_cptr[t + 1] - c0,
-                                    L.if_copy + c0);
+        fused_update<T, MODE, true>(st, s, L.cx, cs, xw, len, out, omega, L.if_cptr[t + 1] - c0,
+                                    L.if_copy + c0, L.cx, cs, t);
     }
 }
 
-template <typename T, int MODE, bool FUSE>
+template <typename T, int MODE, bool FUSE, bool MIRROR>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
@@ -434,7 +467,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    eval_node<T, MODE>(st, s, false, x, b, len, out);
+                    eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
@@ -459,14 +492,16 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    eval_node<T, MODE>(st, s, false, x, b, len, out);
+                    eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
                     }
                     if (FUSE && ((i + 2 * j + 3 * k) & 3) == fcol) {
-                        const int t[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
-                        fused_update<T, MODE, false>(st, t, x, xw, len, out, omega, 0, nullptr);
+                        const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
+                        const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
+                        fused_update<T, MODE, false>(st, tp, x, len, xw, len, out, omega, 0, nullptr,
+                                                     L.cx, (size_t)L.cstride, cm);
                     }
                 }
             }
@@ -477,7 +512,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
             T out[4];
-            iface_full<T, MODE, FUSE>(L, st, t, x, b, xw, len, fcol, omega, out);
+            iface_full<T, MODE, FUSE, MIRROR>(L, st, t, x, b, xw, fcol, omega, out);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int f = f0; f < f1; ++f) {
                 for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
@@ -586,11 +621,19 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     if (!P.ok || i > mm - j) return;
     const int mbf = (int)(tl.macro * F.mstride), mbc = (int)(tl.macro * C.mstride);
     const int sf = slot_of(F.slab_base, n, mbf, i, j, k);
+    // the fine level's mirror follows x (every copy of an interface vertex
+    // computes the same value, so concurrent writes of its entry agree)
+    const int cm = near_boundary(n, i, j, k) ? F.comp_of_slot[sf] : -1;
+    const size_t cs = (size_t)F.cstride;
     const int pi = i & 1, pj = j & 1, pk = k & 1;
     if ((pi | pj | pk) == 0) {
         const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) xf[f * lf + sf] += ec[f * lc + sc];
+        for (int f = 0; f < 4; ++f) {
+            const T v = xf[f * lf + sf] + ec[f * lc + sc];
+            xf[f * lf + sf] = v;
+            if (cm >= 0) F.cx[f * cs + cm] = v;
+        }
         return;
     }
     int di, dj, dk;
@@ -598,7 +641,11 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
     const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) xf[f * lf + sf] += T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+    for (int f = 0; f < 4; ++f) {
+        const T v = xf[f * lf + sf] + T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+        xf[f * lf + sf] = v;
+        if (cm >= 0) F.cx[f * cs + cm] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -770,6 +817,42 @@ __global__ void k_sub_mean(T* __restrict__ p, size_t n, const double* __restrict
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         p[i] -= mean;
+}
+
+// The mirror taken from x: interface vertices (primary slots) and halo.
+template <typename T>
+__global__ void k_mirror_gather(LevelDev<T> L, const T* __restrict__ x) {
+    const int e = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    if (e >= L.ncomp) return;
+    const int sl = e < L.nif ? L.if_self[e] : L.halo_slot[e - L.nif];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) L.cx[f * (size_t)L.cstride + e] = x[f * (size_t)L.len + sl];
+}
+
+// x <- v on n values and y <- v on m values (an iterate and its mirror)
+template <typename T>
+__global__ void k_fill2(T* __restrict__ x, size_t n, T* __restrict__ y, size_t m, T v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n + m;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (i < n)
+            x[i] = v;
+        else
+            y[i - n] = v;
+    }
+}
+
+// p -= mean on an iterate's pressure (n values) and its mirror (m values)
+template <typename T>
+__global__ void k_sub_mean2(T* __restrict__ p, size_t n, T* __restrict__ q, size_t m,
+                            const double* __restrict__ wsum, double inv_mass) {
+    const T mean = (T)(wsum[0] * inv_mass);
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n + m;
+         i += (size_t)gridDim.x * blockDim.x) {
+        if (i < n)
+            p[i] -= mean;
+        else
+            q[i - n] -= mean;
+    }
 }
 
 // layout conversion and ghost exchange

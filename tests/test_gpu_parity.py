@@ -167,6 +167,31 @@ def test_cycles_match_oracle_iterate_by_iterate(cid, R):
         assert _relerr(xg, xo) < 1e-10, k
 
 
+@pytest.mark.parametrize("cid,R,opts", [(1, 4, {"cycle": 1}), (5, 4, {"p_sweep": 1}),
+                                         (4, 4, {"cycle": 1, "p_sweep": 1, "nu1": 2, "nu2": 1})])
+def test_cycle_switches_match_oracle(cid, R, opts):
+    """The variable V-cycle (+2 smoothing steps per coarser level), the
+    symmetric pressure sweep and other smoothing counts: iterates agree with
+    the oracle's cycle of the same settings."""
+    cfg, s, umg = _setup(cid, R, **opts)
+    lv = umg.H.finest
+    bo = umg.rhs(cfg.forcing_field())
+    x0 = np.zeros((4, lv.N))
+    x0[:3] = cfg.dirichlet_field()
+    x0[:3, lv.free] = 0.0
+    xd, bd = s.scatter(_dev(x0)), s.scatter(_dev(bo))
+    xo = x0.copy()
+    r0 = umg.norm(umg.L, umg.residual(umg.L, x0, bo))
+    for k in range(3):
+        s.vcycle(xd, bd)
+        xo = umg.cycle(xo, bo)
+        xg = _host(s.gather(xd))
+        d = xg - xo
+        d[:3, lv.dirichlet] = 0.0
+        assert umg.norm(umg.L, umg.apply(umg.L, d)) <= 1e-10 * r0, k
+        assert _relerr(xg, xo) < 1e-10, k
+
+
 @pytest.mark.parametrize("cid,R", CASES)
 def test_solve_matches_oracle(cid, R):
     cfg, s, umg = _setup(cid, R)
