@@ -65,16 +65,26 @@ struct HostLevel {
     int64_t nfree = 0;                     // free velocity vertices
 };
 
-// Slot of macro-local vertex (i, j, k): tetrahedral slabs k, rows j, each row
-// split into 4 sub-rows by i mod 4 (row length m+1-j padded to a multiple of 4).
+// Slot of macro-local vertex (i, j, k): tetrahedral slabs k; slab k (m = n-k)
+// holds rows j = 0..m of Q_j = ceil((m+1-j)/4) quads, split by i mod 4 into
+// four sub-arrays of S = sum_j Q_j entries, each listing the even rows, then
+// the odd rows (the device kernels address it with the same formulas).
 inline int32_t R4(int32_t L) {
     int32_t a = L >> 2, b = L & 3;
     return 4 * (a + 1) * (2 * a + b);
 }
+inline int32_t parity_prefix_h(int32_t m, int32_t j) {
+    const int32_t J = j >> 1, A = m + 4 - (j & 1);
+    const int32_t E = (J + 1) >> 1, O = J >> 1;
+    return E * (A >> 2) - ((E * (E - 1)) >> 1) + O * ((A - 2) >> 2) - ((O * (O - 1)) >> 1);
+}
+inline int32_t row_off_h(int32_t m, int32_t j) {
+    return (j & 1) ? parity_prefix_h(m, ((m >> 1) << 1) + 2) + parity_prefix_h(m, j)
+                   : parity_prefix_h(m, j);
+}
 inline int64_t local_slot(const HostLevel& L, int m, int i, int j, int k) {
     int mm = L.n - k;
-    int32_t Q = (mm + 4 - j) >> 2;
-    return (int64_t)m * L.mstride + L.slab_base[k] + R4(mm + 1) - R4(mm + 1 - j) + (i & 3) * Q +
+    return (int64_t)m * L.mstride + L.slab_base[k] + row_off_h(mm, j) + (i & 3) * (R4(mm + 1) >> 2) +
            (i >> 2);
 }
 

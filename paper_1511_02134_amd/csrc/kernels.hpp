@@ -29,7 +29,26 @@ __host__ __device__ __forceinline__ int R4d(int L) {
 }
 __host__ __device__ __forceinline__ int at(int base, int Q, int i) { return base + (i & 3) * Q + (i >> 2); }
 
-// Row bases and sub-row lengths around row (j, k) of a macro:
+// Slab k of a macro (m = n - k) holds rows j = 0..m of Q_j = ceil((m+1-j)/4)
+// quads.  It is split by i mod 4 into four sub-arrays of equal length
+// S = sum_j Q_j; inside a sub-array the even rows come first, then the odd
+// rows, each row's Q_j entries contiguous.  Colour c = (i + 2j + 3k) mod 4
+// then occupies the even-row block of sub-array (c+k) mod 4 and the odd-row
+// block of sub-array (c+k+2) mod 4, and its neighbours (colours c -+ 1) fill
+// sub-arrays (c+k-+1) mod 4 entirely: a colour sweep streams whole blocks.
+// Vertex (i, j, k) sits at sb[k] + row_off(m, j) + (i & 3) S + (i >> 2).
+__host__ __device__ __forceinline__ int sub_stride(int m) { return R4d(m + 1) >> 2; }
+// sum of Q_j' over the rows j' < j of the parity of j
+__host__ __device__ __forceinline__ int parity_prefix(int m, int j) {
+    const int J = j >> 1, A = m + 4 - (j & 1);
+    const int E = (J + 1) >> 1, O = J >> 1;
+    return E * (A >> 2) - ((E * (E - 1)) >> 1) + O * ((A - 2) >> 2) - ((O * (O - 1)) >> 1);
+}
+__host__ __device__ __forceinline__ int row_off(int m, int j) {
+    return (j & 1) ? parity_prefix(m, ((m >> 1) << 1) + 2) + parity_prefix(m, j) : parity_prefix(m, j);
+}
+
+// Row bases and sub-array strides around row (j, k) of a macro:
 // 0:(j,k) 1:(j+1,k) 2:(j-1,k) 3:(j-1,k+1) 4:(j+1,k-1) 5:(j,k+1) 6:(j,k-1)
 struct Rows {
     int b[7];
@@ -39,20 +58,25 @@ struct Rows {
 __host__ __device__ __forceinline__ void make_rows(const int* __restrict__ sb, int n, int mb, int j, int k,
                                           Rows& R) {
     const int mm = n - k;
-    R.Q[0] = (mm + 4 - j) >> 2;
-    R.b[0] = mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j);
-    R.Q[1] = (mm + 3 - j) >> 2;
-    R.b[1] = R.b[0] + 4 * R.Q[0];
-    R.Q[2] = (mm + 5 - j) >> 2;
-    R.b[2] = R.b[0] - 4 * R.Q[2];
-    R.Q[5] = (mm + 3 - j) >> 2;
-    R.b[5] = mb + sb[k + 1] + R4d(mm) - R4d(mm - j);
-    R.Q[3] = (mm + 4 - j) >> 2;
-    R.b[3] = R.b[5] - 4 * R.Q[3];
-    R.Q[6] = (mm + 5 - j) >> 2;
-    R.b[6] = mb + sb[k - 1] + R4d(mm + 2) - R4d(mm + 2 - j);
-    R.Q[4] = (mm + 4 - j) >> 2;
-    R.b[4] = R.b[6] + 4 * R.Q[6];
+    const int b0 = mb + sb[k], bp = mb + sb[k + 1], bm = mb + sb[k - 1];
+    const int S0 = sub_stride(mm), Sp = sub_stride(mm - 1), Sm = sub_stride(mm + 1);
+    R.b[0] = b0 + row_off(mm, j);
+    R.b[1] = b0 + row_off(mm, j + 1);
+    R.b[2] = b0 + row_off(mm, j - 1);
+    R.b[3] = bp + row_off(mm - 1, j - 1);
+    R.b[4] = bm + row_off(mm + 1, j + 1);
+    R.b[5] = bp + row_off(mm - 1, j);
+    R.b[6] = bm + row_off(mm + 1, j);
+    R.Q[0] = R.Q[1] = R.Q[2] = S0;
+    R.Q[3] = R.Q[5] = Sp;
+    R.Q[4] = R.Q[6] = Sm;
+}
+
+// slot of macro-local vertex (i, j, k) in a macro whose array starts at mb
+__host__ __device__ __forceinline__ int slot_of(const int* __restrict__ sb, int n, int mb, int i, int j,
+                                       int k) {
+    const int mm = n - k;
+    return mb + sb[k] + row_off(mm, j) + (i & 3) * sub_stride(mm) + (i >> 2);
 }
 
 // slots of the centre and the 14 neighbours in macro-local offset order
@@ -74,12 +98,6 @@ __host__ __device__ __forceinline__ void nbr_slots(const Rows& R, int i, int s[1
     s[14] = at(R.b[4], R.Q[4], i - 1);
 }
 
-// slot of macro-local vertex (i, j, k) in a macro whose array starts at mb
-__host__ __device__ __forceinline__ int slot_of(const int* __restrict__ sb, int n, int mb, int i, int j,
-                                       int k) {
-    const int mm = n - k;
-    return mb + sb[k] + R4d(mm + 1) - R4d(mm + 1 - j) + (i & 3) * ((mm + 4 - j) >> 2) + (i >> 2);
-}
 
 // the 7 taps of A and C (centre, +-e_a, +-e_b, +-e_c) in local order
 __host__ __device__ __forceinline__ void axis_slots(const Rows& R, int i, int s[7]) {
@@ -788,9 +806,8 @@ __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __rest
             const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
             if (P.ok) {
                 const int j = P.j;
-                const int b0 = (int)(tl.macro * L.mstride) + L.slab_base[k] + R4d(mm + 1) -
-                               R4d(mm + 1 - j);
-                const int Q0 = (mm + 4 - j) >> 2;
+                const int b0 = (int)(tl.macro * L.mstride) + L.slab_base[k] + row_off(mm, j);
+                const int Q0 = sub_stride(mm);
                 const double w = (double)L.st[(size_t)tl.macro * ST_SIZE + ST_MASS];
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * P.q + r;
