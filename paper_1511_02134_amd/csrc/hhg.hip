@@ -566,16 +566,26 @@ void fill_iterate(hhg_ctx* c, int l, T* x, hipStream_t s) {
 
 // RU with the velocity sweep of colour col, or BP with the pressure sweep of
 // colour col, in one launch (x is updated in place, t receives the pass)
+// levels with at least this many intervals per macro edge evaluate RU and BP
+// by quad windows (fewer load instructions); smaller ones one vertex per lane
+// (more lanes for a latency-bound launch)
+constexpr int WIN_MIN_N = 32;
+
 template <typename T, int MODE>
 void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int ib = iface_blocks(v.nif);
-    const int grid = ib + full_blocks(v.n_vtiles);
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
-    hipLaunchKernelGGL((k_full<T, MODE, true, true>), dim3(grid), dim3(TPB), 0, s, v, (const T*)x, b,
-                       t, c->partials, ib, x, col, (T)c->opts.omega);
+    if (v.n >= WIN_MIN_N) {
+        hipLaunchKernelGGL((k_full<T, MODE, true, true, true>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s,
+                           v, (const T*)x, b, t, c->partials, ib, x, col, (T)c->opts.omega);
+    } else {
+        hipLaunchKernelGGL((k_full<T, MODE, true, true>), dim3(ib + full_blocks(v.n_vtiles)),
+                           dim3(TPB), 0, s, v, (const T*)x, b, t, c->partials, ib, x, col,
+                           (T)c->opts.omega);
+    }
 }
 
 template <typename T>

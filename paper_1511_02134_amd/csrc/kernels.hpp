@@ -430,6 +430,72 @@ __host__ __device__ __forceinline__ int full_blocks(int n_vtiles) { return 4 * (
 // need every tap of all fields in flight at once (over 256 VGPRs).
 __host__ __device__ constexpr bool quad_lanes(int mode) { return mode == 0 || mode == 1 || mode >= 4; }
 
+// Quad windows: a lane that evaluates the 4 vertices i = 4q..4q+3 of a row
+// loads every distinct tap value once.  Row rho of make_rows contributes the
+// positions 4q + QW_LO[rho] .. +5 (row 0) or +4; tap g of vertex r is window
+// QW_ROW[g] at r + QW_OFF[g] (taps in the local offset order of nbr_slots).
+// Per field that is 36 loads for 4 vertices instead of 60.
+__device__ constexpr int QW_ROW[15] = {0, 0, 0, 1, 2, 1, 2, 3, 4, 5, 6, 5, 6, 3, 4};
+__device__ constexpr int QW_OFF[15] = {1, 2, 0, 0, 1, 1, 0, 0, 1, 0, 1, 1, 0, 1, 0};
+__device__ constexpr int QW_LO[7] = {-1, -1, 0, 0, -1, -1, 0};
+
+// window slots of the quad q (positions past a row's end fall on other slots
+// of the same slab, which only vertices outside the row would use)
+__device__ __forceinline__ void quad_window_slots(const Rows& R, int q, int w[7][6]) {
+#pragma unroll
+    for (int rho = 0; rho < 7; ++rho)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int i = 4 * q + QW_LO[rho] + e;
+            w[rho][e] = R.b[rho] + (i & 3) * R.Q[rho] + (i >> 2);
+        }
+}
+
+template <typename T>
+__device__ __forceinline__ void quad_window_load(const T* __restrict__ f, const int w[7][6], T v[7][6]) {
+#pragma unroll
+    for (int rho = 0; rho < 7; ++rho)
+#pragma unroll
+        for (int e = 0; e < (rho == 0 ? 6 : 5); ++e)
+            v[rho][e] = ldo(f, (uint32_t)w[rho][e] * (uint32_t)sizeof(T));
+}
+
+// RU (t_k = b_k - (B^T p)_k) or BP (t_3 = B u - b_3) for the four vertices of
+// a quad; out[r] receives the values of vertex 4q + r.
+template <typename T, int MODE>
+__device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[7][6],
+                                          const T* __restrict__ x, const T* __restrict__ b,
+                                          size_t len, T out[4][4]) {
+    T v[7][6];
+    if (MODE == MODE_RU) {
+        quad_window_load(x + 3 * len, w, v);
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T acc = T(0);
+#pragma unroll
+                for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * v[QW_ROW[g]][r + QW_OFF[g]];
+                out[r][f] = b[f * len + w[0][r + 1]] - acc;
+            }
+    } else {
+        T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            // one field's window at a time: without the scheduling barrier
+            // the compiler hoists all three windows (over 256 VGPRs)
+            __builtin_amdgcn_sched_barrier(0);
+            quad_window_load(x + f * len, w, v);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int g = 0; g < 15; ++g) acc[r] += st[ST_B + 15 * f + g] * v[QW_ROW[g]][r + QW_OFF[g]];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[r][3] = acc[r] - b[3 * len + w[0][r + 1]];
+    }
+}
+
 // Interface vertex t of a full pass with the stencil record st.  With MIRROR
 // its taps of x come from the mirror; with FUSE (which needs the mirror) the
 // colour-fc vertices (velocity: those without Dirichlet data) are updated too.
@@ -456,18 +522,57 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     }
 }
 
-template <typename T, int MODE, bool FUSE, bool MIRROR>
+// WIN (RU and BP only): one block per tile, a quad per lane, quad windows.
+template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
+    static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP, "quad windows: RU and BP");
     __shared__ double sh[4];
     const size_t len = (size_t)L.len;
     int f0, f1;
     mode_fields<MODE>(f0, f1);
     double ss = 0.0;
     int slot = -1;   // partial-sum slot of this block
-    if (quad_lanes(MODE) && (int)blockIdx.x >= ib) {
+    if (WIN && (int)blockIdx.x >= ib) {
+        const Tile tl = L.vtiles[blockIdx.x - ib];
+        if (tl.macro >= 0) {
+            const int n = L.n, k = tl.k, mm = n - k;
+            const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+            if (P.ok) {
+                const int j = P.j;
+                Rows R;
+                make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+                const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+                int w[7][6];
+                quad_window_slots(R, P.q, w);
+                T out[4][4];
+                quad_eval<T, MODE>(st, w, x, b, len, out);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * P.q + r;
+                    if (i < 1 || i > mm - 1 - j) continue;
+                    for (int f = f0; f < f1; ++f) y[f * len + w[0][r + 1]] = out[r][f];
+                }
+                if (FUSE) {
+                    // the quad's vertex of colour fcol
+                    const int rc = (fcol + 2 * j + k) & 3, i = 4 * P.q + rc;
+                    if (i >= 1 && i <= mm - 1 - j) {
+                        T o[4];
+#pragma unroll
+                        for (int f = 0; f < 4; ++f)
+                            o[f] = rc == 0 ? out[0][f] : rc == 1 ? out[1][f] : rc == 2 ? out[2][f] : out[3][f];
+                        int s7[7];
+                        axis_slots(R, i, s7);
+                        const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s7[0]] : -1;
+                        fused_update<T, MODE, false>(st, s7, x, len, xw, len, o, omega, 0, nullptr,
+                                                     L.cx, (size_t)L.cstride, cm);
+                    }
+                }
+            }
+        }
+    } else if (quad_lanes(MODE) && (int)blockIdx.x >= ib) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
         slot = tl.nat;
         if (tl.macro >= 0) {
