@@ -99,6 +99,37 @@ print(json.dumps({{"seconds": t, "dofs": lv.ndofs(), "cycles": len(hist) - 1}}))
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
+def run_ops(workload_id: int):
+    """A short sequence of finest-level operations for counter collection
+    (rocprofv3 --pmc): K x, the residual, restriction and prolongation three
+    times each, two smoothing steps, then three device copies of 512 MiB whose
+    counter readings calibrate FETCH_SIZE and WRITE_SIZE."""
+    import torch
+    import workloads as W
+    import paper_1511_02134_amd as P
+
+    cfg = W.WORKLOADS[workload_id]
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=0)
+    L, N = s.L, s.num_nodes()
+    rng = np.random.default_rng(0)
+    x = s.scatter(torch.tensor(rng.normal(size=(4, N)), device="cuda"))
+    b = s.scatter(torch.tensor(rng.normal(size=(4, N)), device="cuda"))
+    y = torch.empty_like(x)
+    for _ in range(3):
+        s.apply(x, L, out=y)
+        r, _ = s.residual(x, b, L, norm=False)
+        xc = s.restrict(r, L)
+        s.prolong_add(xc, x, L)
+    s.smooth(x, b, 2, L)
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda").normal_()
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(f"operations done: workload {cfg.name}, {s.num_dofs()} DoFs", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +139,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-R", type=int, default=6,
                     help="refinements of the oracle's bounded sample")
+    ap.add_argument("--ops", action="store_true",
+                    help="run the operation sequence used for counter collection and exit")
     args = ap.parse_args()
+    if args.ops:
+        run_ops(args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "
               f"(requested --gpus {args.gpus})", file=sys.stderr)
