@@ -130,6 +130,82 @@ def run_ops(workload_id: int):
     print(f"operations done: workload {cfg.name}, {s.num_dofs()} DoFs", flush=True)
 
 
+def run_tme(R: int, steps: int, warmup: int):
+    """Full multigrid with one (FMG) and two (2FMG) variable V(2,2) cycles per
+    level on the analytic solution of the efficiency study (Section 5):
+    solve time, its cost in work units (one finest K apply) and the ratio
+    gamma of total to discretisation error (Table "gamma_l"); the discrete
+    solution is an FP64 solve to 1e-12 from the FMG result."""
+    import torch
+    import workloads as W
+    import paper_1511_02134_amd as P
+
+    cfg = W.WORKLOADS[6].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, R, nu1=2, nu2=2, cycle=1)
+    dev = torch.device("cuda")
+    xs0, bs = [], []
+    for l in range(s.L + 1):
+        c = cfg.with_R(2 + l)
+        _, dmask = s.node_info(l)
+        x0 = torch.zeros(4, s.num_nodes(l), dtype=torch.float64, device=dev)
+        x0[:3] = torch.where(torch.tensor(dmask, device=dev)[None, :],
+                             torch.tensor(c.dirichlet_field(), device=dev), 0.0)
+        xs0.append(s.scatter(x0, l))
+        bs.append(s.rhs_level(s.scatter(torch.tensor(c.forcing_field(), device=dev), l), l))
+    xs = [torch.empty_like(x) for x in xs0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    _, dmask = s.node_info(s.L)
+    ex = torch.tensor(cfg.exact_solution(), device=dev)
+    mass = torch.tensor(s.mass_weights(), device=dev)
+    h = 2.0 ** -R
+
+    def hnorm(d):
+        d = d.clone()
+        d[3] -= (mass * d[3]).sum() / mass.sum()
+        return float(torch.sqrt((d[:3] ** 2).sum() + h * h * (d[3] ** 2).sum()))
+
+    yk = torch.empty_like(xs0[-1])
+    times = []
+    for _ in range(25):
+        ev[0].record()
+        s.apply(xs0[-1], None, out=yk)
+        ev[1].record()
+        torch.cuda.synchronize()
+        times.append(ev[0].elapsed_time(ev[1]))
+    t_apply = float(np.median(times[5:]))
+    xdisc = None
+    for cycles in (1, 2):
+        t = []
+        for k in range(warmup + steps):
+            for a, b0 in zip(xs, xs0):
+                a.copy_(b0)
+            torch.cuda.synchronize()
+            ev[0].record()
+            s.fmg(xs, bs, cycles)
+            ev[1].record()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                t.append(ev[0].elapsed_time(ev[1]))
+        xf = s.gather(xs[-1])
+        if xdisc is None:
+            xd = xs[-1].clone()
+            info = s.solve(xd, bs[-1], rtol=1e-12, max_cycles=100)
+            xdisc = s.gather(xd)
+        disc = hnorm(ex - xdisc)
+        ms = float(np.median(t))
+        out["FMG" if cycles == 1 else "2FMG"] = {
+            "ms": ms, "work_units": ms / t_apply,
+            "gamma": hnorm(ex - xf) / disc,
+            "algebraic_error_h": hnorm(xf - xdisc) / hnorm(xdisc)}
+    line = {"metric": "FMG Vvar(2,2) time in work units (TME factor) and error ratio gamma",
+            "workload": cfg.name, "refinements": R, "dofs": s.num_dofs(),
+            "t_apply_ms": t_apply, "model_E_TME": 9.07, "data": "synthetic (analytic solution)",
+            **out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,9 +217,14 @@ def main():
                     help="refinements of the oracle's bounded sample")
     ap.add_argument("--ops", action="store_true",
                     help="run the operation sequence used for counter collection and exit")
+    ap.add_argument("--tme", type=int, default=0, metavar="R",
+                    help="full multigrid efficiency study at R refinements (prints its own line)")
     args = ap.parse_args()
     if args.ops:
         run_ops(args.workload)
+        return
+    if args.tme:
+        run_tme(args.tme, max(args.steps, 3), args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -243,7 +324,8 @@ def main():
         "t_apply_ms": t_apply,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_colour<double,velocity> (finest level)",
+            "kernel": (f"k_colour<{'double' if precision == 0 else 'float'},velocity> "
+                       f"(finest level)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

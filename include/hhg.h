@@ -173,6 +173,11 @@ hhg_status hhg_exchange(hhg_ctx* ctx, int32_t level, void* d_x, int32_t nfields,
  * P1 interpolant of the forcing: d_rhs = (M f on free velocity rows,
  * g_l(I_h f) on pressure rows).  d_f: 3 fields in the internal layout. */
 hhg_status hhg_rhs(hhg_ctx* ctx, const void* d_f, void* d_rhs, hhg_stream stream);
+/* The same on level l (0..L), from the forcing interpolated at that level's
+ * vertices (3 fields, internal layout of level l); the right-hand sides of
+ * full multigrid. */
+hhg_status hhg_rhs_level(hhg_ctx* ctx, int32_t level, const void* d_f, void* d_rhs,
+                         hhg_stream stream);
 
 /* y = K x (eq. linear-system) on level l: rows of free velocity nodes and all
  * pressure rows; Dirichlet velocity rows of y are 0.  x must not alias y. */
@@ -214,6 +219,18 @@ hhg_status hhg_project(hhg_ctx* ctx, int32_t level, void* d_x, hhg_stream stream
  * followed by the mean-zero projection.  In mixed precision the cycle runs
  * in FP32 on the FP64 residual scaled by its norm (iterative refinement). */
 hhg_status hhg_vcycle(hhg_ctx* ctx, void* d_x, const void* d_b, hhg_stream stream);
+/* Full multigrid (Section 5, Figure "FMG"): d_x[l], d_b[l] (host arrays of
+ * L+1 device pointers, internal layout of level l) hold on input the
+ * Dirichlet values of level l in x's boundary velocity slots and the level's
+ * right-hand side.  Level 0 is solved exactly (from those Dirichlet values);
+ * then, for l = 1..L, x_l = P x_(l-1) on every slot but the Dirichlet
+ * velocity ones, followed by `cycles` V-cycles whose top level is l (in the
+ * variable cycle, level k below the top smooths 2 (l - k) more steps), each
+ * followed by the mean-zero projection.  Every other slot of the d_x[l] is
+ * overwritten; x_L is the result.  FP64 only (opts.precision 0): HHG_EINVAL
+ * otherwise, and for cycles outside 1..16 or aliasing pointers. */
+hhg_status hhg_fmg(hhg_ctx* ctx, void* const* d_x, const void* const* d_b, int32_t cycles,
+                   hhg_stream stream);
 /* Cycles from x until ||b - K x||_2 <= rtol ||b - K x_0||_2 (Section 3.6) or
  * max_cycles (<= 255).  Synchronises once per cycle (an 8-byte readback).
  * Returns HHG_ENOCONV if the tolerance was not met, HHG_ENAN on a non-finite

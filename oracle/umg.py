@@ -176,22 +176,46 @@ class UMG:
         return x
 
     # -- cycle -----------------------------------------------------------------
-    def steps(self, l):
-        extra = 2 * (self.L - l) if self.variable else 0
+    def steps(self, l, top=None):
+        """Smoothing steps on level l of a cycle whose top level is `top`: the
+        variable V-cycle adds two per level below the top (Section 3.5)."""
+        top = self.L if top is None else top
+        extra = 2 * (top - l) if self.variable else 0
         return self.nu1 + extra, self.nu2 + extra
 
-    def vcycle(self, l, x, b):
+    def vcycle(self, l, x, b, top=None):
         if l == 0:
             return x + self.coarse_solve(self.residual(0, x, b))
-        pre, post = self.steps(l)
+        pre, post = self.steps(l, top)
         for _ in range(pre):
             self.uzawa(l, x, b)
         bc = self.restrict(l, self.residual(l, x, b))
-        ec = self.vcycle(l - 1, np.zeros_like(bc), bc)
+        ec = self.vcycle(l - 1, np.zeros_like(bc), bc, top)
         x += self.prolong(l, ec)
         for _ in range(post):
             self.uzawa(l, x, b)
         return x
+
+    def fmg(self, bs, xbc, cycles=1):
+        """Full multigrid (Section 5, Figure "FMG"): bs[l] the right-hand side
+        and xbc[l] the Dirichlet velocity values of level l.  Level 0 is solved
+        exactly; every finer level starts from the interpolated solution of the
+        level below (its Dirichlet values restored) and runs `cycles` V-cycles
+        with itself as the top level, each followed by the projection.
+        Returns the solutions of all levels."""
+        lv = self.H.levels[0]
+        x = np.zeros((4, lv.N))
+        x[:3, lv.dirichlet] = xbc[0][:3, lv.dirichlet]
+        x = self.project(x + self.coarse_solve(self.residual(0, x, bs[0])), 0)
+        xs = [x]
+        for l in range(1, self.L + 1):
+            lv = self.H.levels[l]
+            x = self.prolong(l, x)
+            x[:3, lv.dirichlet] = xbc[l][:3, lv.dirichlet]
+            for _ in range(cycles):
+                x = self.project(self.vcycle(l, x, bs[l], top=l), l)
+            xs.append(x)
+        return xs
 
     def project(self, x, l=None):
         lv = self.H.levels[self.L if l is None else l]

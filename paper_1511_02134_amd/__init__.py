@@ -82,6 +82,8 @@ def _load():
         "hhg_gather": (S, [P, I32, P, I32, P, P]),
         "hhg_exchange": (S, [P, I32, P, I32, P]),
         "hhg_rhs": (S, [P, P, P, P]),
+        "hhg_rhs_level": (S, [P, I32, P, P, P]),
+        "hhg_fmg": (S, [P, P, P, I32, P]),
         "hhg_apply": (S, [P, I32, P, P, P]),
         "hhg_residual": (S, [P, I32, P, P, P, ctypes.POINTER(D), P]),
         "hhg_smooth": (S, [P, I32, P, P, I32, P]),
@@ -110,7 +112,8 @@ lib = _load()
 ABI_FUNCTIONS = ("hhg_default_opts", "hhg_plan", "hhg_create", "hhg_destroy", "hhg_last_error",
                  "hhg_global_error", "hhg_num_levels", "hhg_vec_len", "hhg_num_nodes",
                  "hhg_num_dofs", "hhg_num_interface", "hhg_node_info", "hhg_mass_weights", "hhg_check_layout", "hhg_scatter",
-                 "hhg_gather", "hhg_exchange", "hhg_rhs", "hhg_apply", "hhg_residual",
+                 "hhg_gather", "hhg_exchange", "hhg_rhs", "hhg_rhs_level", "hhg_fmg",
+                 "hhg_apply", "hhg_residual",
                  "hhg_smooth", "hhg_restrict", "hhg_prolong_add", "hhg_coarse_solve",
                  "hhg_project", "hhg_vcycle", "hhg_solve", "hhg_grad", "hhg_set_viscosity",
                  "hhg_set_timing", "hhg_kernel_time")
@@ -264,6 +267,22 @@ class Solver:
         b = self.vector()
         _check(lib.hhg_rhs(self.ctx, _ptr(f_internal), _ptr(b), _stream()), self.ctx)
         return b
+
+    def rhs_level(self, f_internal, level):
+        """Right-hand side on `level` from the forcing at that level's vertices."""
+        b = self.vector(level)
+        _check(lib.hhg_rhs_level(self.ctx, level, _ptr(f_internal), _ptr(b), _stream()), self.ctx)
+        return b
+
+    def fmg(self, xs, bs, cycles=1):
+        """Full multigrid over per-level iterates xs[l] (holding the level's
+        Dirichlet values) and right-hand sides bs[l]; xs[-1] is the result."""
+        n = self.L + 1
+        if len(xs) != n or len(bs) != n:
+            raise ValueError(f"need {n} iterates and right-hand sides")
+        px = (ctypes.c_void_p * n)(*[_ptr(x) for x in xs])
+        pb = (ctypes.c_void_p * n)(*[_ptr(b) for b in bs])
+        _check(lib.hhg_fmg(self.ctx, px, pb, cycles, _stream()), self.ctx)
 
     def apply(self, x, level=None, out=None):
         level = self.L if level is None else level

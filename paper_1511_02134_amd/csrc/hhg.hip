@@ -690,8 +690,10 @@ void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
                        v.cx + 3 * cs, cs, c->scal + 4, c->inv_mass[l]);
 }
 
+// V-cycle from level l whose top level is `top` (the variable cycle adds
+// 2 (top - l) smoothing steps on level l)
 template <typename T>
-void vcycle(hhg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
+void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     T *xl, *bl, *rl, *tl;
     vecs<T>(c, l, &xl, &bl, &rl, &tl);
     if (l == 0) {
@@ -704,7 +706,7 @@ void vcycle(hhg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
     }
     // the mirror of x is current on entry (refreshed, filled, or written by
     // the previous cycle's sweeps and projection) and the sweeps keep it so
-    const int extra = c->opts.cycle == 1 ? 2 * (c->L - l) : 0;
+    const int extra = c->opts.cycle == 1 ? 2 * (top - l) : 0;
     for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
     residual_mirror<T>(c, l, x, b, rl, s);
     T *xc, *bc, *rc, *tc;
@@ -714,7 +716,7 @@ void vcycle(hhg_ctx* c, int l, T* x, const T* b, hipStream_t s) {
         coarse_solve<T>(c, bc, xc, s);
     } else {
         fill_iterate<T>(c, l - 1, xc, s);
-        vcycle<T>(c, l - 1, xc, bc, s);
+        vcycle<T>(c, l - 1, top, xc, bc, s);
     }
     prolong_add<T>(c, l, xc, x, s);
     for (int q = 0; q < c->opts.nu2 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
@@ -893,6 +895,17 @@ hhg_status hhg_rhs(hhg_ctx* c, const void* f, void* rhs, hhg_stream stream) {
     return HHG_OK;
 }
 
+hhg_status hhg_rhs_level(hhg_ctx* c, int32_t l, const void* f, void* rhs, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, f);
+    CHECK_PTR(c, rhs);
+    if (f == rhs) return fail(c, HHG_EINVAL, "f and rhs must not alias");
+    full_pass<double, MODE_RHS>(c, l, (const double*)f, nullptr, (double*)rhs, (hipStream_t)stream);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
 hhg_status hhg_apply(hhg_ctx* c, int32_t l, const void* x, void* y, hhg_stream stream) {
     CHECK_DEV(c);
     CHECK_LEVEL(c, l);
@@ -991,7 +1004,7 @@ namespace {
 // one solver iteration on the finest level; on entry of the mixed variant
 // r64_L must hold b - K x and scal[0] its norm
 void cycle_fp64(hhg_ctx* c, double* x, const double* b, hipStream_t s) {
-    vcycle<double>(c, c->L, x, b, s);
+    vcycle<double>(c, c->L, c->L, x, b, s);
     project<double>(c, c->L, x, s);
 }
 
@@ -1002,7 +1015,7 @@ void cycle_mixed(hhg_ctx* c, double* x, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, a.r64, c->scal,
                        a.b32, n4);
     fill_iterate<float>(c, L, a.x32, s);
-    vcycle<float>(c, L, a.x32, a.b32, s);
+    vcycle<float>(c, L, L, a.x32, a.b32, s);
     hipLaunchKernelGGL(k_axpy_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, c->scal, a.x32,
                        n4);
     project<double>(c, L, x, s);
@@ -1024,6 +1037,43 @@ hhg_status hhg_vcycle(hhg_ctx* c, void* x, const void* b, hhg_stream stream) {
     } else {
         mirror_refresh<double>(c, c->L, (const double*)x, s);
         cycle_fp64(c, (double*)x, (const double*)b, s);
+    }
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_fmg(hhg_ctx* c, void* const* xs, const void* const* bs, int32_t cycles,
+                   hhg_stream stream) {
+    CHECK_DEV(c);
+    if (!xs || !bs) return fail(c, HHG_EINVAL, "level pointer arrays are NULL");
+    if (c->opts.precision != 0) return fail(c, HHG_EINVAL, "full multigrid runs in FP64 only");
+    if (cycles < 1 || cycles > 16) return fail(c, HHG_EINVAL, "cycles must be 1..16");
+    for (int l = 0; l <= c->L; ++l) {
+        CHECK_PTR(c, xs[l]);
+        CHECK_PTR(c, bs[l]);
+        if (xs[l] == bs[l]) return fail(c, HHG_EINVAL, "x and b of a level must not alias");
+        for (int q = 0; q < l; ++q)
+            if (xs[q] == xs[l]) return fail(c, HHG_EINVAL, "iterates of two levels alias");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // level 0: x_0 = x_D + K_0^-1 (b_0 - K_0 x_D) from the Dirichlet values alone
+    {
+        LevelDev<double>& v = view<double>(c, 0);
+        hipLaunchKernelGGL(k_keep_dirichlet<double>, dim3(grid_for((size_t)v.len)), dim3(TPB), 0, s, v,
+                           (double*)xs[0]);
+        vcycle<double>(c, 0, 0, (double*)xs[0], (const double*)bs[0], s);
+        project<double>(c, 0, (double*)xs[0], s);
+    }
+    for (int l = 1; l <= c->L; ++l) {
+        LevelDev<double>& F = view<double>(c, l);
+        LevelDev<double>& C = view<double>(c, l - 1);
+        // x_l = P x_(l-1) (Dirichlet velocity kept); writes the mirror of x_l too
+        hipLaunchKernelGGL((k_prolong<double, true>), dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s, F,
+                           C, (const double*)xs[l - 1], (double*)xs[l]);
+        for (int q = 0; q < cycles; ++q) {
+            vcycle<double>(c, l, l, (double*)xs[l], (const double*)bs[l], s);
+            project<double>(c, l, (double*)xs[l], s);
+        }
     }
     LAUNCH_CHECK(c);
     return HHG_OK;

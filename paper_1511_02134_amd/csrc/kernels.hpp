@@ -728,7 +728,9 @@ __host__ __device__ __forceinline__ void parity_dir(int pat, int* di, int* dj, i
     }
 }
 
-template <typename T>
+// SET (full multigrid): x_f = P e_c instead of x_f += P e_c, except on the
+// velocity slots of Dirichlet vertices, which keep their values.
+template <typename T, bool SET = false>
 __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
                                                  const T* __restrict__ ec, T* __restrict__ xf) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
@@ -748,12 +750,19 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     // computes the same value, so concurrent writes of its entry agree)
     const int cm = near_boundary(n, i, j, k) ? F.comp_of_slot[sf] : -1;
     const size_t cs = (size_t)F.cstride;
+    // velocity slots kept by SET: those of Dirichlet vertices (interface
+    // vertices, so their mirror entry is their list index)
+    const bool keep = SET && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 1);
     const int pi = i & 1, pj = j & 1, pk = k & 1;
     if ((pi | pj | pk) == 0) {
         const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            const T v = xf[f * lf + sf] + ec[f * lc + sc];
+            T v = ec[f * lc + sc];
+            if (!SET)
+                v += xf[f * lf + sf];
+            else if (keep && f < 3)
+                v = xf[f * lf + sf];
             xf[f * lf + sf] = v;
             if (cm >= 0) F.cx[f * cs + cm] = v;
         }
@@ -765,10 +774,29 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        const T v = xf[f * lf + sf] + T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+        T v = T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+        if (!SET)
+            v += xf[f * lf + sf];
+        else if (keep && f < 3)
+            v = xf[f * lf + sf];
         xf[f * lf + sf] = v;
         if (cm >= 0) F.cx[f * cs + cm] = v;
     }
+}
+
+// Level-0 start of full multigrid: every slot but the velocity slots of
+// Dirichlet vertices set to zero.
+template <typename T>
+__global__ void k_keep_dirichlet(LevelDev<T> L, T* __restrict__ x) {
+    const size_t s = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (s >= (size_t)L.len) return;
+    const int cm = L.comp_of_slot[s];
+    const bool dir = cm >= 0 && cm < L.nif && (L.if_flag[cm] & 1);
+    const size_t len = (size_t)L.len;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        if (!dir) x[f * len + s] = T(0);
+    x[3 * len + s] = T(0);
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,8 @@ tetrahedra, Section 4 and Table "iteration numbers and time-to-solution"):
   5  channel [0,4]x[0,1]^2, 24 macros, R=7, parabolic inflow at x=0, natural
      outflow at x=4, no-slip walls, f=0, nu_e log-uniform in [0.5, 2] (seed 5),
      observation viscosity seed 52, mixed precision forward + adjoint
+  6  unit cube, 6 macros, R=7, the analytic solution of the efficiency study
+     (Section 5) with its forcing and Dirichlet data, fp64 full multigrid
 """
 from __future__ import annotations
 
@@ -142,6 +144,32 @@ def manufactured_forcing(x, nu: float = 1.0):
     return -nu * lap_u + 1.0
 
 
+def tme_velocity(x):
+    """[3,N] analytic velocity of the efficiency study (Section 5):
+    u = (-4 cos 4z, 8 cos 8x, -2 cos 2y), divergence free."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    return np.stack([-4.0 * np.cos(4.0 * Z), 8.0 * np.cos(8.0 * X), -2.0 * np.cos(2.0 * Y)])
+
+
+def tme_pressure(x):
+    """[N] analytic pressure of the efficiency study: sin 4x sin 8y sin 2z minus
+    its mean over the unit cube."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    mean = ((1.0 - np.cos(4.0)) / 4.0) * ((1.0 - np.cos(8.0)) / 8.0) * ((1.0 - np.cos(2.0)) / 2.0)
+    return np.sin(4.0 * X) * np.sin(8.0 * Y) * np.sin(2.0 * Z) - mean
+
+
+def tme_forcing(x):
+    """[3,N] f = -Laplace(u) + grad(p) (nu = 1) of the efficiency study."""
+    X, Y, Z = x[:, 0], x[:, 1], x[:, 2]
+    s4x, c4x = np.sin(4.0 * X), np.cos(4.0 * X)
+    s8y, c8y = np.sin(8.0 * Y), np.cos(8.0 * Y)
+    s2z, c2z = np.sin(2.0 * Z), np.cos(2.0 * Z)
+    return np.stack([-64.0 * np.cos(4.0 * Z) + 4.0 * c4x * s8y * s2z,
+                     512.0 * np.cos(8.0 * X) + 8.0 * s4x * c8y * s2z,
+                     -8.0 * np.cos(2.0 * Y) + 2.0 * s4x * s8y * c2z])
+
+
 def fourier_forcing(x, seed: int, modes: int = 8):
     """f = sum_m d_m sin(pi k_m . x + phi_m): k_m in {1,2,3}^3, phi_m ~ U[0, 2 pi),
     d_m a random unit vector (amplitude 1).  Returns [3,N]."""
@@ -209,6 +237,7 @@ class Workload:
     forcing_seed: int | None = None
     noise_sigma: float = 0.0
     inflow: bool = False
+    solution: str | None = None     # "tme": the analytic solution of the efficiency study
     extra: dict = field(default_factory=dict)
 
     # -- inputs ----------------------------------------------------------
@@ -241,14 +270,26 @@ class Workload:
             return fourier_forcing(x, self.forcing_seed)
         if self.forcing == "zero":
             return np.zeros((3, x.shape[0]))
+        if self.forcing == "tme":
+            return tme_forcing(x)
         raise ValueError(self.forcing)
 
     def dirichlet_field(self):
-        """[3,N] Dirichlet velocity values (inflow profile or zero)."""
+        """[3,N] Dirichlet velocity values (inflow profile, the analytic
+        velocity, or zero)."""
         x = self.points()
         if self.inflow:
             return inflow_profile(x)
+        if self.solution == "tme":
+            return tme_velocity(x)
         return np.zeros((3, x.shape[0]))
+
+    def exact_solution(self):
+        """[4,N] nodal values of the analytic solution, if the workload has one."""
+        x = self.points()
+        if self.solution == "tme":
+            return np.concatenate([tme_velocity(x), tme_pressure(x)[None, :]])
+        raise ValueError("workload has no analytic solution")
 
     def observation_viscosity(self):
         _, _, nu, _ = self.mesh()
@@ -264,4 +305,5 @@ WORKLOADS = {
                 nu_seed=4, nu_obs_seed=42, forcing="fourier", forcing_seed=41),
     5: Workload("channel4-R7-adjoint-mixed", a=4, R=7, precision="mixed", natural_x=4.0,
                 nu_range=(0.5, 2.0), nu_seed=5, nu_obs_seed=52, forcing="zero", inflow=True),
+    6: Workload("unit-cube-tme-R7-fp64", a=1, R=7, precision="fp64", forcing="tme", solution="tme"),
 }
