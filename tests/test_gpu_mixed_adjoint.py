@@ -106,10 +106,13 @@ def test_adjoint_gradient_matches_oracle(cid, R):
     assert np.abs(gnu_gpu - gnu).max() <= 1e-8 * np.abs(gnu).max()
 
 
-@pytest.mark.parametrize("cid,R,precision", [(4, 4, 0), (5, 4, 1)])
+@pytest.mark.parametrize("cid,R,precision", [(4, 4, 0), (5, 4, 1), (4, 6, 0), (5, 7, 1)])
 def test_adjoint_gradient_matches_finite_differences(cid, R, precision):
     """Central differences with eps = 1e-6 per macro viscosity, forward solves
-    driven to rtol 1e-13 (1e-11 with FP32 cycles); gradients within 1e-6."""
+    driven to rtol 1e-13 (1e-12 with FP32 cycles); gradients within 1e-6.
+    The last two cases are the full box (R = 6, FP64) and the full channel
+    (R = 7, FP32 cycles in FP64 refinement) in the solver's default launch
+    configuration."""
     from paper_1511_02134_amd.autograd import StokesSolve
     _announce(f"finite differences config {cid} R={R} precision={precision}")
     rtol = 1e-13 if precision == 0 else 1e-12
