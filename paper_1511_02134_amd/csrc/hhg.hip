@@ -525,6 +525,28 @@ inline int full_vblocks(int mode, int n_vtiles) {
     return quad_lanes(mode) ? n_vtiles : full_blocks(n_vtiles);
 }
 
+// levels with at least this many intervals per macro edge launch the volume
+// and the interface blocks of K x and the residual separately: the volume
+// kernel is then not held to the interface lanes' register budget
+constexpr int SPLIT_MIN_N = 64;
+
+// K x or the residual (MODE_APPLY / MODE_RES); MIRROR: interface taps from
+// the level's mirror of x
+template <typename T, int MODE, bool MIRROR>
+void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
+    if (v.n >= SPLIT_MIN_N) {
+        // volume launch: one vertex per lane (four blocks per tile)
+        hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1>), dim3(full_blocks(v.n_vtiles)),
+                           dim3(TPB), 0, s, v, x, b, y, c->partials, 0, (T*)nullptr, -1, T(0));
+        if (ib > 0)
+            hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 2>), dim3(ib), dim3(TPB), 0, s, v,
+                               x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+        return;
+    }
+    hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s, v, x,
+                       b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+}
+
 template <typename T, int MODE>
 void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
@@ -534,8 +556,11 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
     Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
              bytes);
-    hipLaunchKernelGGL((k_full<T, MODE, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y,
-                       c->partials, ib, (T*)nullptr, -1, T(0));
+    if (MODE == MODE_APPLY || MODE == MODE_RES)
+        launch_kx<T, (MODE == MODE_RES ? MODE_RES : MODE_APPLY), false>(c, v, ib, x, b, y, s);
+    else
+        hipLaunchKernelGGL((k_full<T, MODE, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y,
+                           c->partials, ib, (T*)nullptr, -1, T(0));
 }
 
 // residual of the level's smoothed iterate: interface taps from its mirror
@@ -545,8 +570,8 @@ void residual_mirror(hhg_ctx* c, int l, const T* x, const T* b, T* r, hipStream_
     const int ib = iface_blocks(v.nif);
     const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
     Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
-    hipLaunchKernelGGL((k_full<T, MODE_RES, false, true>), dim3(grid), dim3(TPB), 0, s, v, x, b, r,
-                       c->partials, ib, (T*)nullptr, -1, T(0));
+    (void)grid;
+    launch_kx<T, MODE_RES, true>(c, v, ib, x, b, r, s);
 }
 
 // mirror of x taken afresh (entry points that smooth a caller's vector)
@@ -638,11 +663,14 @@ void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out,
     } else {
         const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
         Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
-        hipLaunchKernelGGL((k_full<T, MODE_RES, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b,
-                           r, c->partials, ib, (T*)nullptr, -1, T(0));
+        (void)grid;
+        launch_kx<T, MODE_RES, false>(c, v, ib, x, b, r, s);
     }
+    // partial sums: per tile (one block per tile) or per tile and sub-row
+    // (split launches, one vertex per lane), then per interface block
+    const int nvol = (v.n >= SPLIT_MIN_N ? 4 : 1) * v.nv_nat;
     hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
-                       v.nv_nat + (v.nif + TPB - 1) / TPB, out, 1);
+                       nvol + (v.nif + TPB - 1) / TPB, out, 1);
 }
 
 template <typename T>

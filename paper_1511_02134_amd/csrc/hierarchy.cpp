@@ -578,6 +578,47 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
     return compute_stencils(mi, &L, err);
 }
 
+// An interior stencil of the Kuhn lattice is invariant under x -> -x of the
+// offsets: in the local tap order the 14 neighbours come in opposite pairs
+// (2q+1, 2q+2), and A, C and M are symmetric over a pair, B_k antisymmetric,
+// and B^T_k(d) = B_k(-d).  Checked to round-off and then made exact, so that
+// kernels may evaluate interior rows from pair sums and differences.
+static bool pair_symmetries(double* r, std::string* err) {
+    auto fail_sym = [&](const char* what) {
+        *err = std::string("internal error: interior stencil not pair-symmetric (") + what + ")";
+        return false;
+    };
+    for (int blk : {ST_A, ST_C, ST_M}) {
+        double sc = 0.0;
+        for (int g = 0; g < 15; ++g) sc = std::max(sc, std::fabs(r[blk + g]));
+        for (int q = 0; q < 7; ++q) {
+            double& a = r[blk + 2 * q + 1];
+            double& b = r[blk + 2 * q + 2];
+            if (std::fabs(a - b) > 1e-12 * sc) return fail_sym("A, C or M");
+            a = b = 0.5 * (a + b);
+        }
+    }
+    for (int f = 0; f < 3; ++f) {
+        double* B = r + ST_B + 15 * f;
+        double* BT = r + ST_BT + 15 * f;
+        double sc = 0.0;
+        for (int g = 0; g < 15; ++g) sc = std::max(sc, std::max(std::fabs(B[g]), std::fabs(BT[g])));
+        if (B[0] != 0.0 || BT[0] != 0.0) return fail_sym("divergence centre");
+        for (int q = 0; q < 7; ++q) {
+            const int d = 2 * q + 1, e = 2 * q + 2;
+            if (std::fabs(B[d] + B[e]) > 1e-12 * sc || std::fabs(BT[d] - B[e]) > 1e-12 * sc ||
+                std::fabs(BT[e] - B[d]) > 1e-12 * sc)
+                return fail_sym("B");
+            const double v = 0.5 * (B[d] - B[e]);
+            B[d] = v;
+            B[e] = -v;
+            BT[d] = -v;
+            BT[e] = v;
+        }
+    }
+    return true;
+}
+
 bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
     HostLevel& L = *Lp;
     const int nm = L.nm, n = L.n;
@@ -611,6 +652,7 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
         double* loc = &L.st[(size_t)m * ST_SIZE];
         to_local(M, g.data(), loc, 15);   // A, C, M, B(3), BT(3), G(3), GT(3)
         for (int q = ST_INVA; q < ST_SIZE; ++q) loc[q] = g[q];
+        if (!pair_symmetries(loc, err)) return false;
     }
     // interface stencils: every tetrahedron around the vertex belongs to the
     // macro whose closure contains its centroid strictly

@@ -361,6 +361,62 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
     out[3] = MODE == MODE_RES ? b[3 * bs + bslot] - kp : kp;
 }
 
+// Interior rows of K x or of the residual from the pair symmetries of an
+// interior stencil (A and C symmetric, B_k antisymmetric and B^T_k(d) =
+// B_k(-d) over the opposite taps (2q+1, 2q+2); checked and made exact when the
+// records are built): with pair sums for the three axis pairs (taps 1-2, 3-4,
+// 7-8, where A and C live) and pair differences for all seven pairs, 29
+// coefficients and half the products of the general row.
+template <typename T, int MODE>
+__device__ __forceinline__ void eval_vol_pairs(const T* __restrict__ st, const int* s,
+                                               const T* __restrict__ x, const T* __restrict__ b,
+                                               size_t len, T out[4]) {
+    uint32_t o[15];
+#pragma unroll
+    for (int g = 0; g < 15; ++g) o[g] = (uint32_t)s[g] * (uint32_t)sizeof(T);
+    T ku[3], kp;
+    {
+        const T* p = x + 3 * len;
+        const T p0 = ldo(p, o[0]);
+        T pd[7], ps[3];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const T a = ldo(p, o[2 * q + 1]), c = ldo(p, o[2 * q + 2]);
+            pd[q] = a - c;
+            if (q == 0) ps[0] = a + c;
+            if (q == 1) ps[1] = a + c;
+            if (q == 3) ps[2] = a + c;
+        }
+        kp = -(st[ST_C] * p0 + st[ST_C + 1] * ps[0] + st[ST_C + 3] * ps[1] + st[ST_C + 7] * ps[2]);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T acc = T(0);
+#pragma unroll
+            for (int q = 0; q < 7; ++q) acc += st[ST_BT + 15 * f + 2 * q + 1] * pd[q];
+            ku[f] = acc;
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* u = x + f * len;
+        const T u0 = ldo(u, o[0]);
+        T bu = T(0), us[3];
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const T a = ldo(u, o[2 * q + 1]), c = ldo(u, o[2 * q + 2]);
+            bu += st[ST_B + 15 * f + 2 * q + 1] * (a - c);
+            if (q == 0) us[0] = a + c;
+            if (q == 1) us[1] = a + c;
+            if (q == 3) us[2] = a + c;
+        }
+        ku[f] += st[ST_A] * u0 + st[ST_A + 1] * us[0] + st[ST_A + 3] * us[1] + st[ST_A + 7] * us[2];
+        kp += bu;
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) out[f] = MODE == MODE_RES ? b[f * len + s[0]] - ku[f] : ku[f];
+    out[3] = MODE == MODE_RES ? b[3 * len + s[0]] - kp : kp;
+}
+
 template <int MODE>
 __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
     f0 = 0;
@@ -523,19 +579,24 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
 }
 
 // WIN (RU and BP only): one block per tile, a quad per lane, quad windows.
-template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false>
+// PART 1 / 2: a launch of the volume blocks only (ib = 0) or of the interface
+// blocks only (grid = ib); each then gets the registers of its own branch.
+template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false, int PART = 0>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
     static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP, "quad windows: RU and BP");
+    if (PART == 1) ib = 0;
+    // volume block or interface block (decided at compile time for PART 1, 2)
+    const bool vol = PART == 1 ? true : PART == 2 ? false : (int)blockIdx.x >= ib;
     __shared__ double sh[4];
     const size_t len = (size_t)L.len;
     int f0, f1;
     mode_fields<MODE>(f0, f1);
     double ss = 0.0;
     int slot = -1;   // partial-sum slot of this block
-    if (WIN && (int)blockIdx.x >= ib) {
+    if (WIN && vol) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
         if (tl.macro >= 0) {
             const int n = L.n, k = tl.k, mm = n - k;
@@ -572,7 +633,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 }
             }
         }
-    } else if (quad_lanes(MODE) && (int)blockIdx.x >= ib) {
+    } else if (quad_lanes(MODE) && PART == 0 && vol) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
         slot = tl.nat;
         if (tl.macro >= 0) {
@@ -590,7 +651,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
+                    if (MODE == MODE_APPLY || MODE == MODE_RES)
+                        eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
+                    else
+                        eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
@@ -598,7 +662,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 }
             }
         }
-    } else if ((int)blockIdx.x >= ib) {
+    } else if (vol) {
         const int v = (int)blockIdx.x - ib;
         const int ti = full_tile(v), r = full_sub(v);
         if (ti < L.n_vtiles) {
@@ -615,7 +679,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
+                    if (MODE == MODE_APPLY || MODE == MODE_RES)
+                        eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
+                    else
+                        eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
@@ -630,7 +697,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             }
         }
     } else {
-        if ((int)blockIdx.x * TPB < L.nif) slot = (quad_lanes(MODE) ? 1 : 4) * L.nv_nat + (int)blockIdx.x;
+        if ((int)blockIdx.x * TPB < L.nif)
+            slot = (quad_lanes(MODE) && PART == 0 ? 1 : 4) * L.nv_nat + (int)blockIdx.x;
         const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
