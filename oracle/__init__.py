@@ -15,6 +15,11 @@ coarse solves.  It follows the paper's formulas in the paper's order:
                 right-hand side f and g_l, transfer operator (Section 2.1)
   umg.py     -- inexact Uzawa smoother (eq. Uzawa_smooth), V-cycle, coarse
                 solve, stopping criterion (Sections 3.3-3.6)
+  krylov.py  -- velocity multigrid with (FHGS, BHGS) smoothing, block-diagonal
+                PMINRES and the Schur-complement CG of Algorithm 1
+                (Sections 3.1, 3.2, 3.5)
+  rows.py    -- single rows of the system at chosen vertices (full-size checks)
+  cost.py    -- operator counts, E_TME and memory models (Sections 4.1, 4.2, 5)
   adjoint.py -- gradients of J = 1/2 ||u - u_obs||^2 with respect to the
                 forcing and the per-macro viscosity (not in the paper; the
                 discrete adjoint of the same symmetric system)

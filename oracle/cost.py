@@ -72,3 +72,36 @@ def memory_bytes(L: int, vectors: int = 3, bytes_per_value: int = 8) -> float:
     n = 2 ** (L + 2)
     dofs = 4 * (n - 1) ** 3
     return vectors * dofs * sum(level_weight(l, L) for l in range(L + 1)) * bytes_per_value
+
+
+def velocity_cycle_ops(L: int, nu1: int, nu2: int) -> float:
+    """Weighted A evaluations of one velocity V(nu1, nu2) cycle with (FHGS,
+    BHGS) smoothing (Section 3.5, Table "settings"): a forward or backward
+    sweep over all colours applies A once, the residual before restriction
+    once more, on every level (the same per-level convention as the UMG sums
+    of Section 4.2, which include level 0)."""
+    return sum(level_weight(l, L) * (nu1 + nu2 + 1) for l in range(L + 1))
+
+
+def pminres_ops(L: int, iterations: int, nu: int = 1) -> dict:
+    """Operator evaluations of block-diagonal PMINRES (Section 3.2): the
+    initial residual and every iteration apply K once (A once, B and B^T,
+    C once) and the preconditioner once (a velocity V(nu, nu) cycle and the
+    lumped mass M)."""
+    k = iterations + 1
+    return {"A": k * (1.0 + velocity_cycle_ops(L, nu, nu)), "B": 2.0 * k, "C": float(k),
+            "M": float(k)}
+
+
+def scg_ops(L: int, outer: int, n_A: int = 3, n_S: int = 3, n_I: int = 1, nu: int = 3) -> dict:
+    """Operator evaluations of the Schur-complement CG (Algorithm 1) with
+    `outer` outer iterations: per outer iteration B^T p for the velocity
+    right-hand side, n_A velocity V(nu, nu) cycles, the Schur residual
+    B u - C p - g and its preconditioning by M, then n_S CG steps each with
+    B^T d, n_I cycles, B w, C d and M; the stopping test applies K once per
+    outer iteration and once at the start."""
+    cyc = velocity_cycle_ops(L, nu, nu)
+    return {"A": (outer + 1) + outer * (n_A + n_S * n_I) * cyc,
+            "B": 2.0 * (outer + 1) + outer * (2 + 2 * n_S),
+            "C": (outer + 1) + outer * (1 + n_S),
+            "M": float(outer * (1 + n_S))}
