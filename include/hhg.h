@@ -99,6 +99,9 @@ typedef struct {
                               (computed once at set-up; one matrix-vector product
                               per solve; default, at most 8192 level-0 unknowns);
                               1: the block-diagonal preconditioned MINRES above */
+    int32_t krylov;       /* 1: reserve the ten finest-level vectors (4 fields each) of
+                             hhg_pminres and hhg_scg; 0 (default): those calls return
+                             HHG_EINVAL */
 } hhg_opts;
 
 /* Result of hhg_solve. */
@@ -237,6 +240,47 @@ hhg_status hhg_fmg(hhg_ctx* ctx, void* const* d_x, const void* const* d_b, int32
  * norm; info (may be NULL) is filled in every case. */
 hhg_status hhg_solve(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int32_t max_cycles,
                      hhg_solve_info* info, hhg_stream stream);
+
+/* One multigrid cycle for the velocity block alone, A u_k = b_k (k = 0..2),
+ * on the finest level (Sections 3.1, 3.2; Table "settings", SCG and PMINRES
+ * columns): V(nu1, nu2) with forward colour Gauss-Seidel (colours 0,1,2,3) in
+ * the pre-smoothing and backward (3,2,1,0) in the post-smoothing steps, the
+ * A-residual restricted by the transpose of P1 interpolation, A_0 inverted
+ * exactly on level 0.  Fields 0..2 of d_x are updated in place (their
+ * Dirichlet entries are kept), field 3 is not touched; d_b fields 0..2 are
+ * read (their Dirichlet rows are ignored).  0 <= nu1, nu2 <= 64, nu1 + nu2 > 0;
+ * EINVAL on aliasing.  FP64. */
+hhg_status hhg_vel_cycle(hhg_ctx* ctx, int32_t nu1, int32_t nu2, void* d_x, const void* d_b,
+                         hhg_stream stream);
+
+/* Block-diagonal preconditioned MINRES on K x = b (Section 3.2, eq.
+ * precond_block_diag): Ahat^-1 one velocity V(nu, nu) cycle as in
+ * hhg_vel_cycle (nu = 1 in Table "settings"), Shat^-1 the inverse of the
+ * lumped pressure mass weighted by 1/nu_T (sum over the tetrahedra around a
+ * vertex of |T| / (4 nu_T)).  x carries the Dirichlet velocity values.  The
+ * Euclidean residual norm of the stopping test (Section 3.6) is carried by
+ * its recurrence; iterations stop when it falls to rtol ||b - K x_0||_2, or
+ * after maxit iterations (rtol = 0: exactly maxit).  The pressure is
+ * projected to zero mean at the end when it is only defined up to a
+ * constant.  info->cycles counts iterations, res_hist the residual after
+ * each.  Needs krylov = 1 at creation; FP64; synchronises once per iteration.
+ * HHG_ENOCONV if the tolerance was not met (x holds the last iterate). */
+hhg_status hhg_pminres(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int32_t maxit,
+                       int32_t nu, hhg_solve_info* info, hhg_stream stream);
+
+/* Schur-complement CG (Section 3.1, Algorithm 1).  Every outer iteration runs
+ * n_A velocity V(nu, nu) cycles for A u = f - B^T p from the current u, then
+ * n_S steps of CG on S p = B A^-1 f - g, S = B A^-1 B^T + C, preconditioned
+ * by the weighted lumped mass of hhg_pminres, from the current p with the
+ * residual B u - C p - g; inside CG every A^-1 is n_I cycles from zero.  The
+ * pressure is projected to zero mean (when needed) and the stopping test
+ * ||b - K x||_2 <= rtol ||b - K x_0||_2 evaluated after every outer
+ * iteration (rtol = 0: exactly max_outer <= 255 of them).  Table "settings":
+ * n_A = n_S = 3, n_I = 1, nu = 3.  Needs krylov = 1; FP64; synchronises once
+ * per outer iteration. */
+hhg_status hhg_scg(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int32_t max_outer,
+                   int32_t n_A, int32_t n_S, int32_t n_I, int32_t nu, hhg_solve_info* info,
+                   hhg_stream stream);
 
 /* Adjoint gradients of J = 1/2 ||u - u_obs||^2 (not in the paper): given the
  * forward solution x (with its Dirichlet values), the adjoint solution lambda

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
                 ("p_sweep", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32),
-                ("coarse_prec", ctypes.c_int32), ("coarse_solver", ctypes.c_int32)]
+                ("coarse_prec", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
+                ("krylov", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -93,6 +94,9 @@ def _load():
         "hhg_project": (S, [P, I32, P, P]),
         "hhg_vcycle": (S, [P, P, P, P]),
         "hhg_solve": (S, [P, P, P, D, I32, ctypes.POINTER(SolveInfo), P]),
+        "hhg_vel_cycle": (S, [P, I32, I32, P, P, P]),
+        "hhg_pminres": (S, [P, P, P, D, I32, I32, ctypes.POINTER(SolveInfo), P]),
+        "hhg_scg": (S, [P, P, P, D, I32, I32, I32, I32, I32, ctypes.POINTER(SolveInfo), P]),
         "hhg_grad": (S, [P, P, P, P, P, P, P]),
         "hhg_set_viscosity": (S, [P, P]),
         "hhg_set_timing": (S, [P, I32]),
@@ -115,7 +119,8 @@ ABI_FUNCTIONS = ("hhg_default_opts", "hhg_plan", "hhg_create", "hhg_destroy", "h
                  "hhg_gather", "hhg_exchange", "hhg_rhs", "hhg_rhs_level", "hhg_fmg",
                  "hhg_apply", "hhg_residual",
                  "hhg_smooth", "hhg_restrict", "hhg_prolong_add", "hhg_coarse_solve",
-                 "hhg_project", "hhg_vcycle", "hhg_solve", "hhg_grad", "hhg_set_viscosity",
+                 "hhg_project", "hhg_vcycle", "hhg_solve", "hhg_vel_cycle", "hhg_pminres",
+                 "hhg_scg", "hhg_grad", "hhg_set_viscosity",
                  "hhg_set_timing", "hhg_kernel_time")
 
 
@@ -327,16 +332,40 @@ class Solver:
     def vcycle(self, x, b):
         _check(lib.hhg_vcycle(self.ctx, _ptr(x), _ptr(b), _stream()), self.ctx)
 
-    def solve(self, x, b, rtol=1e-8, max_cycles=100, raise_on_noconv=False):
-        info = SolveInfo()
-        st = lib.hhg_solve(self.ctx, _ptr(x), _ptr(b), rtol, max_cycles, ctypes.byref(info),
-                           _stream())
+    def _info(self, st, info, raise_on_noconv):
         if st not in (HHG_OK, HHG_ENOCONV) or (st == HHG_ENOCONV and raise_on_noconv):
             _check(st, self.ctx)
         k = info.cycles
         return {"status": st, "cycles": k, "r0": info.r0, "r_final": info.r_final,
                 "rel_res": info.rel_res, "rho_mean": info.rho_mean, "rho_max": info.rho_max,
                 "t_solve_ms": info.t_solve_ms, "res_hist": list(info.res_hist[:min(k, 255) + 1])}
+
+    def solve(self, x, b, rtol=1e-8, max_cycles=100, raise_on_noconv=False):
+        info = SolveInfo()
+        st = lib.hhg_solve(self.ctx, _ptr(x), _ptr(b), rtol, max_cycles, ctypes.byref(info),
+                           _stream())
+        return self._info(st, info, raise_on_noconv)
+
+    def vel_cycle(self, x, b, nu1=1, nu2=1):
+        """One velocity V(nu1, nu2) cycle for A u = b on fields 0..2 of x."""
+        _check(lib.hhg_vel_cycle(self.ctx, nu1, nu2, _ptr(x), _ptr(b), _stream()), self.ctx)
+
+    def pminres(self, x, b, rtol=1e-8, maxit=1000, nu=1, raise_on_noconv=False):
+        """Block-diagonal preconditioned MINRES (needs krylov=1 at creation);
+        rtol=0 runs exactly maxit iterations."""
+        info = SolveInfo()
+        st = lib.hhg_pminres(self.ctx, _ptr(x), _ptr(b), rtol, maxit, nu, ctypes.byref(info),
+                             _stream())
+        return self._info(st, info, raise_on_noconv)
+
+    def scg(self, x, b, rtol=1e-8, max_outer=200, n_A=3, n_S=3, n_I=1, nu=3,
+            raise_on_noconv=False):
+        """Schur-complement CG, Algorithm 1 (needs krylov=1 at creation);
+        rtol=0 runs exactly max_outer outer iterations."""
+        info = SolveInfo()
+        st = lib.hhg_scg(self.ctx, _ptr(x), _ptr(b), rtol, max_outer, n_A, n_S, n_I, nu,
+                         ctypes.byref(info), _stream())
+        return self._info(st, info, raise_on_noconv)
 
     def grad(self, x, lam, f=None, want_df=True):
         import torch

@@ -13,6 +13,7 @@
 #include "../../include/hhg.h"
 #include "hierarchy.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 
 using namespace hhg;
 
@@ -49,7 +50,13 @@ struct DevLevelArrays {
     // work vectors (4 fields each)
     double *x64, *b64, *r64, *t64;
     float *x32, *b32, *r32, *t32;
+    // finest level: primary-slot flags (inner products count each vertex
+    // once) and 1 / (lumped pressure mass weighted by 1/nu) on every copy
+    uint8_t* owned;
+    double* pinv;
 };
+
+constexpr int KV_N = 10;   // finest-level vectors of the Krylov solvers
 
 struct TimerPair {
     hipEvent_t a, b;
@@ -74,6 +81,9 @@ struct hhg_ctx {
     double* partials = nullptr;
     int npartials = 0;
     double* scal = nullptr;        // small device scalars
+    double* kv[KV_N] = {};         // Krylov vectors (4 fields each; opts.krylov)
+    double* kpart = nullptr;       // partial sums of the vector kernels
+    double* kscal = nullptr;       // device scalars of the Krylov solvers
     double* gpart = nullptr;       // gradient partials
     std::vector<double> inv_mass;  // 1 / sum_i m_i per level
     std::string err;
@@ -121,6 +131,10 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
     if (!(o->coarse_rtol > 0.0) || o->coarse_maxit < 1 || o->coarse_maxit > 100000 ||
         o->coarse_prec < 0 || o->coarse_prec > 1 || o->coarse_solver < 0 || o->coarse_solver > 1) {
         *err = "invalid coarse solver settings";
+        return false;
+    }
+    if (o->krylov < 0 || o->krylov > 1) {
+        *err = "krylov must be 0 or 1";
         return false;
     }
     return true;
@@ -213,6 +227,14 @@ size_t layout(hhg_ctx* c, char* ws) {
             a.r32 = cv.take<float>(v4);
             a.t32 = cv.take<float>(v4);
         }
+        a.owned = nullptr;
+        a.pinv = nullptr;
+        if (l == c->L) {
+            a.owned = cv.take<uint8_t>(h.len);
+            a.pinv = cv.take<double>(h.len);
+            for (int q = 0; q < KV_N; ++q)
+                c->kv[q] = c->opts.krylov ? cv.take<double>(v4) : nullptr;
+        }
         const int nb = full_blocks((int)h.vtiles.size()) + iface_blocks(h.nif);
         maxblocks = std::max(maxblocks, nb);
         maxblocks = std::max(maxblocks, (int)h.ctiles.size());
@@ -221,6 +243,8 @@ size_t layout(hhg_ctx* c, char* ws) {
     c->partials = cv.take<double>(maxblocks);
     c->gpart = cv.take<double>(maxblocks);
     c->scal = cv.take<double>(64);
+    c->kpart = cv.take<double>(VGRID_MAX);
+    c->kscal = cv.take<double>(16);
     // coarse system
     CoarseHost& C = c->CH;
     CoarseDev& d = c->cd;
@@ -419,6 +443,24 @@ hhg_status upload_all(hhg_ctx* c) {
         }
     }
     if ((s = upload_stencils(c)) != HHG_OK) return s;
+    {
+        // primary-slot flags and the pressure preconditioner of the finest level
+        HostLevel& h = c->H[c->L];
+        std::vector<uint8_t> own((size_t)h.len, 0);
+        std::vector<double> pinv((size_t)h.len, 0.0);
+        for (int64_t q = 0; q < h.len; ++q) {
+            const int32_t nd = h.slot_node[q];
+            if (nd < 0) continue;
+            if (h.node_slot[nd] == q) own[q] = 1;
+            const int32_t sid = h.node_sid[nd];
+            const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
+                                        : &h.st[(size_t)sid * ST_SIZE];
+            pinv[q] = 1.0 / rec[ST_MASSNU];
+        }
+        DevLevelArrays& a = c->A[c->L];
+        if ((s = upload<uint8_t>(c, a.owned, own.data(), own.size())) != HHG_OK) return s;
+        if ((s = upload<double>(c, a.pinv, pinv.data(), pinv.size())) != HHG_OK) return s;
+    }
     // algorithmic bytes of the timed kernel classes on the finest level
     HostLevel& h = c->H[c->L];
     double Nc[4] = {0, 0, 0, 0}, Nfc[4] = {0, 0, 0, 0}, Nf = 0;
@@ -673,20 +715,21 @@ void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out,
                        nvol + (v.nif + TPB - 1) / TPB, out, 1);
 }
 
-template <typename T>
+template <typename T, int NF = 4>
 void restrict_to(hhg_ctx* c, int l, const T* rf, T* bc, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
     const int ib = iface_blocks(C.nif);
     const int grid = ib + full_blocks(C.n_vtiles);
-    hipLaunchKernelGGL(k_restrict<T>, dim3(grid), dim3(TPB), 0, s, C, F, rf, bc, ib);
+    hipLaunchKernelGGL((k_restrict<T, NF>), dim3(grid), dim3(TPB), 0, s, C, F, rf, bc, ib);
 }
 
-template <typename T>
+template <typename T, int NF = 4>
 void prolong_add(hhg_ctx* c, int l, const T* ec, T* xf, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
-    hipLaunchKernelGGL(k_prolong<T>, dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s, F, C, ec, xf);
+    hipLaunchKernelGGL((k_prolong<T, false, NF>), dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s, F,
+                       C, ec, xf);
 }
 
 template <typename T>
@@ -750,6 +793,115 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     for (int q = 0; q < c->opts.nu2 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
 }
 
+// ------------------------------------------------------- velocity multigrid
+// Multigrid for the velocity block A alone (Sections 3.1, 3.2 and Table
+// "settings", SCG and PMINRES columns): V(nu1, nu2) with forward colour
+// Gauss-Seidel (colours 0..3) before and backward (3..0) after the coarse
+// correction, the A-residual restricted by P^T (three fields), A_0 inverted
+// exactly on level 0.  Works on fields 0..2 of x and b; field 3 of x is left
+// alone.  The mirror of x is current on entry and kept so.
+template <typename T>
+void coarse_avel(hhg_ctx* c, const T* b, T* x, hipStream_t s) {
+    const size_t len = (size_t)c->H[0].len;
+    const int rows = (3 * c->cd.nfv + TPB / 64 - 1) / (TPB / 64);
+    const int grid = std::max(std::max(rows, (c->cd.N + TPB - 1) / TPB), 1);
+    hipLaunchKernelGGL(k_coarse_avel<T>, dim3(grid), dim3(TPB), 3 * c->cd.nfv * sizeof(double), s,
+                       c->cd, b, len, x, len);
+}
+
+// velocity fields of x <- 0, with their mirror entries
+template <typename T>
+void fill_velocity(hhg_ctx* c, int l, T* x, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const size_t n3 = 3 * (size_t)v.len, m3 = 3 * (size_t)v.cstride;
+    hipLaunchKernelGGL(k_fill2<T>, dim3(grid_for(n3 + m3)), dim3(TPB), 0, s, x, n3, v.cx, m3, T(0));
+}
+
+template <typename T>
+void vel_cycle(hhg_ctx* c, int l, int nu1, int nu2, T* x, const T* b, hipStream_t s) {
+    T *xl, *bl, *rl, *tl;
+    vecs<T>(c, l, &xl, &bl, &rl, &tl);
+    if (l == 0) {
+        full_pass<T, MODE_ARES>(c, 0, x, b, rl, s);
+        coarse_avel<T>(c, rl, tl, s);
+        const size_t n3 = 3 * (size_t)c->H[0].len;
+        hipLaunchKernelGGL(k_add<T>, dim3(grid_for(n3)), dim3(TPB), 0, s, x, (const T*)tl, n3);
+        return;
+    }
+    for (int q = 0; q < nu1; ++q)
+        for (int col = 0; col < 4; ++col) colour_pass<T>(c, l, col, true, x, b, s);
+    full_pass<T, MODE_ARES>(c, l, x, b, rl, s);
+    T *xc, *bc, *rc, *tc;
+    vecs<T>(c, l - 1, &xc, &bc, &rc, &tc);
+    restrict_to<T, 3>(c, l, rl, bc, s);
+    if (l - 1 == 0) {
+        coarse_avel<T>(c, bc, xc, s);
+    } else {
+        fill_velocity<T>(c, l - 1, xc, s);
+        vel_cycle<T>(c, l - 1, nu1, nu2, xc, bc, s);
+    }
+    prolong_add<T, 3>(c, l, xc, x, s);
+    for (int q = 0; q < nu2; ++q)
+        for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, true, x, b, s);
+}
+
+// ------------------------------------------------------- Krylov helpers
+inline int vgrid(size_t n) {
+    return (int)std::max<size_t>(1, std::min<size_t>((n + TPB - 1) / TPB, VGRID_MAX));
+}
+
+// reduce the partials of a vector kernel launched with vgrid(len) into *out
+void vreduce(hhg_ctx* c, size_t len, double* out, bool sqrt_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->kpart, vgrid(len), out,
+                       sqrt_out ? 1 : 0);
+}
+
+// <a, b> over owned slots of the finest level, fields 0..nf-1 -> *out
+void vdot(hhg_ctx* c, const double* a, const double* b, int nf, double* out, hipStream_t s) {
+    const size_t len = (size_t)c->H[c->L].len;
+    hipLaunchKernelGGL(k_vdot, dim3(vgrid(len)), dim3(TPB), 0, s, a, b, c->A[c->L].owned, len, nf,
+                       c->kpart);
+    vreduce(c, len, out, false, s);
+}
+
+// z = diag(Ahat, Shat)^-1 v on the finest level (eq. precond_block_diag):
+// one velocity V(nu, nu) cycle from zero and the weighted lumped mass; *vz
+// receives <v, z>
+void block_prec(hhg_ctx* c, int nu, const double* v, double* z, double* vz, hipStream_t s) {
+    const int L = c->L;
+    const size_t len = (size_t)c->H[L].len;
+    fill_velocity<double>(c, L, z, s);
+    vel_cycle<double>(c, L, nu, nu, z, v, s);
+    hipLaunchKernelGGL(k_mr_precp_dot, dim3(vgrid(len)), dim3(TPB), 0, s, v, z, c->A[L].pinv,
+                       c->A[L].owned, len, c->kpart);
+    vreduce(c, len, vz, false, s);
+}
+
+hhg_status read_scalars(hhg_ctx* c, double* h, const double* d, int n, hipStream_t s) {
+    HIPCHECK(c, hipMemcpyAsync(h, d, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(c, hipStreamSynchronize(s));
+    return HHG_OK;
+}
+
+// residual history entry k (the info keeps the first 256)
+void hist_put(hhg_solve_info* I, int k, double r) {
+    if (k < 256) I->res_hist[k] = r;
+    I->cycles = k;
+    I->r_final = r;
+    I->rel_res = I->r0 > 0.0 ? r / I->r0 : 0.0;
+    if (k >= 1 && k < 256 && I->res_hist[k - 1] > 0.0)
+        I->rho_max = std::max(I->rho_max, r / I->res_hist[k - 1]);
+}
+
+// elapsed time between two recorded events (0 when timing is unavailable)
+double event_ms(hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) return 0.0;
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms;
+}
+
 }  // namespace
 
 // ============================================================== ABI
@@ -768,6 +920,7 @@ void hhg_default_opts(hhg_opts* o) {
     o->block_order = 1;
     o->coarse_prec = 1;
     o->coarse_solver = 0;
+    o->krylov = 0;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }
@@ -1530,6 +1683,237 @@ hhg_status hhg_kernel_time(hhg_ctx* c, int32_t cls, int64_t* launches, double* m
     if (launches) *launches = (int64_t)c->tpairs[cls].size();
     if (ms) *ms = tot;
     if (bytes) *bytes = c->tbytes[cls];
+    return HHG_OK;
+}
+
+
+hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const void* b,
+                         hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, b);
+    if (x == b) return fail(c, HHG_EINVAL, "x and b must not alias");
+    if (nu1 < 0 || nu2 < 0 || nu1 + nu2 == 0 || nu1 > 64 || nu2 > 64)
+        return fail(c, HHG_EINVAL, "smoothing steps must be in 0..64 with nu1 + nu2 > 0");
+    hipStream_t s = (hipStream_t)stream;
+    mirror_refresh<double>(c, c->L, (const double*)x, s);
+    vel_cycle<double>(c, c->L, nu1, nu2, (double*)x, (const double*)b, s);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
+hhg_status hhg_pminres(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t maxit, int32_t nu,
+                       hhg_solve_info* info, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, xv);
+    CHECK_PTR(c, bv);
+    if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");
+    if (!c->kv[0]) return fail(c, HHG_EINVAL, "Krylov vectors not reserved (create with krylov = 1)");
+    if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000 || nu < 1 || nu > 16)
+        return fail(c, HHG_EINVAL, "need rtol >= 0, 0 <= maxit <= 100000, 1 <= nu <= 16");
+    hipStream_t s = (hipStream_t)stream;
+    double* x = (double*)xv;
+    const double* b = (const double*)bv;
+    hhg_solve_info loc;
+    hhg_solve_info* I = info ? info : &loc;
+    std::memset(I, 0, sizeof(*I));
+    const int L = c->L;
+    const size_t len = (size_t)c->H[L].len, n4 = 4 * len;
+    double* R = c->kv[0];
+    double* Vb[2] = {c->kv[1], c->kv[2]};
+    double* Zb[2] = {c->kv[3], c->kv[4]};
+    double* Q = c->kv[5];
+    double* Wb[2] = {c->kv[6], c->kv[7]};
+    double* KWb[2] = {c->kv[8], c->kv[9]};
+    for (int q = 0; q < KV_N; ++q) fill<double>(c->kv[q], n4, 0.0, s);
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    if (e0) (void)hipEventRecord(e0, s);
+    // r_0 = f~ - K x_0, V_1 = r_0, Z_1 = P^-1 r_0 (unnormalised Lanczos vectors)
+    residual_norm<double>(c, L, x, b, R, c->kscal + 2, s);
+    hipLaunchKernelGGL(k_copy, dim3(vgrid(n4)), dim3(TPB), 0, s, Vb[1], (const double*)R, n4);
+    block_prec(c, nu, Vb[1], Zb[0], c->kscal + 1, s);
+    double h[3];
+    hhg_status rs = read_scalars(c, h, c->kscal, 3, s);
+    if (rs != HHG_OK) return rs;
+    const double r0 = h[2];
+    I->r0 = r0;
+    hist_put(I, 0, r0);
+    if (!std::isfinite(r0) || !std::isfinite(h[1])) {
+        I->status = HHG_ENAN;
+        return fail(c, HHG_ENAN, "initial residual is not finite");
+    }
+    hhg_status st = HHG_ENOCONV;
+    if (r0 == 0.0) st = HHG_OK;
+    int cur = 1, zc = 0, wc = 0, it = 0;
+    double beta = std::sqrt(std::max(h[1], 0.0)), beta_prev = 0.0;
+    double c_old = 1.0, s_old = 0.0, cs = 1.0, sn = 0.0, eta = beta;
+    bool pending = false;
+    while (st == HHG_ENOCONV && beta > 0.0) {
+        if (it >= maxit) break;
+        // Lanczos: Q = K Z_j, alpha_j = <Q, Z_j> / beta_j^2, V_{j+1}, Z_{j+1} = P^-1 V_{j+1}
+        full_pass<double, MODE_APPLY>(c, L, Zb[zc], nullptr, Q, s);
+        vdot(c, Q, Zb[zc], 4, c->kscal + 0, s);
+        hipLaunchKernelGGL(k_mr_lanczos, dim3(vgrid(n4)), dim3(TPB), 0, s, (const double*)Q,
+                           (const double*)Vb[cur], Vb[cur ^ 1], n4, beta,
+                           it == 0 ? 0.0 : beta / beta_prev, (const double*)c->kscal);
+        block_prec(c, nu, Vb[cur ^ 1], Zb[zc ^ 1], c->kscal + 1, s);
+        if ((rs = read_scalars(c, h, c->kscal, 3, s)) != HHG_OK) return rs;
+        if (pending) {
+            // residual of the previous update (Q, V and Z do not touch x or r)
+            hist_put(I, it, h[2]);
+            pending = false;
+            if (!std::isfinite(h[2])) {
+                st = HHG_ENAN;
+                break;
+            }
+            if (h[2] <= rtol * r0) {
+                st = HHG_OK;
+                break;
+            }
+        }
+        const double alpha = h[0] / (beta * beta);
+        const double beta_new = std::sqrt(std::max(h[1], 0.0));
+        // rotations G_{j-2}, G_{j-1} on column j of the tridiagonal matrix,
+        // then G_j annihilating beta_{j+1}
+        const double eps = s_old * beta, dhat = c_old * beta;
+        const double delta = cs * dhat + sn * alpha, ghat = -sn * dhat + cs * alpha;
+        const double gamma = std::hypot(ghat, beta_new);
+        if (!std::isfinite(gamma)) {
+            st = HHG_ENAN;
+            break;
+        }
+        if (gamma == 0.0) break;
+        const double c_new = ghat / gamma, s_new = beta_new / gamma;
+        const double tau = c_new * eta;
+        eta = -s_new * eta;
+        MrCoef k{1.0 / (beta * gamma), eps / gamma, delta / gamma, tau};
+        hipLaunchKernelGGL(k_mr_update, dim3(vgrid(len)), dim3(TPB), 0, s, (const double*)Zb[zc],
+                           Wb[wc], (const double*)Wb[wc ^ 1], x, (const double*)Q, KWb[wc],
+                           (const double*)KWb[wc ^ 1], R, (const uint8_t*)c->A[L].owned, len, k,
+                           c->kpart);
+        vreduce(c, len, c->kscal + 2, true, s);
+        pending = true;
+        ++it;
+        wc ^= 1;
+        cur ^= 1;
+        zc ^= 1;
+        c_old = cs;
+        s_old = sn;
+        cs = c_new;
+        sn = s_new;
+        beta_prev = beta;
+        beta = beta_new;
+    }
+    if (pending) {
+        if ((rs = read_scalars(c, h, c->kscal + 2, 1, s)) != HHG_OK) return rs;
+        hist_put(I, it, h[0]);
+        if (!std::isfinite(h[0]))
+            st = HHG_ENAN;
+        else if (h[0] <= rtol * r0)
+            st = HHG_OK;
+    }
+    project<double>(c, L, x, s);
+    if (e1) (void)hipEventRecord(e1, s);
+    I->t_solve_ms = event_ms(e0, e1);
+    if (I->cycles > 0 && I->rel_res > 0.0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    I->status = st;
+    c->evused = c->timing ? c->evused : 0;
+    LAUNCH_CHECK(c);
+    if (st == HHG_ENAN) return fail(c, HHG_ENAN, "residual norm is not finite");
+    if (st == HHG_ENOCONV) return fail(c, HHG_ENOCONV, "tolerance not reached");
+    return HHG_OK;
+}
+
+hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t max_outer,
+                   int32_t n_A, int32_t n_S, int32_t n_I, int32_t nu, hhg_solve_info* info,
+                   hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, xv);
+    CHECK_PTR(c, bv);
+    if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");
+    if (!c->kv[0]) return fail(c, HHG_EINVAL, "Krylov vectors not reserved (create with krylov = 1)");
+    if (!(rtol >= 0.0) || max_outer < 0 || max_outer > 255 || n_A < 1 || n_A > 64 || n_S < 1 ||
+        n_S > 64 || n_I < 1 || n_I > 64 || nu < 1 || nu > 16)
+        return fail(c, HHG_EINVAL,
+                    "need rtol >= 0, 0 <= max_outer <= 255, n_A, n_S, n_I in 1..64, nu in 1..16");
+    hipStream_t s = (hipStream_t)stream;
+    double* x = (double*)xv;
+    const double* b = (const double*)bv;
+    hhg_solve_info loc;
+    hhg_solve_info* I = info ? info : &loc;
+    std::memset(I, 0, sizeof(*I));
+    const int L = c->L;
+    const size_t len = (size_t)c->H[L].len, n4 = 4 * len;
+    double* T = c->kv[0];              // velocity right-hand sides
+    double* DW = c->kv[1];             // w = -Ahat^-1 B^T d (fields 0..2), d (field 3)
+    double* Y = c->kv[2];              // field 3: C p - B u, then S d
+    double* RHO = c->kv[3];            // Schur residual
+    double* ZP = c->kv[3] + len;       // M^-1 rho
+    double* D = DW + 3 * len;
+    double* Rr = c->A[L].r64;
+    const uint8_t* own = c->A[L].owned;
+    const double* pinv = c->A[L].pinv;
+    for (int q = 0; q < 4; ++q) fill<double>(c->kv[q], n4, 0.0, s);
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    if (e0) (void)hipEventRecord(e0, s);
+    residual_norm<double>(c, L, x, b, Rr, c->kscal + 2, s);
+    double h[1];
+    hhg_status rs = read_scalars(c, h, c->kscal + 2, 1, s);
+    if (rs != HHG_OK) return rs;
+    const double r0 = h[0];
+    I->r0 = r0;
+    hist_put(I, 0, r0);
+    if (!std::isfinite(r0)) {
+        I->status = HHG_ENAN;
+        return fail(c, HHG_ENAN, "initial residual is not finite");
+    }
+    hhg_status st = r0 == 0.0 ? HHG_OK : HHG_ENOCONV;
+    double* rz = c->kscal + 4;         // ping-pong pair rz[0], rz[1]
+    double* dy = c->kscal + 6;
+    for (int k = 1; k <= max_outer && st == HHG_ENOCONV; ++k) {
+        // n_A cycles for A u = f - B^T p from the previous u
+        full_pass<double, MODE_RU>(c, L, x, b, T, s);
+        mirror_refresh<double>(c, L, x, s);
+        for (int q = 0; q < n_A; ++q) vel_cycle<double>(c, L, nu, nu, x, T, s);
+        // CG on S p = B A^-1 f - g from p with rho = B u - C p - g
+        full_pass<double, MODE_SCHUR>(c, L, x, nullptr, Y, s);
+        hipLaunchKernelGGL(k_cg_start, dim3(vgrid(len)), dim3(TPB), 0, s,
+                           (const double*)(Y + 3 * len), b + 3 * len, RHO, ZP, D, pinv, own, len,
+                           c->kpart);
+        vreduce(c, len, rz, false, s);
+        int cur = 0;
+        for (int i = 0; i < n_S; ++i) {
+            // S d = B A^-1 B^T d + C d with A^-1 ~ n_I cycles from zero
+            full_pass<double, MODE_BTN>(c, L, DW, nullptr, T, s);
+            fill_velocity<double>(c, L, DW, s);
+            for (int q = 0; q < n_I; ++q) vel_cycle<double>(c, L, nu, nu, DW, T, s);
+            full_pass<double, MODE_SCHUR>(c, L, DW, nullptr, Y, s);
+            vdot(c, D, Y + 3 * len, 1, dy, s);
+            hipLaunchKernelGGL(k_cg_step, dim3(vgrid(len)), dim3(TPB), 0, s, x + 3 * len,
+                               (const double*)D, RHO, (const double*)(Y + 3 * len), ZP, pinv, own,
+                               len, (const double*)(rz + cur), (const double*)dy, c->kpart);
+            vreduce(c, len, rz + (cur ^ 1), false, s);
+            hipLaunchKernelGGL(k_cg_dir, dim3(vgrid(len)), dim3(TPB), 0, s, D, (const double*)ZP,
+                               len, (const double*)(rz + (cur ^ 1)), (const double*)(rz + cur));
+            cur ^= 1;
+        }
+        project<double>(c, L, x, s);
+        residual_norm<double>(c, L, x, b, Rr, c->kscal + 2, s);
+        if ((rs = read_scalars(c, h, c->kscal + 2, 1, s)) != HHG_OK) return rs;
+        hist_put(I, k, h[0]);
+        if (!std::isfinite(h[0]))
+            st = HHG_ENAN;
+        else if (h[0] <= rtol * r0)
+            st = HHG_OK;
+    }
+    if (e1) (void)hipEventRecord(e1, s);
+    I->t_solve_ms = event_ms(e0, e1);
+    if (I->cycles > 0 && I->rel_res > 0.0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    I->status = st;
+    c->evused = c->timing ? c->evused : 0;
+    LAUNCH_CHECK(c);
+    if (st == HHG_ENAN) return fail(c, HHG_ENAN, "residual norm is not finite");
+    if (st == HHG_ENOCONV) return fail(c, HHG_ENOCONV, "tolerance not reached");
     return HHG_OK;
 }
 

@@ -265,8 +265,12 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
 //   MODE_BP      t_3 = (B u) - b_3
 //   MODE_RHS     y = (M f on free rows, sum_k G_k f_k)    (in: f in fields 0..2)
 //   MODE_GRADF   y_k = M lam_k + GT_k lam_p                (in: lambda)
+//   MODE_ARES    t_k = b_k - (A u_k)  (k = 0..2; Dirichlet rows 0)  velocity multigrid
+//   MODE_BTN     t_k = -(B^T p)_k     (k = 0..2; Dirichlet rows 0)  Schur complement
+//   MODE_SCHUR   t_3 = (C p) - (B u)                               Schur complement
 // ---------------------------------------------------------------------------
-enum { MODE_APPLY = 0, MODE_RES = 1, MODE_RU = 2, MODE_BP = 3, MODE_RHS = 4, MODE_GRADF = 5 };
+enum { MODE_APPLY = 0, MODE_RES = 1, MODE_RU = 2, MODE_BP = 3, MODE_RHS = 4, MODE_GRADF = 5,
+       MODE_ARES = 6, MODE_BTN = 7, MODE_SCHUR = 8 };
 
 // Load from a uniform field base at a 32-bit byte offset: the address is an
 // SGPR base plus one 32-bit VGPR per tap, shared by all fields (slot offsets
@@ -280,11 +284,57 @@ __device__ __forceinline__ T ldo(const T* __restrict__ base, uint32_t boff) {
 // field of stride xs (a macro array, or the compact mirror for interface
 // vertices); the vertex's own entries of b sit at slot bslot of fields of
 // stride bs.
+// Velocity residual of A alone at one vertex: tp[] the centre and the six
+// axis taps, ca[] the record positions of their coefficients (A couples only
+// the axis neighbours on Kuhn lattices).
+template <typename T>
+__device__ __forceinline__ void eval_ares(const T* __restrict__ st, const int* tp, const int* ca,
+                                          bool dir, const T* __restrict__ x, size_t xs,
+                                          const T* __restrict__ b, size_t bs, int bslot,
+                                          T out[4]) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        T acc = T(0);
+#pragma unroll
+        for (int g = 0; g < 7; ++g) acc += st[ST_A + ca[g]] * x[f * xs + tp[g]];
+        out[f] = dir ? T(0) : b[f * bs + bslot] - acc;
+    }
+}
+
 template <typename T, int MODE>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
                                           const T* __restrict__ x, size_t xs,
                                           const T* __restrict__ b, size_t bs, int bslot,
                                           T out[4]) {
+    if (MODE == MODE_ARES) {
+        // interface rows: the axis taps are 1..6 of the global direction order
+        const int ca[7] = {0, 1, 2, 3, 4, 5, 6};
+        eval_ares<T>(st, s, ca, dir, x, xs, b, bs, bslot, out);
+        return;
+    }
+    if (MODE == MODE_BTN) {
+        const T* p = x + 3 * xs;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T acc = T(0);
+#pragma unroll
+            for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * p[s[g]];
+            out[f] = dir ? T(0) : -acc;
+        }
+        return;
+    }
+    if (MODE == MODE_SCHUR) {
+        const T* p = x + 3 * xs;
+        T acc = T(0);
+#pragma unroll
+        for (int g = 0; g < 15; ++g) acc += st[ST_C + g] * p[s[g]];
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int g = 0; g < 15; ++g) acc -= st[ST_B + 15 * f + g] * x[f * xs + s[g]];
+        out[3] = acc;
+        return;
+    }
     if (MODE == MODE_RU) {
         const T* p = x + 3 * xs;
 #pragma unroll
@@ -421,8 +471,8 @@ template <int MODE>
 __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
     f0 = 0;
     f1 = 4;
-    if (MODE == MODE_RU || MODE == MODE_GRADF) f1 = 3;
-    if (MODE == MODE_BP) f0 = 3;
+    if (MODE == MODE_RU || MODE == MODE_GRADF || MODE == MODE_ARES || MODE == MODE_BTN) f1 = 3;
+    if (MODE == MODE_BP || MODE == MODE_SCHUR) f0 = 3;
 }
 
 // Colour-c update fused into a full pass (velocity Gauss-Seidel into the
@@ -484,7 +534,9 @@ __host__ __device__ __forceinline__ int full_blocks(int n_vtiles) { return 4 * (
 // right-hand side and the forcing gradient) keep one block per tile and four
 // vertices per lane, evaluated one after another: one vertex per lane would
 // need every tap of all fields in flight at once (over 256 VGPRs).
-__host__ __device__ constexpr bool quad_lanes(int mode) { return mode == 0 || mode == 1 || mode >= 4; }
+__host__ __device__ constexpr bool quad_lanes(int mode) {
+    return mode == MODE_APPLY || mode == MODE_RES || mode == MODE_RHS || mode == MODE_GRADF;
+}
 
 // Quad windows: a lane that evaluates the 4 vertices i = 4q..4q+3 of a row
 // loads every distinct tap value once.  Row rho of make_rows contributes the
@@ -679,10 +731,16 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    if (MODE == MODE_APPLY || MODE == MODE_RES)
+                    if (MODE == MODE_ARES) {
+                        // volume rows: axis taps 1, 2, 3, 4, 7, 8 of the local order
+                        const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
+                        const int ca[7] = {0, 1, 2, 3, 4, 7, 8};
+                        eval_ares<T>(st, tp, ca, false, x, len, b, len, s[0], out);
+                    } else if (MODE == MODE_APPLY || MODE == MODE_RES) {
                         eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
-                    else
+                    } else {
                         eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
+                    }
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
@@ -721,7 +779,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
 // Restriction r_c = P^T r_f (weights 1 at the coincident vertex, 1/2 at its 14
 // neighbours); velocity Dirichlet rows of the coarse level are zero.
 // ---------------------------------------------------------------------------
-template <typename T>
+// NF = 3: velocity fields only (multigrid for the velocity block).
+template <typename T, int NF = 4>
 __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
                                                   const T* __restrict__ rf, T* __restrict__ bc,
                                                   int ib) {
@@ -743,7 +802,7 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
         nbr_slots(RF, 2 * i, s);
         const int sc = slot_of(C.slab_base, n, (int)(tl.macro * C.mstride), i, j, k);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < NF; ++f) {
             const T* vf = rf + f * lf;
             T acc = T(0);
 #pragma unroll
@@ -763,7 +822,7 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
     const bool dir = (C.if_flag[t] & 1) != 0;
     const int c0 = C.if_cptr[t], c1 = C.if_cptr[t + 1];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
         const T* v = rf + f * lf;
         T acc = T(0);
 #pragma unroll
@@ -798,7 +857,8 @@ __host__ __device__ __forceinline__ void parity_dir(int pat, int* di, int* dj, i
 
 // SET (full multigrid): x_f = P e_c instead of x_f += P e_c, except on the
 // velocity slots of Dirichlet vertices, which keep their values.
-template <typename T, bool SET = false>
+// NF = 3: velocity fields only.
+template <typename T, bool SET = false, int NF = 4>
 __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
                                                  const T* __restrict__ ec, T* __restrict__ xf) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
@@ -825,7 +885,7 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     if ((pi | pj | pk) == 0) {
         const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < NF; ++f) {
             T v = ec[f * lc + sc];
             if (!SET)
                 v += xf[f * lf + sf];
@@ -841,7 +901,7 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
     const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < NF; ++f) {
         T v = T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
         if (!SET)
             v += xf[f * lf + sf];

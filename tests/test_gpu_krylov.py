@@ -1,0 +1,207 @@
+"""GPU parity of the global Krylov solvers (Sections 3.1, 3.2): the velocity
+multigrid cycle, block-diagonal PMINRES and the Schur-complement CG through
+the C ABI against the oracle on the same seeded inputs (FP64).  Fixed
+iteration counts compare iterates element by element; full solves compare
+iteration counts, residual histories and solutions."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import UMG, build_hierarchy
+from oracle.krylov import StokesKrylov, VelocityMG
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _setup(cid, R, krylov=1):
+    import paper_1511_02134_amd as P
+    cfg = W.WORKLOADS[cid].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    _announce(f"config {cid} R={R}")
+    s = P.Solver(xyz, tet, nu, tags, R, krylov=krylov)
+    H = build_hierarchy(xyz, tet, nu, tags, R)
+    return cfg, s, H
+
+
+def _problem(cfg, H, seed):
+    """Right-hand side of the workload's forcing plus noise, and a random
+    start carrying the workload's Dirichlet values."""
+    lv = H.finest
+    f = cfg.forcing_field() + W.nodal_noise(lv.N, seed, 1.0)
+    b = UMG(H).rhs(f)
+    x0 = np.random.default_rng(seed + 1).normal(size=(4, lv.N))
+    x0[:3, lv.dirichlet] = cfg.dirichlet_field()[:, lv.dirichlet]
+    return b, x0
+
+
+VCASES = [(1, 2, 1, 1), (1, 4, 1, 1), (4, 4, 1, 1), (5, 4, 3, 3), (1, 5, 3, 3), (4, 3, 2, 0),
+          (5, 3, 0, 2)]
+
+
+@pytest.mark.parametrize("cid,R,nu1,nu2", VCASES)
+def test_velocity_cycle_matches_oracle(cid, R, nu1, nu2):
+    """One velocity V(nu1, nu2) cycle from a random iterate (Dirichlet entries
+    nonzero): fields 0..2 equal the oracle's, field 3 is untouched."""
+    cfg, s, H = _setup(cid, R)
+    lv = H.finest
+    rng = np.random.default_rng(100 + R)
+    x = rng.normal(size=(4, lv.N))
+    b = rng.normal(size=(4, lv.N))
+    xd = s.scatter(_dev(x))
+    s.vel_cycle(xd, s.scatter(_dev(b)), nu1, nu2)
+    xg = _host(s.gather(xd))
+    xo = VelocityMG(H, nu1, nu2).cycle(len(H.levels) - 1, x[:3].copy(), b[:3])
+    err = _relerr(xg[:3], xo)
+    _announce(f"velocity cycle V({nu1},{nu2}): max rel. difference {err:.2e}")
+    assert err < 1e-12
+    assert np.array_equal(xg[3], x[3])
+    assert np.array_equal(xg[:3, lv.dirichlet], x[:3, lv.dirichlet])
+
+
+PCASES = [(1, 3), (4, 4), (5, 4), (1, 2)]
+
+
+@pytest.mark.parametrize("cid,R", PCASES)
+@pytest.mark.parametrize("iters", [1, 4, 12])
+def test_pminres_iterates_match_oracle(cid, R, iters):
+    """PMINRES after a fixed number of iterations (rtol = 0): iterate and
+    residual history equal the oracle's."""
+    cfg, s, H = _setup(cid, R)
+    b, x0 = _problem(cfg, H, 7)
+    ks = StokesKrylov(H, 1, 1)
+    xo, ho = ks.pminres(x0, b, iters=iters)
+    xd = s.scatter(_dev(x0))
+    info = s.pminres(xd, s.scatter(_dev(b)), rtol=0.0, maxit=iters)
+    xg = _host(s.gather(xd))
+    assert info["cycles"] == iters
+    hist = np.array(info["res_hist"])
+    err = _relerr(xg, xo)
+    herr = np.abs(hist - np.array(ho)).max() / ho[0]
+    _announce(f"PMINRES {iters} iterations: max rel. difference {err:.2e}, history {herr:.2e}")
+    assert herr < 1e-11
+    assert err < 1e-9
+
+
+@pytest.mark.parametrize("cid,R", [(1, 4), (4, 4), (5, 4)])
+def test_pminres_solve_matches_oracle(cid, R):
+    """Full solve to 1e-8: the residual histories agree (Lanczos recurrences
+    in two summation orders drift apart slowly over a hundred iterations, so
+    the crossing of the threshold may move by a few percent of the count on
+    a flat stretch), the true residual meets the tolerance, the solution
+    agrees with the oracle's."""
+    cfg, s, H = _setup(cid, R)
+    b, x0 = _problem(cfg, H, 11)
+    ks = StokesKrylov(H, 1, 1)
+    xo, ho = ks.pminres(x0, b, rtol=1e-8)
+    xd = s.scatter(_dev(x0))
+    bd = s.scatter(_dev(b))
+    info = s.pminres(xd, bd, rtol=1e-8, maxit=500)
+    hg = np.array(info["res_hist"])
+    m = min(len(hg), len(ho))
+    drift = np.max(np.abs(hg[:m] - np.array(ho[:m])) / np.array(ho[:m]))
+    _announce(f"PMINRES: {info['cycles']} iterations (oracle {len(ho) - 1}), "
+              f"rel. residual {info['rel_res']:.2e}, history drift {drift:.2e}, "
+              f"{info['t_solve_ms']:.1f} ms")
+    assert info["status"] == 0
+    assert drift < 0.05
+    assert abs(info["cycles"] - (len(ho) - 1)) <= max(1, 0.03 * (len(ho) - 1))
+    _, rn = s.residual(xd, bd)
+    assert rn <= 1.01e-8 * info["r0"]
+    # stopped a few iterations apart, the two iterates differ by the error of
+    # a 1e-8 solution: both must be that close to the discrete solution
+    # (the oracle's iterate at 1e-13)
+    xs, _ = ks.pminres(x0, b, rtol=1e-13)
+    eg, eo = _relerr(_host(s.gather(xd)), xs), _relerr(xo, xs)
+    _announce(f"error against the 1e-13 solution: GPU {eg:.2e}, oracle {eo:.2e}")
+    assert eg <= 3.0 * eo + 1e-12
+
+
+SCASES = [(1, 3), (4, 4), (5, 4)]
+
+
+@pytest.mark.parametrize("cid,R", SCASES)
+@pytest.mark.parametrize("outer,n_S", [(1, 1), (1, 3), (2, 3)])
+def test_scg_iterates_match_oracle(cid, R, outer, n_S):
+    cfg, s, H = _setup(cid, R)
+    b, x0 = _problem(cfg, H, 13)
+    ks = StokesKrylov(H, 3, 3)
+    xo, ho = ks.scg(x0, b, n_S=n_S, outer=outer)
+    xd = s.scatter(_dev(x0))
+    info = s.scg(xd, s.scatter(_dev(b)), rtol=0.0, max_outer=outer, n_S=n_S)
+    xg = _host(s.gather(xd))
+    assert info["cycles"] == outer
+    err = _relerr(xg, xo)
+    herr = np.abs(np.array(info["res_hist"]) - np.array(ho)).max() / ho[0]
+    _announce(f"SCG {outer} outer x {n_S} CG: max rel. difference {err:.2e}, history {herr:.2e}")
+    assert herr < 1e-11
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("cid,R", [(1, 4), (5, 4)])
+def test_scg_solve_matches_oracle(cid, R):
+    cfg, s, H = _setup(cid, R)
+    b, x0 = _problem(cfg, H, 17)
+    ks = StokesKrylov(H, 3, 3)
+    xo, ho = ks.scg(x0, b, rtol=1e-8)
+    xd = s.scatter(_dev(x0))
+    bd = s.scatter(_dev(b))
+    info = s.scg(xd, bd, rtol=1e-8)
+    _announce(f"SCG: {info['cycles']} outer iterations (oracle {len(ho) - 1}), "
+              f"rel. residual {info['rel_res']:.2e}, {info['t_solve_ms']:.1f} ms")
+    assert info["status"] == 0
+    assert abs(info["cycles"] - (len(ho) - 1)) <= 1
+    _, rn = s.residual(xd, bd)
+    assert rn <= 1.0000001e-8 * info["r0"]
+    assert _relerr(_host(s.gather(xd)), xo) < 1e-8
+
+
+def test_krylov_entry_points_need_reserved_vectors_and_valid_arguments():
+    import paper_1511_02134_amd as P
+    cfg, s, H = _setup(1, 3, krylov=0)
+    x = s.vector()
+    b = s.vector()
+    with pytest.raises(P.HHGError) as e:
+        s.pminres(x, b)
+    assert e.value.status == P.HHG_EINVAL
+    with pytest.raises(P.HHGError):
+        s.scg(x, b)
+    _, s2, _ = _setup(1, 3)
+    for bad in (dict(nu=0), dict(maxit=-1), dict(rtol=-1.0)):
+        with pytest.raises(P.HHGError):
+            s2.pminres(x, b, **bad)
+    for bad in (dict(n_S=0), dict(n_A=65), dict(max_outer=256)):
+        with pytest.raises(P.HHGError):
+            s2.scg(x, b, **bad)
+    with pytest.raises(P.HHGError):
+        s2.vel_cycle(x, x)
+    with pytest.raises(P.HHGError):
+        s2.vel_cycle(x, b, 0, 0)
+    # a zero right-hand side and a zero start: converged at once
+    info = s2.pminres(x, b)
+    assert info["status"] == 0 and info["cycles"] == 0
+    info = s2.scg(x, b)
+    assert info["status"] == 0 and info["cycles"] == 0
+    # too few iterations: HHG_ENOCONV reported, not raised
+    cfg, s3, H = _setup(1, 3)
+    bb, x0 = _problem(cfg, H, 3)
+    info = s3.pminres(s3.scatter(_dev(x0)), s3.scatter(_dev(bb)), rtol=1e-8, maxit=2)
+    assert info["status"] == P.HHG_ENOCONV and info["cycles"] == 2
