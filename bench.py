@@ -16,6 +16,8 @@ Printed as one JSON line with, besides the contract fields:
                bounded size on the host cores, setup excluded.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+    python bench.py --tme R        (full multigrid efficiency study)
+    python bench.py --compare R    (UMG / PMINRES / SCG comparison)
 """
 from __future__ import annotations
 
@@ -206,6 +208,56 @@ def run_tme(R: int, steps: int, warmup: int):
     print(json.dumps(line), flush=True)
 
 
+def run_compare(R: int, steps: int, warmup: int):
+    """The solver comparison of Section 4 (Table T:itertime1, Figure opcount):
+    unit cube, f = 0, nu = 1, random start u0 ~ U[0,1], p0 ~ U[0, 1/h_min]
+    (Section 3.6), relative residual 1e-8; UMG with the variable V(3,3)
+    cycle, block-diagonal PMINRES with a velocity V(1,1) cycle, and SCG with
+    V(3,3), n_A = n_S = 3, n_I = 1 (Table "settings").  Prints iterations,
+    time to solution (median of the timed solves, hipEvents) and the
+    measured operator evaluations per block (eq. op_count)."""
+    import torch
+    import workloads as W
+    import paper_1511_02134_amd as P
+
+    cfg = W.WORKLOADS[1].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, R, cycle=1, krylov=1)
+    dev = torch.device("cuda")
+    n = 2 ** R
+    hmin = (1.0 / (6.0 * n ** 3)) ** (1.0 / 3.0)
+    x0n = W.random_initial_guess(s.num_nodes(), 1.0 / hmin, seed=0)
+    _, dmask = s.node_info()
+    x0n[:3, dmask] = 0.0
+    x0 = s.scatter(torch.tensor(x0n, device=dev))
+    b = s.vector()
+    x = torch.empty_like(x0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    runs = {"UMG": lambda: s.solve(x, b, rtol=1e-8, max_cycles=100),
+            "PMINRES": lambda: s.pminres(x, b, rtol=1e-8, maxit=2000, nu=1),
+            "SCG": lambda: s.scg(x, b, rtol=1e-8, max_outer=255, n_A=3, n_S=3, n_I=1, nu=3)}
+    out = {}
+    for name, fn in runs.items():
+        t = []
+        for k in range(warmup + steps):
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            ev[0].record()
+            info = fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                t.append(ev[0].elapsed_time(ev[1]))
+        out[name] = {"iterations": info["cycles"], "status": info["status"],
+                     "rel_res": info["rel_res"], "ms": float(np.median(t)),
+                     "n_op": {k: round(v, 2) for k, v in info["n_op"].items()}}
+    line = {"metric": "time to solution and operator evaluations of UMG, PMINRES and SCG",
+            "workload": f"unit cube, {R} refinements, f = 0, random start (seed 0)",
+            "refinements": R, "paper_level": R - 2, "dofs": s.num_dofs(), "rtol": 1e-8,
+            "dtype": "f64", "data": "synthetic", **out}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,12 +271,17 @@ def main():
                     help="run the operation sequence used for counter collection and exit")
     ap.add_argument("--tme", type=int, default=0, metavar="R",
                     help="full multigrid efficiency study at R refinements (prints its own line)")
+    ap.add_argument("--compare", type=int, default=0, metavar="R",
+                    help="UMG / PMINRES / SCG comparison at R refinements (prints its own line)")
     args = ap.parse_args()
     if args.ops:
         run_ops(args.workload)
         return
     if args.tme:
         run_tme(args.tme, max(args.steps, 3), args.warmup)
+        return
+    if args.compare:
+        run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "

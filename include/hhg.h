@@ -115,6 +115,11 @@ typedef struct {
     double rho_max;        /* largest ||r_k|| / ||r_{k-1}|| */
     double t_solve_ms;     /* wall time of the cycles, hipEvent timed on the stream */
     double res_hist[256];  /* ||r_k||_2, k = 0..min(cycles, 255) */
+    double n_op[4];        /* operator evaluations of A, B, C and M during the call,
+                              weighted by level, sum_l 8^(l-L) n_op,l (Section 4.2,
+                              eq. op_count); a colour sweep counts a quarter of its
+                              operator, B and B^T count as B, the exact level-0
+                              solves count nothing */
 } hhg_solve_info;
 
 /* Fills opts with the defaults above. */

@@ -52,7 +52,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int32), ("status", ctypes.c_int32), ("r0", ctypes.c_double),
                 ("r_final", ctypes.c_double), ("rel_res", ctypes.c_double),
                 ("rho_mean", ctypes.c_double), ("rho_max", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double), ("res_hist", ctypes.c_double * 256)]
+                ("t_solve_ms", ctypes.c_double), ("res_hist", ctypes.c_double * 256),
+                ("n_op", ctypes.c_double * 4)]
 
 
 def _load():
@@ -338,7 +339,8 @@ class Solver:
         k = info.cycles
         return {"status": st, "cycles": k, "r0": info.r0, "r_final": info.r_final,
                 "rel_res": info.rel_res, "rho_mean": info.rho_mean, "rho_max": info.rho_max,
-                "t_solve_ms": info.t_solve_ms, "res_hist": list(info.res_hist[:min(k, 255) + 1])}
+                "t_solve_ms": info.t_solve_ms, "res_hist": list(info.res_hist[:min(k, 255) + 1]),
+                "n_op": dict(zip("ABCM", list(info.n_op)))}
 
     def solve(self, x, b, rtol=1e-8, max_cycles=100, raise_on_noconv=False):
         info = SolveInfo()

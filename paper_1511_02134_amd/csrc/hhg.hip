@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -86,6 +87,9 @@ struct hhg_ctx {
     double* kscal = nullptr;       // device scalars of the Krylov solvers
     double* gpart = nullptr;       // gradient partials
     std::vector<double> inv_mass;  // 1 / sum_i m_i per level
+    // operator evaluations per level (A, B, C, M) since the last reset; a
+    // colour sweep counts a quarter of its operator (Section 4.2)
+    std::vector<std::array<double, 4>> opc;
     std::string err;
     // timing
     bool timing = false;
@@ -360,6 +364,7 @@ hhg_status upload_all(hhg_ctx* c) {
     c->D64.assign(nl, LevelDev<double>{});
     c->D32.assign(nl, LevelDev<float>{});
     c->inv_mass.assign(nl, 0.0);
+    c->opc.assign(nl, std::array<double, 4>{0.0, 0.0, 0.0, 0.0});
     for (int l = 0; l < nl; ++l) {
         HostLevel& h = c->H[l];
         DevLevelArrays& a = c->A[l];
@@ -531,6 +536,28 @@ struct Timed {
 
 inline int grid_for(size_t n) { return (int)std::min<size_t>((n + TPB - 1) / TPB, 8192); }
 
+// ------------------------------------------------------------------ operator counts
+inline void ops(hhg_ctx* c, int l, double a, double b, double cc, double m) {
+    std::array<double, 4>& o = c->opc[l];
+    o[0] += a;
+    o[1] += b;
+    o[2] += cc;
+    o[3] += m;
+}
+
+void reset_ops(hhg_ctx* c) {
+    c->opc.assign(c->L + 1, std::array<double, 4>{0.0, 0.0, 0.0, 0.0});
+}
+
+// weighted counts of eq. op_count: sum_l 8^(l-L) n_op,l
+void put_ops(hhg_ctx* c, hhg_solve_info* I) {
+    for (int q = 0; q < 4; ++q) {
+        double t = 0.0;
+        for (int l = 0; l <= c->L; ++l) t += std::ldexp(c->opc[l][q], 3 * (l - c->L));
+        I->n_op[q] = t;
+    }
+}
+
 // ------------------------------------------------------------------ operators
 template <typename T>
 LevelDev<T>& view(hhg_ctx* c, int l);
@@ -598,6 +625,10 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     double bytes = MODE == MODE_RU ? c->bytes_ru : MODE == MODE_BP ? c->bytes_bp : c->bytes_res;
     Timed tm(c, HHG_K_APPLY, s, finest && (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_RES),
              bytes);
+    if (MODE == MODE_APPLY || MODE == MODE_RES) ops(c, l, 1, 2, 1, 0);
+    if (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_BTN) ops(c, l, 0, 1, 0, 0);
+    if (MODE == MODE_ARES) ops(c, l, 1, 0, 0, 0);
+    if (MODE == MODE_SCHUR) ops(c, l, 0, 1, 1, 0);
     if (MODE == MODE_APPLY || MODE == MODE_RES)
         launch_kx<T, (MODE == MODE_RES ? MODE_RES : MODE_APPLY), false>(c, v, ib, x, b, y, s);
     else
@@ -613,6 +644,7 @@ void residual_mirror(hhg_ctx* c, int l, const T* x, const T* b, T* r, hipStream_
     const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
     Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
     (void)grid;
+    ops(c, l, 1, 2, 1, 0);
     launch_kx<T, MODE_RES, true>(c, v, ib, x, b, r, s);
 }
 
@@ -645,6 +677,8 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
+    if (MODE == MODE_RU) ops(c, l, 0.25, 1, 0, 0);
+    else ops(c, l, 0, 1, 0.25, 0);
     if (v.n >= WIN_MIN_N) {
         hipLaunchKernelGGL((k_full<T, MODE, true, true, true>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s,
                            v, (const T*)x, b, t, c->partials, ib, x, col, (T)c->opts.omega);
@@ -662,6 +696,7 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
     const int ib = iface_blocks(cnt);
     const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
+    ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);
     if (vel) {
         Timed tm(c, HHG_K_VEL, s, finest, c->bytes_vel[col]);
         hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0), ib);
@@ -706,6 +741,7 @@ void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out,
         const int grid = ib + full_vblocks(MODE_RES, v.n_vtiles);
         Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
         (void)grid;
+        ops(c, l, 1, 2, 1, 0);
         launch_kx<T, MODE_RES, false>(c, v, ib, x, b, r, s);
     }
     // partial sums: per tile (one block per tile) or per tile and sub-row
@@ -872,6 +908,7 @@ void block_prec(hhg_ctx* c, int nu, const double* v, double* z, double* vz, hipS
     const size_t len = (size_t)c->H[L].len;
     fill_velocity<double>(c, L, z, s);
     vel_cycle<double>(c, L, nu, nu, z, v, s);
+    ops(c, L, 0, 0, 0, 1);
     hipLaunchKernelGGL(k_mr_precp_dot, dim3(vgrid(len)), dim3(TPB), 0, s, v, z, c->A[L].pinv,
                        c->A[L].owned, len, c->kpart);
     vreduce(c, len, vz, false, s);
@@ -1274,6 +1311,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     hhg_solve_info loc;
     hhg_solve_info* I = info ? info : &loc;
     std::memset(I, 0, sizeof(*I));
+    reset_ops(c);
     hipEvent_t e0 = next_event(c), e1 = next_event(c);
     double* r = c->A[c->L].r64;
     residual_norm<double>(c, c->L, x, b, r, c->scal, s);
@@ -1337,6 +1375,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
         I->t_solve_ms = ms;
     }
     if (I->cycles > 0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    put_ops(c, I);
     I->status = st;
     c->evused = c->timing ? c->evused : 0;
     LAUNCH_CHECK(c);
@@ -1717,6 +1756,7 @@ hhg_status hhg_pminres(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_
     hhg_solve_info loc;
     hhg_solve_info* I = info ? info : &loc;
     std::memset(I, 0, sizeof(*I));
+    reset_ops(c);
     const int L = c->L;
     const size_t len = (size_t)c->H[L].len, n4 = 4 * len;
     double* R = c->kv[0];
@@ -1816,6 +1856,7 @@ hhg_status hhg_pminres(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_
     if (e1) (void)hipEventRecord(e1, s);
     I->t_solve_ms = event_ms(e0, e1);
     if (I->cycles > 0 && I->rel_res > 0.0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    put_ops(c, I);
     I->status = st;
     c->evused = c->timing ? c->evused : 0;
     LAUNCH_CHECK(c);
@@ -1842,6 +1883,7 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
     hhg_solve_info loc;
     hhg_solve_info* I = info ? info : &loc;
     std::memset(I, 0, sizeof(*I));
+    reset_ops(c);
     const int L = c->L;
     const size_t len = (size_t)c->H[L].len, n4 = 4 * len;
     double* T = c->kv[0];              // velocity right-hand sides
@@ -1877,6 +1919,7 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
         for (int q = 0; q < n_A; ++q) vel_cycle<double>(c, L, nu, nu, x, T, s);
         // CG on S p = B A^-1 f - g from p with rho = B u - C p - g
         full_pass<double, MODE_SCHUR>(c, L, x, nullptr, Y, s);
+        ops(c, L, 0, 0, 0, 1);
         hipLaunchKernelGGL(k_cg_start, dim3(vgrid(len)), dim3(TPB), 0, s,
                            (const double*)(Y + 3 * len), b + 3 * len, RHO, ZP, D, pinv, own, len,
                            c->kpart);
@@ -1889,6 +1932,7 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
             for (int q = 0; q < n_I; ++q) vel_cycle<double>(c, L, nu, nu, DW, T, s);
             full_pass<double, MODE_SCHUR>(c, L, DW, nullptr, Y, s);
             vdot(c, D, Y + 3 * len, 1, dy, s);
+            ops(c, L, 0, 0, 0, 1);
             hipLaunchKernelGGL(k_cg_step, dim3(vgrid(len)), dim3(TPB), 0, s, x + 3 * len,
                                (const double*)D, RHO, (const double*)(Y + 3 * len), ZP, pinv, own,
                                len, (const double*)(rz + cur), (const double*)dy, c->kpart);
@@ -1909,6 +1953,7 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
     if (e1) (void)hipEventRecord(e1, s);
     I->t_solve_ms = event_ms(e0, e1);
     if (I->cycles > 0 && I->rel_res > 0.0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
+    put_ops(c, I);
     I->status = st;
     c->evused = c->timing ? c->evused : 0;
     LAUNCH_CHECK(c);
