@@ -11,6 +11,12 @@ Follows Section 2 of the paper:
     g_l(q) = -sum_T delta_T h_T^2 <f, grad q>_T with h_T = |T|^(1/3) and
     delta_T = 1/12.
   * eq. (linear-system): K = [[A, B^T], [B, -C]], right-hand side (f, g).
+  * the D form a_2(u,v) = 2 <nu D(u), D(v)> with D(u) = (grad u + grad u^T)/2
+    (eq. cauchystress and the forms below eq. varform): for P1 functions
+    2 D(phi_b e_l) : D(phi_a e_k) = delta_kl grad phi_a . grad phi_b
+    + d_l phi_a d_k phi_b, so A_2 = diag(A_1, A_1, A_1) + E with the coupling
+    blocks E^{kl}[a, b] = sum_T nu_T |T| d_l phi_a d_k phi_b (row a and
+    component k test, column b and component l trial).
 
 Everything is assembled element by element on the global mesh with generic P1
 formulas (gradients of the barycentric coordinates from the inverse of the
@@ -104,6 +110,8 @@ class Level:
     Gf: list = field(default_factory=list)   # g_l as a map of nodal f_k: g = sum_k Gf_k f_k
     colour: np.ndarray = None  # [N] (X+Y+Z) mod 4
     mass: np.ndarray = None    # [N] int phi_i (row sums of M)
+    E: list = None             # D form only: E[k][l] coupling blocks (N x N)
+    A2: sp.csr_matrix = None   # D form only: the 3N x 3N velocity block (component major)
 
     @property
     def N(self):
@@ -122,10 +130,14 @@ def _assemble(rows, cols, vals, N):
     return sp.coo_matrix((vals.ravel(), (rows.ravel(), cols.ravel())), shape=(N, N)).tocsr()
 
 
-def assemble_level(lv: Level, nu_macro, chunk=1 << 21):
-    """Element-by-element assembly of A (a_1), C (c_l), M, B_k and the g_l map."""
+def assemble_level(lv: Level, nu_macro, chunk=1 << 21, op="laplace"):
+    """Element-by-element assembly of A (a_1), C (c_l), M, B_k and the g_l map;
+    for op == "D" also the coupling blocks E of a_2 and the velocity block A_2."""
     N = lv.N
-    mats = {k: None for k in ("A", "C", "M", "B0", "B1", "B2", "G0", "G1", "G2")}
+    keys = ["A", "C", "M", "B0", "B1", "B2", "G0", "G1", "G2"]
+    if op == "D":
+        keys += [f"E{k}{l}" for k in range(3) for l in range(3)]
+    mats = {k: None for k in keys}
     nt = lv.tets.shape[0]
     eye = np.eye(4)
     for s in range(0, nt, chunk):
@@ -149,6 +161,12 @@ def assemble_level(lv: Level, nu_macro, chunk=1 << 21):
             # g_l(phi_a) for f = phi_b e_k: -delta h_T^2 (|T|/4) d_k phi_a
             part[f"G{k}"] = np.broadcast_to((-DELTA * hT2 * vol / (4.0 * nu))[:, None, None]
                                             * G[:, :, None, k], (T.shape[0], 4, 4))
+        if op == "D":
+            for k in range(3):
+                for l in range(3):
+                    # nu |T| d_l phi_a d_k phi_b, a the row (test) node
+                    part[f"E{k}{l}"] = (nu * vol)[:, None, None] * (G[:, :, None, l]
+                                                                   * G[:, None, :, k])
         for key, val in part.items():
             m = _assemble(rows, cols, np.ascontiguousarray(val), N)
             mats[key] = m if mats[key] is None else mats[key] + m
@@ -156,6 +174,10 @@ def assemble_level(lv: Level, nu_macro, chunk=1 << 21):
     lv.B = [mats[f"B{k}"] for k in range(3)]
     lv.Gf = [mats[f"G{k}"] for k in range(3)]
     lv.mass = np.asarray(lv.M.sum(axis=1)).ravel()
+    if op == "D":
+        lv.E = [[mats[f"E{k}{l}"] for l in range(3)] for k in range(3)]
+        lv.A2 = sp.bmat([[lv.E[k][l] + (lv.A if k == l else 0) for l in range(3)]
+                         for k in range(3)], format="csr")
 
 
 def _dirichlet_nodes(X, n, macro_int, tet, face_bc):
@@ -178,7 +200,7 @@ def _dirichlet_nodes(X, n, macro_int, tet, face_bc):
     return mask
 
 
-def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu):
+def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu, op="laplace"):
     n = 1 << R
     ext = macro_int.max(axis=0).astype(np.int64) * n + 1
     shape = (int(ext[0]), int(ext[1]), int(ext[2]))
@@ -192,7 +214,7 @@ def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu):
     lv = Level(R=R, n=n, shape=shape, lat=lat, X=X, tets=tets, tet_macro=tet_macro,
                vol=vol, G=G, dirichlet=_dirichlet_nodes(X, n, macro_int, tet, face_bc))
     lv.colour = (X.sum(axis=1) % 4).astype(np.int64)
-    assemble_level(lv, nu)
+    assemble_level(lv, nu, op=op)
     return lv
 
 
@@ -232,14 +254,18 @@ class Hierarchy:
     P: list                    # P[l] maps level l-1 -> level l (P[0] is None)
     nu: np.ndarray
     project: bool              # pressure determined up to a constant (no natural face)
+    op: str = "laplace"        # velocity form: "laplace" (a_1) or "D" (a_2)
 
     @property
     def finest(self):
         return self.levels[-1]
 
 
-def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2):
-    """Levels R0..R of the uniformly refined macro mesh (xyz must be integer)."""
+def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2, op="laplace"):
+    """Levels R0..R of the uniformly refined macro mesh (xyz must be integer);
+    op selects the velocity form, "laplace" (a_1) or "D" (a_2)."""
+    if op not in ("laplace", "D"):
+        raise ValueError(op)
     macro_int = np.rint(xyz).astype(np.int64)
     if not np.array_equal(macro_int, xyz):
         raise ValueError("oracle expects macro vertices on the integer lattice")
@@ -249,13 +275,13 @@ def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2):
     for _ in range(R0):
         P = refine(P)
         tet_macro = np.repeat(tet_macro, 8)
-    levels = [_make_level(P, tet_macro, R0, macro_int, tet, face_bc, nu)]
+    levels = [_make_level(P, tet_macro, R0, macro_int, tet, face_bc, nu, op)]
     prol = [None]
     for r in range(R0 + 1, R + 1):
         P = refine(P)
         tet_macro = np.repeat(tet_macro, 8)
-        lv = _make_level(P, tet_macro, r, macro_int, tet, face_bc, nu)
+        lv = _make_level(P, tet_macro, r, macro_int, tet, face_bc, nu, op)
         prol.append(_prolongation(levels[-1], None, lv))
         levels.append(lv)
     project = not np.any(face_bc == 2)
-    return Hierarchy(levels=levels, P=prol, nu=nu, project=project)
+    return Hierarchy(levels=levels, P=prol, nu=nu, project=project, op=op)

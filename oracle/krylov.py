@@ -62,6 +62,8 @@ class VelocityMG:
     components), cycle V(nu1, nu2) with (FHGS, BHGS) smoothing."""
 
     def __init__(self, H: Hierarchy, nu1=1, nu2=1):
+        if H.op != "laplace":
+            raise ValueError("the velocity multigrid here is for the Laplace form")
         self.H = H
         self.nu1, self.nu2 = nu1, nu2
         self.L = len(H.levels) - 1

@@ -30,6 +30,12 @@ Readings taken (listed again in the design notes):
     null space.
   * stopping criterion (Section 3.6): ||K x_k - f~||_2 <= eps ||K x_0 - f~||_2,
     Euclidean over free velocity rows and all pressure rows.
+  * D form (a_2, Section 2.1): the velocity block couples the three
+    components, so the velocity sweep is a point-block Gauss-Seidel: at each
+    vertex of the colour the 3x3 diagonal block is solved exactly.  The
+    same 4-colouring applies (the coupling stays within the 15-point
+    neighbourhood), and with the order 0 1 2 3 2 1 0 the repeated sweep of
+    colour 3 is again skipped.
 """
 from __future__ import annotations
 
@@ -47,6 +53,7 @@ class UMG:
         self.variable = variable
         self.p_sweep = p_sweep
         self.L = len(H.levels) - 1
+        self.dform = H.op == "D"
         self._gs = []
         for lv in H.levels:
             dA, dC = lv.A.diagonal(), lv.C.diagonal()
@@ -54,7 +61,15 @@ class UMG:
             for c in range(4):
                 iv = np.nonzero(lv.free & (lv.colour == c))[0]
                 ip = np.nonzero(lv.colour == c)[0]
-                g["v"].append((iv, lv.A[iv], dA[iv]))
+                if self.dform:
+                    r3 = np.concatenate([iv, iv + lv.N, iv + 2 * lv.N])
+                    blk = np.empty((iv.shape[0], 3, 3))
+                    for k in range(3):
+                        for l in range(3):
+                            blk[:, k, l] = lv.A2[iv + k * lv.N, iv + l * lv.N].A.ravel()
+                    g["v"].append((iv, r3, lv.A2[r3], np.linalg.inv(blk)))
+                else:
+                    g["v"].append((iv, lv.A[iv], dA[iv]))
                 g["p"].append((ip, lv.C[ip], dC[ip]))
             self._gs.append(g)
         self._coarse = self._factor_coarse(H.levels[0])
@@ -73,13 +88,7 @@ class UMG:
     def apply(self, l, x):
         """y = K x on free velocity rows and all pressure rows; x carries the
         Dirichlet values in its Dirichlet velocity entries."""
-        lv = self.H.levels[l]
-        y = np.zeros_like(x)
-        for k in range(3):
-            y[k] = lv.A @ x[k] + lv.B[k].T @ x[3]
-            y[k][lv.dirichlet] = 0.0
-        y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
-        return y
+        return apply_level(self.H.levels[l], x)
 
     def residual(self, l, x, b):
         return b - self.apply(l, x)
@@ -90,9 +99,19 @@ class UMG:
 
     # -- smoother (eq. Uzawa_smooth) ---------------------------------------
     def sgs(self, l, r):
-        """Ahat^{-1} r: one symmetric Gauss-Seidel sweep on A d = r from d = 0."""
+        """Ahat^{-1} r: one symmetric Gauss-Seidel sweep on A d = r from d = 0
+        (Laplace form: per component; D form: r and the result are [3, N]
+        and every vertex solves its 3x3 diagonal block)."""
         d = np.zeros_like(r)
         order = list(range(4)) + list(range(3, -1, -1))
+        if self.dform:
+            N = r.shape[-1]
+            rf, df = r.ravel(), d.ravel()
+            for c in order:
+                iv, r3, rows, dinv = self._gs[l]["v"][c]
+                res = (rf[r3] - rows @ df).reshape(3, -1)
+                df[r3] += np.einsum("ikl,li->ki", dinv, res).ravel()
+            return df.reshape(3, N)
         for c in order:
             idx, rows, diag = self._gs[l]["v"][c]
             d[idx] += (r[idx] - rows @ d) / diag
@@ -113,10 +132,16 @@ class UMG:
     def uzawa(self, l, x, b):
         lv = self.H.levels[l]
         u, p = x[:3], x[3]
-        for k in range(3):
-            ru = b[k] - lv.A @ u[k] - lv.B[k].T @ p
-            ru[lv.dirichlet] = 0.0
-            u[k] += self.sgs(l, ru)
+        if self.dform:
+            au = (lv.A2 @ u.ravel()).reshape(3, -1)
+            ru = np.stack([b[k] - au[k] - lv.B[k].T @ p for k in range(3)])
+            ru[:, lv.dirichlet] = 0.0
+            u += self.sgs(l, ru)
+        else:
+            for k in range(3):
+                ru = b[k] - lv.A @ u[k] - lv.B[k].T @ p
+                ru[lv.dirichlet] = 0.0
+                u[k] += self.sgs(l, ru)
         s = sum(lv.B[k] @ u[k] for k in range(3)) - lv.C @ p - b[3]
         x[3] = p + self.sor(l, s)
         return x
@@ -144,6 +169,9 @@ class UMG:
         for k in range(3):
             Bk = lv.B[k][:, fr].toarray()
             K[k * nf:(k + 1) * nf, k * nf:(k + 1) * nf] = A
+            if lv.E is not None:
+                for l in range(3):
+                    K[k * nf:(k + 1) * nf, l * nf:(l + 1) * nf] += lv.E[k][l][fr][:, fr].toarray()
             K[3 * nf:, k * nf:(k + 1) * nf] = Bk
             K[k * nf:(k + 1) * nf, 3 * nf:] = Bk.T
         K[3 * nf:, 3 * nf:] = -lv.C.toarray()
@@ -254,8 +282,9 @@ class UMG:
 def apply_level(lv, x):
     """y = K x on one level (same as UMG.apply, usable without a hierarchy)."""
     y = np.zeros_like(x)
+    au = (lv.A2 @ x[:3].ravel()).reshape(3, -1) if lv.A2 is not None else None
     for k in range(3):
-        y[k] = lv.A @ x[k] + lv.B[k].T @ x[3]
+        y[k] = (au[k] if au is not None else lv.A @ x[k]) + lv.B[k].T @ x[3]
         y[k][lv.dirichlet] = 0.0
     y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
     return y
@@ -279,6 +308,10 @@ def direct_solve(lv, b, project, xbc=None):
     blocks = [[None] * 4 for _ in range(4)]
     for k in range(3):
         blocks[k][k] = A
+        if lv.E is not None:
+            for l in range(3):
+                Ekl = lv.E[k][l][fr][:, fr]
+                blocks[k][l] = Ekl if blocks[k][l] is None else blocks[k][l] + Ekl
         Bk = lv.B[k][:, fr]
         blocks[3][k] = Bk
         blocks[k][3] = Bk.T
