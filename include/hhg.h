@@ -102,6 +102,18 @@ typedef struct {
     int32_t krylov;       /* 1: reserve the ten finest-level vectors (4 fields each) of
                              hhg_pminres and hhg_scg; 0 (default): those calls return
                              HHG_EINVAL */
+    int32_t graphs;       /* 1: hhg_solve captures the launches of one cycle and its
+                             stopping test in a HIP graph on first use for an (x, b) pair
+                             and replays it (at most four pairs kept; the capture records
+                             launches without running them); 0 (default): plain launches
+                             on the stream.  Results are bitwise identical either way */
+    int32_t op;           /* velocity form (Section 2.1, eq. varform): 0 the Laplace form
+                             a_1 = <nu grad u, grad v> (default); 1 the D form
+                             a_2 = 2 <nu D(u), D(v)>, whose velocity block couples the
+                             components: the velocity sweeps become point-block Gauss-Seidel
+                             (3x3 centre block solved exactly, same colours and order).  The
+                             D form needs coarse_solver = 0; hhg_vel_cycle, hhg_pminres,
+                             hhg_scg and hhg_grad return HHG_EINVAL for it */
 } hhg_opts;
 
 /* Result of hhg_solve. */

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32),
                 ("coarse_prec", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
-                ("krylov", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("graphs", ctypes.c_int32), ("op", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

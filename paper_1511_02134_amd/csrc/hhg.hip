@@ -90,6 +90,15 @@ struct hhg_ctx {
     // operator evaluations per level (A, B, C, M) since the last reset; a
     // colour sweep counts a quarter of its operator (Section 4.2)
     std::vector<std::array<double, 4>> opc;
+    // captured solver cycles (hhg_solve), re-used while x and b stay the same
+    struct CycleGraph {
+        const void* x;
+        const void* b;
+        hipGraphExec_t exec;
+        std::vector<std::array<double, 4>> ops;   // operator counts of one replay
+    };
+    std::vector<CycleGraph> graphs;
+    hipStream_t cap = nullptr;
     std::string err;
     // timing
     bool timing = false;
@@ -137,8 +146,16 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
         *err = "invalid coarse solver settings";
         return false;
     }
-    if (o->krylov < 0 || o->krylov > 1) {
-        *err = "krylov must be 0 or 1";
+    if (o->krylov < 0 || o->krylov > 1 || o->graphs < 0 || o->graphs > 1) {
+        *err = "krylov and graphs must be 0 or 1";
+        return false;
+    }
+    if (o->op < 0 || o->op > 1) {
+        *err = "op must be 0 (Laplace form) or 1 (D form)";
+        return false;
+    }
+    if (o->op == 1 && o->coarse_solver != 0) {
+        *err = "the D form needs the exact coarse solver (coarse_solver = 0)";
         return false;
     }
     return true;
@@ -167,7 +184,7 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
         for (int32_t t : c->H[l].rif_fine)
             if (t < 0) return fail(c, HHG_EINVAL, "internal error: coarse interface vertex missing");
     }
-    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, &c->CH, &err))
+    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, c->opts.op == 1, &c->CH, &err))
         return fail(c, HHG_EINVAL, err);
     if (c->CH.nd > 4096) return fail(c, HHG_EINVAL, "coarse system larger than 4096 unknowns");
     return HHG_OK;
@@ -483,7 +500,9 @@ hhg_status upload_all(hhg_ctx* c) {
     const double vs = c->opts.precision == 1 ? 4.0 : 8.0;
     for (int col = 0; col < 4; ++col) {
         const double nbr = Nc[(col + 1) & 3] + Nc[(col + 3) & 3];
-        c->bytes_vel[col] = vs * 3.0 * (nbr + 2.0 * Nfc[col]);
+        // the D form's velocity sweep reads the neighbours of every other colour
+        const double vnbr = c->opts.op == 1 ? Nall - Nc[col] : nbr;
+        c->bytes_vel[col] = vs * 3.0 * (vnbr + 2.0 * Nfc[col]);
         c->bytes_pres[col] = vs * (nbr + 3.0 * Nc[col]);
     }
     c->bytes_ru = vs * (Nall + 6.0 * Nf);
@@ -558,6 +577,59 @@ void put_ops(hhg_ctx* c, hhg_solve_info* I) {
     }
 }
 
+// ------------------------------------------------------------------ captured cycles
+void drop_graphs(hhg_ctx* c) {
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+// Executable graph of body(stream) for the pair (x, b): captured on the
+// library's own stream the first time (the launches are recorded, not run)
+// and kept; at most four pairs are kept.  Returns nullptr if capturing fails
+// (the caller then launches on its stream).
+template <typename F>
+hhg_ctx::CycleGraph* cycle_graph(hhg_ctx* c, const void* x, const void* b, F&& body) {
+    for (auto& g : c->graphs)
+        if (g.x == x && g.b == b) return &g;
+    if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        c->cap = nullptr;
+        return nullptr;
+    }
+    const std::vector<std::array<double, 4>> before = c->opc;
+    if (hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    body(c->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    std::vector<std::array<double, 4>> delta = c->opc;
+    c->opc = before;
+    if (e != hipSuccess || !graph) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    for (size_t l = 0; l < delta.size(); ++l)
+        for (int q = 0; q < 4; ++q) delta[l][q] -= before[l][q];
+    if (c->graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back(hhg_ctx::CycleGraph{x, b, exec, delta});
+    return &c->graphs.back();
+}
+
+// replay of a captured cycle on stream s, with its operator counts
+hipError_t replay(hhg_ctx* c, hhg_ctx::CycleGraph* g, hipStream_t s) {
+    for (size_t l = 0; l < g->ops.size(); ++l)
+        for (int q = 0; q < 4; ++q) c->opc[l][q] += g->ops[l][q];
+    return hipGraphLaunch(g->exec, s);
+}
+
 // ------------------------------------------------------------------ operators
 template <typename T>
 LevelDev<T>& view(hhg_ctx* c, int l);
@@ -601,19 +673,29 @@ constexpr int SPLIT_MIN_N = 64;
 
 // K x or the residual (MODE_APPLY / MODE_RES); MIRROR: interface taps from
 // the level's mirror of x
-template <typename T, int MODE, bool MIRROR>
-void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
+template <typename T, int MODE, bool MIRROR, bool DOP>
+void launch_kx_op(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
     if (v.n >= SPLIT_MIN_N) {
         // volume launch: one vertex per lane (four blocks per tile)
-        hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1>), dim3(full_blocks(v.n_vtiles)),
-                           dim3(TPB), 0, s, v, x, b, y, c->partials, 0, (T*)nullptr, -1, T(0));
+        hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1, DOP>),
+                           dim3(full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, x, b, y, c->partials, 0,
+                           (T*)nullptr, -1, T(0));
         if (ib > 0)
-            hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 2>), dim3(ib), dim3(TPB), 0, s, v,
-                               x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+            hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 2, DOP>), dim3(ib), dim3(TPB), 0,
+                               s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
         return;
     }
-    hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s, v, x,
-                       b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+    hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 0, DOP>), dim3(ib + v.n_vtiles),
+                       dim3(TPB), 0, s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+}
+
+// the velocity form of the context: Laplace (a_1) or D (a_2)
+template <typename T, int MODE, bool MIRROR>
+void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
+    if (c->opts.op == 1)
+        launch_kx_op<T, MODE, MIRROR, true>(c, v, ib, x, b, y, s);
+    else
+        launch_kx_op<T, MODE, MIRROR, false>(c, v, ib, x, b, y, s);
 }
 
 template <typename T, int MODE>
@@ -699,7 +781,12 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
     ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);
     if (vel) {
         Timed tm(c, HHG_K_VEL, s, finest, c->bytes_vel[col]);
-        hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0), ib);
+        if (c->opts.op == 1)
+            hipLaunchKernelGGL((k_colour<T, true, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
+                               T(0), ib);
+        else
+            hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0),
+                               ib);
     } else {
         Timed tm(c, HHG_K_PRES, s, finest, c->bytes_pres[col]);
         hipLaunchKernelGGL((k_colour<T, false>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
@@ -712,9 +799,15 @@ template <typename T>
 void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
     // colour 3 right after the first would recompute identical values); the
-    // first sweep runs inside the pass that forms f - B^T p
-    full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
+    // first sweep runs inside the pass that forms f - B^T p, except for the D
+    // form, whose point-block sweeps run on their own
     static const int vorder[6] = {1, 2, 3, 2, 1, 0};
+    if (c->opts.op == 1) {
+        full_pass<T, MODE_RU>(c, l, x, b, t, s);
+        colour_pass<T>(c, l, 0, true, x, t, s);
+    } else {
+        full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
+    }
     for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
     full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
@@ -958,6 +1051,8 @@ void hhg_default_opts(hhg_opts* o) {
     o->coarse_prec = 1;
     o->coarse_solver = 0;
     o->krylov = 0;
+    o->graphs = 0;
+    o->op = 0;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }
@@ -1003,6 +1098,8 @@ hhg_status hhg_create(const hhg_mesh* mesh, int32_t R, const hhg_opts* opts, voi
 void hhg_destroy(hhg_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
 }
 
@@ -1340,12 +1437,22 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     const bool fp64 = c->opts.precision != 1;
     if (fp64) mirror_refresh<double>(c, c->L, x, s);
     int k = 0;
-    for (k = 1; k <= max_cycles; ++k) {
+    // one cycle and its stopping-test residual: the same launches every cycle,
+    // replayed from a captured graph unless graphs are off or timing is on
+    auto body = [&](hipStream_t st) {
         if (!fp64)
-            cycle_mixed(c, x, s);
+            cycle_mixed(c, x, st);
         else
-            cycle_fp64(c, x, b, s);
-        residual_norm<double>(c, c->L, x, b, r, c->scal, s, fp64);
+            cycle_fp64(c, x, b, st);
+        residual_norm<double>(c, c->L, x, b, r, c->scal, st, fp64);
+    };
+    hhg_ctx::CycleGraph* graph =
+        (c->opts.graphs && !c->timing) ? cycle_graph(c, x, b, body) : nullptr;
+    for (k = 1; k <= max_cycles; ++k) {
+        if (graph)
+            HIPCHECK(c, replay(c, graph, s));
+        else
+            body(s);
         HIPCHECK(c, hipMemcpyAsync(&nrm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
         I->res_hist[k] = nrm;
@@ -1387,6 +1494,8 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
 hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, double* dnu,
                     void* df, hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->opts.op != 0)
+        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, x);
     CHECK_PTR(c, lam);
     CHECK_PTR(c, dnu);
@@ -1414,9 +1523,10 @@ hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
     std::string err;
     for (int l = 0; l <= c->L; ++l)
         if (!compute_stencils(c->mi, &c->H[l], &err)) return fail(c, HHG_EINVAL, err);
-    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, &c->CH, &err))
+    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, c->opts.op == 1, &c->CH, &err))
         return fail(c, HHG_EINVAL, err);
     if (!c->device) return HHG_OK;
+    drop_graphs(c);
     hhg_status st = upload_stencils(c);
     if (st != HHG_OK) return st;
     HIPCHECK(c, hipDeviceSynchronize());
@@ -1729,6 +1839,8 @@ hhg_status hhg_kernel_time(hhg_ctx* c, int32_t cls, int64_t* launches, double* m
 hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const void* b,
                          hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->opts.op != 0)
+        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, x);
     CHECK_PTR(c, b);
     if (x == b) return fail(c, HHG_EINVAL, "x and b must not alias");
@@ -1744,6 +1856,8 @@ hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const vo
 hhg_status hhg_pminres(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t maxit, int32_t nu,
                        hhg_solve_info* info, hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->opts.op != 0)
+        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, xv);
     CHECK_PTR(c, bv);
     if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");
@@ -1869,6 +1983,8 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
                    int32_t n_A, int32_t n_S, int32_t n_I, int32_t nu, hhg_solve_info* info,
                    hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->opts.op != 0)
+        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, xv);
     CHECK_PTR(c, bv);
     if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");

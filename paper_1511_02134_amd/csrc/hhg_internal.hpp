@@ -29,7 +29,13 @@ constexpr int ST_INVA = 225;   // 1 / A[0]
 constexpr int ST_INVC = 226;   // 1 / C[0]
 constexpr int ST_MASS = 227;   // int phi_x (row sum of M)
 constexpr int ST_MASSNU = 228; // sum over the tetrahedra T around x of (|T|/4) / nu_T
-constexpr int ST_SIZE = 232;
+// D form a_2 = 2 <nu D(u), D(v)>: the velocity block couples the components;
+// block (k, l) of 15 taps at ST_A2 + 15 (3 k + l) is delta_kl A + E^{kl} with
+// E^{kl} = sum_T nu_T |T| d_l phi_x d_k phi_y (x the row vertex, y the tap),
+// and the inverse of the 3x3 centre block (row major) follows.
+constexpr int ST_A2 = 232;
+constexpr int ST_DINV = 367;
+constexpr int ST_SIZE = 376;
 
 // Per-macro one-sided stencils for the viscosity gradient: the part of A, C
 // and G that comes from the fine tetrahedra of one macro only, at unit

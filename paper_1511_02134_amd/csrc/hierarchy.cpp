@@ -139,6 +139,10 @@ void add_element(double* rec, const Incident& t, double h, double nuA, double nu
             continue;
         }
         rec[ST_M + g] += vol / 20.0 * (a == b ? 2.0 : 1.0);
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                rec[ST_A2 + 15 * (3 * k + l) + g] +=
+                    nuA * vol * ((k == l ? gg : 0.0) + G[a][l] * G[b][k]);
         for (int k = 0; k < 3; ++k) {
             rec[ST_B + 15 * k + g] += -(vol / 4.0) * G[b][k];
             rec[ST_BT + 15 * k + g] += -(vol / 4.0) * G[a][k];
@@ -155,6 +159,29 @@ void add_element(double* rec, const Incident& t, double h, double nuA, double nu
 void finish_record(double* rec) {
     rec[ST_INVA] = rec[ST_A] != 0.0 ? 1.0 / rec[ST_A] : 0.0;
     rec[ST_INVC] = rec[ST_C] != 0.0 ? 1.0 / rec[ST_C] : 0.0;
+    // inverse of the (symmetric positive definite) 3x3 centre block of A_2
+    double m[3][3];
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) m[k][l] = rec[ST_A2 + 15 * (3 * k + l)];
+    const double c00 = m[1][1] * m[2][2] - m[1][2] * m[2][1];
+    const double c01 = m[1][2] * m[2][0] - m[1][0] * m[2][2];
+    const double c02 = m[1][0] * m[2][1] - m[1][1] * m[2][0];
+    const double det = m[0][0] * c00 + m[0][1] * c01 + m[0][2] * c02;
+    double* inv = rec + ST_DINV;
+    if (det == 0.0) {
+        for (int q = 0; q < 9; ++q) inv[q] = 0.0;
+        return;
+    }
+    const double id = 1.0 / det;
+    inv[0] = c00 * id;
+    inv[1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+    inv[2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+    inv[3] = c01 * id;
+    inv[4] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+    inv[5] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+    inv[6] = c02 * id;
+    inv[7] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+    inv[8] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
 }
 
 // global-order record -> macro-local order (blocks of 15 taps)
@@ -652,6 +679,7 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
         double* loc = &L.st[(size_t)m * ST_SIZE];
         to_local(M, g.data(), loc, 15);   // A, C, M, B(3), BT(3), G(3), GT(3)
         for (int q = ST_INVA; q < ST_SIZE; ++q) loc[q] = g[q];
+        to_local(M, g.data() + ST_A2, loc + ST_A2, 9);   // A_2 blocks
         if (!pair_symmetries(loc, err)) return false;
     }
     // interface stencils: every tetrahedron around the vertex belongs to the
@@ -757,8 +785,8 @@ static bool invert_dense(std::vector<double>& M, int n) {
     return true;
 }
 
-bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, CoarseHost* out,
-                  std::string* err) {
+bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dform,
+                  CoarseHost* out, std::string* err) {
     CoarseHost& C = *out;
     const int N = (int)L.N;
     C.N = N;
@@ -803,7 +831,13 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, CoarseHos
                 int w = g == 0 ? v : nbr(v, g);
                 if (w < 0) continue;
                 if (vidx[w] >= 0) {
-                    push(k * nfv + vidx[w], r[ST_A + g]);
+                    if (dform) {
+                        // D form: the velocity rows couple all three components
+                        for (int l = 0; l < 3; ++l)
+                            push(l * nfv + vidx[w], r[ST_A2 + 15 * (3 * k + l) + g]);
+                    } else {
+                        push(k * nfv + vidx[w], r[ST_A + g]);
+                    }
                     if (k == 0) A[(size_t)iv * nfv + vidx[w]] += r[ST_A + g];
                 }
                 push(3 * nfv + w, r[ST_BT + 15 * k + g]);

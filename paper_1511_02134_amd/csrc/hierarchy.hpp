@@ -111,7 +111,8 @@ struct CoarseHost {
     std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
 };
 constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns of the direct solver
-bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, CoarseHost* out,
+bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, bool dform,
+                  CoarseHost* out,
                   std::string* err);
 
 }  // namespace hhg

@@ -167,20 +167,60 @@ __host__ __device__ __forceinline__ bool near_boundary(int n, int i, int j, int 
     return i <= 1 || j <= 1 || k <= 1 || i + j + k >= n - 1;
 }
 
+// Point-block Gauss-Seidel update of the D form (a_2) at one vertex:
+// u(x) = D_xx^-1 (t(x) - sum_{taps g != 0} sum_l A_2^{kl}_g u_l(g)), D_xx the
+// 3x3 centre block of the record.  v[g] (g = 1..14) holds the slots of the
+// 14 neighbours in the record's tap order, in fields of stride xs.
+template <typename T>
+__device__ __forceinline__ void dform_block(const T* __restrict__ st, const int* v,
+                                            const T* __restrict__ u, size_t xs, T res[3]) {
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const T* ul = u + l * xs;
+#pragma unroll
+        for (int g = 1; g < 15; ++g) {
+            const T val = ul[v[g]];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) res[k] -= st[ST_A2 + 15 * (3 * k + l) + g] * val;
+        }
+    }
+    const T* di = st + ST_DINV;
+    const T r0 = res[0], r1 = res[1], r2 = res[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) res[k] = di[3 * k] * r0 + di[3 * k + 1] * r1 + di[3 * k + 2] * r2;
+}
+
 // One interface vertex t of a colour sweep: its neighbours come from the
 // mirror (unit-stride runs), the new value goes to every macro copy of the
 // vertex (the ghost exchange fused into the update) and to the mirror.
-template <typename T, bool VEL>
+// DOP: the velocity update of the D form (all 14 neighbours, 3x3 block).
+template <typename T, bool VEL, bool DOP = false>
 __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                              T* __restrict__ x, const T* __restrict__ rhs, T omega) {
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
     const int self = L.if_self[t];
     T* cx = L.cx;
+    const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+    if (VEL && DOP) {
+        int v[15];
+        v[0] = t;
+#pragma unroll
+        for (int g = 1; g < 15; ++g) v[g] = L.if_tap[(g - 1) * nif + t];
+        T res[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) res[f] = rhs[f * len + self];
+        dform_block<T>(st, v, cx, cs, res);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            for (int q = c0; q < c1; ++q) x[f * len + L.if_copy[q]] = res[f];
+            cx[f * cs + t] = res[f];
+        }
+        return;
+    }
     int nb[6];
 #pragma unroll
     for (int g = 0; g < 6; ++g) nb[g] = L.if_tap[g * nif + t];
-    const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
     if (VEL) {
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
@@ -206,7 +246,7 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
 
 // Colour sweeps keep the mirror of x current: a level's smoothing starts
 // with a current mirror (refreshed, filled or written by the prolongation).
-template <typename T, bool VEL>
+template <typename T, bool VEL, bool DOP = false>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
                                                 const T* __restrict__ rhs, T omega, int ib) {
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
@@ -221,9 +261,24 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         if (i < 1 || i > mm - 1 - j) return;
         Rows R;
         make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+        const T* st = L.st + (size_t)tl.macro * ST_SIZE;
+        if (VEL && DOP) {
+            int v[15];
+            nbr_slots(R, i, v);
+            const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[v[0]] : -1;
+            T res[3];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) res[f] = rhs[f * len + v[0]];
+            dform_block<T>(st, v, x, len, res);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                x[f * len + v[0]] = res[f];
+                if (cm >= 0) L.cx[f * cs + cm] = res[f];
+            }
+            return;
+        }
         int s[7];
         axis_slots(R, i, s);
-        const T* st = L.st + (size_t)tl.macro * ST_SIZE;
         const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
         if (VEL) {
             const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
@@ -253,7 +308,7 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
     if (t >= tend) return;
-    iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
+    iface_colour<T, VEL, DOP>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,7 +356,7 @@ __device__ __forceinline__ void eval_ares(const T* __restrict__ st, const int* t
     }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool DOP = false>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
                                           const T* __restrict__ x, size_t xs,
                                           const T* __restrict__ b, size_t bs, int bslot,
@@ -389,6 +444,35 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
     T pv[15];
 #pragma unroll
     for (int g = 0; g < 15; ++g) pv[g] = ldo(p, o[g]);
+    if (DOP) {
+        // D form: the velocity rows couple the three components
+        T ku[3] = {T(0), T(0), T(0)}, bu = T(0);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const T* u = x + l * xs;
+#pragma unroll
+            for (int g = 0; g < 15; ++g) {
+                const T uv = ldo(u, o[g]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) ku[k] += st[ST_A2 + 15 * (3 * k + l) + g] * uv;
+                bu += st[ST_B + 15 * l + g] * uv;
+            }
+        }
+        T cp = T(0);
+#pragma unroll
+        for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * pv[g];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            T btp = T(0);
+#pragma unroll
+            for (int g = 0; g < 15; ++g) btp += st[ST_BT + 15 * k + g] * pv[g];
+            const T kk = ku[k] + btp;
+            out[k] = dir ? T(0) : (MODE == MODE_RES ? b[k * bs + bslot] - kk : kk);
+        }
+        const T kp = bu - cp;
+        out[3] = MODE == MODE_RES ? b[3 * bs + bslot] - kp : kp;
+        return;
+    }
     T bu = T(0);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
@@ -607,7 +691,7 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
 // Interface vertex t of a full pass with the stencil record st.  With MIRROR
 // its taps of x come from the mirror; with FUSE (which needs the mirror) the
 // colour-fc vertices (velocity: those without Dirichlet data) are updated too.
-template <typename T, int MODE, bool FUSE, bool MIRROR>
+template <typename T, int MODE, bool FUSE, bool MIRROR, bool DOP = false>
 __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                            const T* __restrict__ x, const T* __restrict__ b, T* xw,
                                            int fcol, T omega, T out[4]) {
@@ -621,7 +705,7 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
 #pragma unroll
     for (int g = 1; g < 15; ++g) s[g] = taps[(g - 1) * nif + t];
     const bool dir = (L.if_flag[t] & 1) != 0;
-    eval_node<T, MODE>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out);
+    eval_node<T, MODE, DOP>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out);
     if (FUSE && t >= L.col_start[fcol] &&
         t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
         const int c0 = L.if_cptr[t];
@@ -633,12 +717,16 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
 // WIN (RU and BP only): one block per tile, a quad per lane, quad windows.
 // PART 1 / 2: a launch of the volume blocks only (ib = 0) or of the interface
 // blocks only (grid = ib); each then gets the registers of its own branch.
-template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false, int PART = 0>
+// DOP (K x and the residual only): the D form a_2, every row from eval_node.
+template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false, int PART = 0,
+          bool DOP = false>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
     static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP, "quad windows: RU and BP");
+    static_assert(!DOP || ((MODE == MODE_APPLY || MODE == MODE_RES) && !FUSE),
+                  "D form: K x and the residual");
     if (PART == 1) ib = 0;
     // volume block or interface block (decided at compile time for PART 1, 2)
     const bool vol = PART == 1 ? true : PART == 2 ? false : (int)blockIdx.x >= ib;
@@ -703,7 +791,9 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    if (MODE == MODE_APPLY || MODE == MODE_RES)
+                    if (DOP)
+                        eval_node<T, MODE, true>(st, s, false, x, len, b, len, s[0], out);
+                    else if (MODE == MODE_APPLY || MODE == MODE_RES)
                         eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
                     else
                         eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
@@ -736,6 +826,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                         const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
                         const int ca[7] = {0, 1, 2, 3, 4, 7, 8};
                         eval_ares<T>(st, tp, ca, false, x, len, b, len, s[0], out);
+                    } else if (DOP) {
+                        eval_node<T, MODE, true>(st, s, false, x, len, b, len, s[0], out);
                     } else if (MODE == MODE_APPLY || MODE == MODE_RES) {
                         eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
                     } else {
@@ -761,7 +853,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
             T out[4];
-            iface_full<T, MODE, FUSE, MIRROR>(L, st, t, x, b, xw, fcol, omega, out);
+            iface_full<T, MODE, FUSE, MIRROR, DOP>(L, st, t, x, b, xw, fcol, omega, out);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int f = f0; f < f1; ++f) {
                 for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
