@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
+                    help="velocity form: Laplace (a_1, default) or D (a_2 = 2<nu D(u), D(v)>)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-R", type=int, default=6,
                     help="refinements of the oracle's bounded sample")
@@ -295,7 +297,8 @@ def main():
     cfg = W.WORKLOADS[args.workload]
     xyz, tet, nu, tags = cfg.mesh()
     precision = 1 if cfg.precision == "mixed" else 0
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision)
+    dform = args.op == "D"
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0)
     dofs = s.num_dofs()
     dev = torch.device("cuda")
     f = torch.tensor(cfg.forcing_field(), dtype=torch.float64, device=dev)
@@ -349,7 +352,7 @@ def main():
     napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
     s.set_timing(False)
     vel_avg_ms = ms_vel / max(nvel, 1)
-    traffic = measured_traffic() if args.workload == 2 and precision == 0 else None
+    traffic = measured_traffic() if args.workload == 2 and precision == 0 and not dform else None
     achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
 
     line = {
@@ -371,6 +374,7 @@ def main():
             "refinements": cfg.R,
             "dofs": dofs,
             "cycle": "V(3,3)",
+            "form": "D (a_2)" if dform else "Laplace (a_1)",
             "rtol": 1e-8,
             "cycles": info["cycles"],
             "coarse": ("exact (inverse of the bordered level-0 system)" if s.opts.coarse_solver == 0
@@ -381,7 +385,8 @@ def main():
         "t_apply_ms": t_apply,
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"k_colour<{'double' if precision == 0 else 'float'},velocity> "
+            "kernel": (f"k_colour<{'double' if precision == 0 else 'float'},velocity"
+                       f"{',D' if dform else ''}> "
                        f"(finest level)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
