@@ -58,30 +58,52 @@ def lumped_mass_nu(lv, nu_macro):
 
 
 class VelocityMG:
-    """Multigrid for the scalar velocity block A (applied to each of the three
-    components), cycle V(nu1, nu2) with (FHGS, BHGS) smoothing."""
+    """Multigrid for the velocity block, cycle V(nu1, nu2) with (FHGS, BHGS)
+    smoothing.  Laplace form: the scalar A applied to each component.  D form
+    (a_2): the coupled block A_2, point-block Gauss-Seidel sweeps (the 3x3
+    block of each vertex solved exactly, as in the Uzawa smoother) and the
+    coupled level-0 block inverted exactly."""
 
     def __init__(self, H: Hierarchy, nu1=1, nu2=1):
-        if H.op != "laplace":
-            raise ValueError("the velocity multigrid here is for the Laplace form")
         self.H = H
         self.nu1, self.nu2 = nu1, nu2
         self.L = len(H.levels) - 1
+        self.dform = H.op == "D"
         self._gs = []
         for lv in H.levels:
             dA = lv.A.diagonal()
             g = []
             for c in range(4):
                 iv = np.nonzero(lv.free & (lv.colour == c))[0]
-                g.append((iv, lv.A[iv], dA[iv]))
+                if self.dform:
+                    r3 = np.concatenate([iv, iv + lv.N, iv + 2 * lv.N])
+                    blk = np.empty((iv.shape[0], 3, 3))
+                    for k in range(3):
+                        for m in range(3):
+                            blk[:, k, m] = lv.A2[iv + k * lv.N, iv + m * lv.N].A.ravel()
+                    g.append((r3, lv.A2[r3], np.linalg.inv(blk)))
+                else:
+                    g.append((iv, lv.A[iv], dA[iv]))
             self._gs.append(g)
         lv0 = H.levels[0]
         self._fr0 = np.nonzero(lv0.free)[0]
-        self._chol0 = sla.cho_factor(lv0.A[self._fr0][:, self._fr0].toarray())
+        if self.dform:
+            f3 = np.concatenate([self._fr0 + k * lv0.N for k in range(3)])
+            self._f30 = f3
+            self._chol0 = sla.cho_factor(lv0.A2[f3][:, f3].toarray())
+        else:
+            self._chol0 = sla.cho_factor(lv0.A[self._fr0][:, self._fr0].toarray())
 
     def sweep(self, l, u, b, order):
         """Gauss-Seidel on A u = b over the colours in `order` (in place; the
         nodes of one colour are mutually uncoupled)."""
+        if self.dform:
+            uf, bf = u.reshape(-1), b.reshape(-1)
+            for c in order:
+                r3, rows, dinv = self._gs[l][c]
+                res = (bf[r3] - rows @ uf).reshape(3, -1)
+                uf[r3] += np.einsum("ikm,mi->ki", dinv, res).ravel()
+            return u
         for c in order:
             idx, rows, diag = self._gs[l][c]
             for k in range(3):
@@ -90,13 +112,19 @@ class VelocityMG:
 
     def residual(self, l, u, b):
         lv = self.H.levels[l]
-        r = np.stack([b[k] - lv.A @ u[k] for k in range(3)])
+        if self.dform:
+            r = b[:3] - (lv.A2 @ u.reshape(-1)).reshape(3, -1)
+        else:
+            r = np.stack([b[k] - lv.A @ u[k] for k in range(3)])
         r[:, lv.dirichlet] = 0.0
         return r
 
     def coarse(self, b):
         lv = self.H.levels[0]
         u = np.zeros((3, lv.N))
+        if self.dform:
+            u.reshape(-1)[self._f30] = sla.cho_solve(self._chol0, b[:3].reshape(-1)[self._f30])
+            return u
         for k in range(3):
             u[k][self._fr0] = sla.cho_solve(self._chol0, b[k][self._fr0])
         return u
@@ -139,13 +167,8 @@ class StokesKrylov:
 
     # -- operators ------------------------------------------------------------
     def apply(self, x):
-        lv = self.lv
-        y = np.zeros_like(x)
-        for k in range(3):
-            y[k] = lv.A @ x[k] + lv.B[k].T @ x[3]
-            y[k][lv.dirichlet] = 0.0
-        y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
-        return y
+        from .umg import apply_level
+        return apply_level(self.lv, x)
 
     def norm(self, r):
         return float(np.sqrt(np.sum(r[:3, self.lv.free] ** 2) + np.sum(r[3] ** 2)))

@@ -151,3 +151,85 @@ def test_d_form_multigrid_rate_and_direct_solution():
     x, hist = umg.solve(np.zeros((4, H.finest.N)), b, rtol=1e-12)
     xd = direct_solve(H.finest, b, H.project)
     assert np.abs(x - xd).max() <= 1e-9 * np.abs(xd).max()
+
+
+def test_d_form_velocity_multigrid_two_grid_operator_and_symmetry():
+    """Velocity multigrid of the Krylov solvers for the D form: on two levels
+    V(1,1) has the error propagation (I - (D_B+U_B)^-1 A)(I - P A_c^-1 P^T A)
+    (I - (D_B+L_B)^-1 A) with the 3x3 vertex blocks D_B and the Galerkin
+    A_c = P^T A_2 P (equal to the rediscretised coupled block); V(1,1) from
+    zero is symmetric, V(1,0) and V(0,1) adjoint."""
+    from oracle.krylov import VelocityMG
+    import scipy.sparse as sp
+    _, H = _H(4, 3)
+    f, c = H.levels[1], H.levels[0]
+    ff = np.nonzero(f.free)[0]
+    ff = ff[np.argsort(f.colour[ff], kind="stable")]
+    fc = np.nonzero(c.free)[0]
+    F3 = np.concatenate([ff + k * f.N for k in range(3)])
+    C3 = np.concatenate([fc + k * c.N for k in range(3)])
+    A = f.A2[F3][:, F3].toarray()
+    P = sp.block_diag([H.P[1]] * 3).tocsr()[F3][:, C3].toarray()
+    Ac = P.T @ A @ P
+    assert np.allclose(Ac, c.A2[C3][:, C3].toarray(), rtol=1e-12, atol=1e-12 * np.abs(Ac).max())
+    nv = ff.shape[0]
+    vert = np.tile(np.arange(nv), 3)
+    col = f.colour[ff][vert]
+    same = vert[:, None] == vert[None, :]
+    lower = col[:, None] > col[None, :]
+    DB = np.where(same, A, 0.0)
+    LB = np.where(lower & ~same, A, 0.0)
+    UB = np.where(lower.T & ~same, A, 0.0)
+    I = np.eye(A.shape[0])
+    E = ((I - np.linalg.solve(DB + UB, A)) @ (I - P @ np.linalg.solve(Ac, P.T @ A))
+         @ (I - np.linalg.solve(DB + LB, A)))
+    rng = np.random.default_rng(1)
+    us = rng.normal(size=(3, f.N))
+    us[:, f.dirichlet] = 0.0
+    b = (f.A2 @ us.ravel()).reshape(3, -1)
+    b[:, f.dirichlet] = 0.0
+    u0 = rng.normal(size=(3, f.N))
+    u0[:, f.dirichlet] = 0.0
+    mg = VelocityMG(H, 1, 1)
+    u1 = mg.cycle(1, u0.copy(), b)
+    e_ref = E @ (us - u0).ravel()[F3]
+    assert np.allclose((us - u1).ravel()[F3], e_ref, rtol=1e-10, atol=1e-12 * np.abs(us).max())
+    _, H4 = _H(4, 4)
+    lv = H4.finest
+    b1, b2 = rng.normal(size=(3, lv.N)), rng.normal(size=(3, lv.N))
+    b1[:, lv.dirichlet] = 0.0
+    b2[:, lv.dirichlet] = 0.0
+    m11 = VelocityMG(H4, 1, 1)
+    s1, s2 = np.sum(m11.inv(b1) * b2), np.sum(b1 * m11.inv(b2))
+    assert abs(s1 - s2) <= 1e-12 * abs(s1)
+    s1 = np.sum(VelocityMG(H4, 1, 0).inv(b1) * b2)
+    s2 = np.sum(b1 * VelocityMG(H4, 0, 1).inv(b2))
+    assert abs(s1 - s2) <= 1e-12 * abs(s1)
+
+
+def test_d_form_krylov_solvers_reach_direct_solution_and_paper_trend():
+    """PMINRES and SCG for the D form converge to the direct solution (box,
+    variable viscosity); on the unit cube in the setting of Table
+    T:itertime_D_ser both need fewer iterations than for the Laplace form,
+    as the paper reports (PMINRES 68/65 against 73/70 at L = 4, 5)."""
+    from oracle.krylov import StokesKrylov
+    cfg, H = _H(4, 3)
+    lv = H.finest
+    b = UMG(H).rhs(W.fourier_forcing(W.lattice_points(cfg.a, 3), 41))
+    xd = direct_solve(lv, b, H.project)
+    x, hist = StokesKrylov(H, 1, 1).pminres(np.zeros((4, lv.N)), b, rtol=1e-12)
+    assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
+    x, hist = StokesKrylov(H, 3, 3).scg(np.zeros((4, lv.N)), b, rtol=1e-12)
+    assert np.abs(x - xd).max() <= 1e-8 * np.abs(xd).max()
+    its = {}
+    for op in ("laplace", "D"):
+        _, Hc = _H(1, 4, op)
+        lc = Hc.finest
+        hmin = (1.0 / (6 * lc.n ** 3)) ** (1.0 / 3.0)
+        x0 = W.random_initial_guess(lc.N, 1.0 / hmin, seed=0)
+        x0[:3, lc.dirichlet] = 0.0
+        z = np.zeros_like(x0)
+        its[op] = (len(StokesKrylov(Hc, 1, 1).pminres(x0, z)[1]) - 1,
+                   len(StokesKrylov(Hc, 3, 3).scg(x0, z)[1]) - 1)
+    assert its["D"][0] < its["laplace"][0] and its["D"][1] < its["laplace"][1], its
+    assert 50 <= its["D"][0] <= 80, its
