@@ -208,7 +208,7 @@ def run_tme(R: int, steps: int, warmup: int):
     print(json.dumps(line), flush=True)
 
 
-def run_compare(R: int, steps: int, warmup: int):
+def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     """The solver comparison of Section 4 (Table T:itertime1, Figure opcount):
     unit cube, f = 0, nu = 1, random start u0 ~ U[0,1], p0 ~ U[0, 1/h_min]
     (Section 3.6), relative residual 1e-8; UMG with the variable V(3,3)
@@ -222,7 +222,7 @@ def run_compare(R: int, steps: int, warmup: int):
 
     cfg = W.WORKLOADS[1].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    s = P.Solver(xyz, tet, nu, tags, R, cycle=1, krylov=1)
+    s = P.Solver(xyz, tet, nu, tags, R, cycle=1, krylov=1, op=1 if dform else 0)
     dev = torch.device("cuda")
     n = 2 ** R
     hmin = (1.0 / (6.0 * n ** 3)) ** (1.0 / 3.0)
@@ -253,6 +253,7 @@ def run_compare(R: int, steps: int, warmup: int):
                      "n_op": {k: round(v, 2) for k, v in info["n_op"].items()}}
     line = {"metric": "time to solution and operator evaluations of UMG, PMINRES and SCG",
             "workload": f"unit cube, {R} refinements, f = 0, random start (seed 0)",
+            "form": "D (a_2)" if dform else "Laplace (a_1)",
             "refinements": R, "paper_level": R - 2, "dofs": s.num_dofs(), "rtol": 1e-8,
             "dtype": "f64", "data": "synthetic", **out}
     print(json.dumps(line), flush=True)
@@ -283,7 +284,8 @@ def main():
         run_tme(args.tme, max(args.steps, 3), args.warmup)
         return
     if args.compare:
-        run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1))
+        run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1),
+                    args.op == "D")
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "

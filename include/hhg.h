@@ -111,9 +111,10 @@ typedef struct {
                              a_1 = <nu grad u, grad v> (default); 1 the D form
                              a_2 = 2 <nu D(u), D(v)>, whose velocity block couples the
                              components: the velocity sweeps become point-block Gauss-Seidel
-                             (3x3 centre block solved exactly, same colours and order).  The
-                             D form needs coarse_solver = 0; hhg_vel_cycle, hhg_pminres,
-                             hhg_scg and hhg_grad return HHG_EINVAL for it */
+                             (3x3 centre block solved exactly, same colours and order), also
+                             in the velocity multigrid of hhg_vel_cycle, hhg_pminres and
+                             hhg_scg.  The D form needs coarse_solver = 0; hhg_grad returns
+                             HHG_EINVAL for it */
 } hhg_opts;
 
 /* Result of hhg_solve. */
@@ -263,7 +264,8 @@ hhg_status hhg_solve(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int3
  * columns): V(nu1, nu2) with forward colour Gauss-Seidel (colours 0,1,2,3) in
  * the pre-smoothing and backward (3,2,1,0) in the post-smoothing steps, the
  * A-residual restricted by the transpose of P1 interpolation, A_0 inverted
- * exactly on level 0.  Fields 0..2 of d_x are updated in place (their
+ * exactly on level 0 (the D form: point-block sweeps, the coupled A_2
+ * residual and level-0 block).  Fields 0..2 of d_x are updated in place (their
  * Dirichlet entries are kept), field 3 is not touched; d_b fields 0..2 are
  * read (their Dirichlet rows are ignored).  0 <= nu1, nu2 <= 64, nu1 + nu2 > 0;
  * EINVAL on aliasing.  FP64. */

@@ -286,6 +286,8 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.node_copy = cv.take<int32_t>(C.node_copy.size());
     d.gscratch = cv.take<double>((size_t)8 * C.nd);
     d.zinv = cv.take<double>(std::max<size_t>(1, C.zinv.size()));
+    d.a2inv = cv.take<double>(std::max<size_t>(1, C.a2inv.size()));
+    d.coupled = C.a2inv.empty() ? 0 : 1;
     return cv.off + 256;
 }
 
@@ -369,6 +371,9 @@ hhg_status upload_stencils(hhg_ctx* c) {
     if ((s = upload<double>(c, (double*)c->cd.sinv, C.sinv.data(), C.sinv.size())) != HHG_OK)
         return s;
     if ((s = upload<double>(c, (double*)c->cd.zinv, C.zinv.data(), C.zinv.size())) != HHG_OK)
+        return s;
+    if (!C.a2inv.empty() &&
+        (s = upload<double>(c, (double*)c->cd.a2inv, C.a2inv.data(), C.a2inv.size())) != HHG_OK)
         return s;
     if ((s = upload<double>(c, (double*)c->cd.mass, C.mass.data(), C.mass.size())) != HHG_OK)
         return s;
@@ -713,6 +718,9 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     if (MODE == MODE_SCHUR) ops(c, l, 0, 1, 1, 0);
     if (MODE == MODE_APPLY || MODE == MODE_RES)
         launch_kx<T, (MODE == MODE_RES ? MODE_RES : MODE_APPLY), false>(c, v, ib, x, b, y, s);
+    else if (MODE == MODE_ARES && c->opts.op == 1)
+        hipLaunchKernelGGL((k_full<T, MODE_ARES, false, false, false, 0, true>), dim3(grid),
+                           dim3(TPB), 0, s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
     else
         hipLaunchKernelGGL((k_full<T, MODE, false, false>), dim3(grid), dim3(TPB), 0, s, v, x, b, y,
                            c->partials, ib, (T*)nullptr, -1, T(0));
@@ -1839,8 +1847,6 @@ hhg_status hhg_kernel_time(hhg_ctx* c, int32_t cls, int64_t* launches, double* m
 hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const void* b,
                          hhg_stream stream) {
     CHECK_DEV(c);
-    if (c->opts.op != 0)
-        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, x);
     CHECK_PTR(c, b);
     if (x == b) return fail(c, HHG_EINVAL, "x and b must not alias");
@@ -1856,8 +1862,6 @@ hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const vo
 hhg_status hhg_pminres(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t maxit, int32_t nu,
                        hhg_solve_info* info, hhg_stream stream) {
     CHECK_DEV(c);
-    if (c->opts.op != 0)
-        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, xv);
     CHECK_PTR(c, bv);
     if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");
@@ -1983,8 +1987,6 @@ hhg_status hhg_scg(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t ma
                    int32_t n_A, int32_t n_S, int32_t n_I, int32_t nu, hhg_solve_info* info,
                    hhg_stream stream) {
     CHECK_DEV(c);
-    if (c->opts.op != 0)
-        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, xv);
     CHECK_PTR(c, bv);
     if (xv == bv) return fail(c, HHG_EINVAL, "x and b must not alias");

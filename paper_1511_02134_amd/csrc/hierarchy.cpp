@@ -968,6 +968,21 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dfor
             }
         }
     }
+    // D form: inverse of the coupled free velocity block (velocity multigrid
+    // of the Krylov solvers), from the velocity-velocity entries of the rows
+    C.a2inv.clear();
+    if (dform) {
+        const int n3 = 3 * nfv;
+        std::vector<double> K((size_t)n3 * n3, 0.0);
+        for (int r = 0; r < n3; ++r)
+            for (int e = C.rowptr[r]; e < C.rowptr[r + 1]; ++e)
+                if (C.col[e] < n3) K[(size_t)r * n3 + C.col[e]] += C.val[e];
+        if (!invert_dense(K, n3)) {
+            *err = "coupled coarse velocity block is singular";
+            return false;
+        }
+        C.a2inv.swap(K);
+    }
     // direct solver: the inverse of K_0 bordered by the constraint
     // sum_i m_i p_i = 0 (only when the pressure has a null space); its leading
     // nd x nd block maps any right-hand side to the mean-zero solution of the

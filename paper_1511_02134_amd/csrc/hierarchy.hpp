@@ -105,6 +105,8 @@ struct CoarseHost {
                                     // pressure null space), symmetric
     std::vector<double> zinv;       // [nd][nd] solution operator of the level-0
                                     // system with the mean constraint (direct solver)
+    std::vector<double> a2inv;      // D form: [3 nfv][3 nfv] inverse of the coupled
+                                    // free velocity block
     std::vector<double> mass;       // [N] int phi_i
     std::vector<int32_t> vel_node;  // [nfv] lattice node of compact velocity vertex
     std::vector<int32_t> node_slot; // [N]

@@ -361,6 +361,21 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
                                           const T* __restrict__ x, size_t xs,
                                           const T* __restrict__ b, size_t bs, int bslot,
                                           T out[4]) {
+    if (MODE == MODE_ARES && DOP) {
+        // D form: every tap of all three components
+        T ru[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int g = 0; g < 15; ++g) {
+                const T uv = x[l * xs + s[g]];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) ru[k] += st[ST_A2 + 15 * (3 * k + l) + g] * uv;
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[k] = dir ? T(0) : b[k * bs + bslot] - ru[k];
+        return;
+    }
     if (MODE == MODE_ARES) {
         // interface rows: the axis taps are 1..6 of the global direction order
         const int ca[7] = {0, 1, 2, 3, 4, 5, 6};
@@ -725,8 +740,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
     static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP, "quad windows: RU and BP");
-    static_assert(!DOP || ((MODE == MODE_APPLY || MODE == MODE_RES) && !FUSE),
-                  "D form: K x and the residual");
+    static_assert(!DOP || ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_ARES) && !FUSE),
+                  "D form: K x and the residuals");
     if (PART == 1) ib = 0;
     // volume block or interface block (decided at compile time for PART 1, 2)
     const bool vol = PART == 1 ? true : PART == 2 ? false : (int)blockIdx.x >= ib;
@@ -821,7 +836,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     int s[15];
                     nbr_slots(R, i, s);
                     T out[4];
-                    if (MODE == MODE_ARES) {
+                    if (MODE == MODE_ARES && !DOP) {
                         // volume rows: axis taps 1, 2, 3, 4, 7, 8 of the local order
                         const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
                         const int ca[7] = {0, 1, 2, 3, 4, 7, 8};
@@ -1280,6 +1295,8 @@ struct CoarseDev {
     const int* node_copy;
     double* gscratch;       // 8 * nd doubles when the vectors do not fit in LDS
     const double* zinv;     // [nd][nd] solution operator (direct solver)
+    const double* a2inv;    // D form: [3 nfv][3 nfv] inverse of the coupled velocity block
+    int coupled;            // 1: the velocity block couples the components (D form)
     // what lives in the dynamic LDS (in this order): vectors, CSR (val, then
     // col and row pointers), A^-1, S^-1
     int vec_lds, csr_lds, ainv_lds, sinv_lds;

@@ -17,8 +17,9 @@ namespace hhg {
 constexpr int VGRID_MAX = 2048;   // workgroups of the reducing vector kernels
 
 // Velocity block of the level-0 system: x_k = A_0^-1 b_k on the free
-// vertices (every copy), zero on Dirichlet vertices, k = 0..2.  One wave per
-// row of the dense inverse; b gathered into LDS by every workgroup.
+// vertices (every copy), zero on Dirichlet vertices, k = 0..2 (D form: the
+// coupled block, x = A_2,0^-1 b over all three components at once).  One wave
+// per row of the dense inverse; b gathered into LDS by every workgroup.
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_coarse_avel(CoarseDev cd, const T* __restrict__ b,
                                                      size_t blen, T* __restrict__ x, size_t xlen) {
@@ -33,10 +34,15 @@ __global__ void __launch_bounds__(TPB) k_coarse_avel(CoarseDev cd, const T* __re
     const int row = (int)blockIdx.x * (TPB / 64) + ((int)threadIdx.x >> 6);
     if (row < 3 * nfv) {
         const int comp = row / nfv, r = row - comp * nfv;
-        const double* a = cd.ainv + (size_t)r * nfv;
-        const double* bb = bl + comp * nfv;
         double acc = 0.0;
-        for (int q = lane; q < nfv; q += 64) acc += a[q] * bb[q];
+        if (cd.coupled) {
+            const double* a = cd.a2inv + (size_t)row * 3 * nfv;
+            for (int q = lane; q < 3 * nfv; q += 64) acc += a[q] * bl[q];
+        } else {
+            const double* a = cd.ainv + (size_t)r * nfv;
+            const double* bb = bl + comp * nfv;
+            for (int q = lane; q < nfv; q += 64) acc += a[q] * bb[q];
+        }
         acc = wave_sum(acc);
         if (lane == 0) {
             const int vtx = cd.vel_node[r];
