@@ -5,6 +5,7 @@ the element matrices of the tetrahedra around the vertex, with the bilinear
 forms of Section 2.1 exactly as in the global assembly (fem.assemble_level):
 
   a_1:  nu_T |T| grad phi_a . grad phi_b                    (per component)
+  a_2:  a_1 + nu_T |T| d_l phi_a d_k phi_b (row component k, column l; D form)
   b:    b(phi_v e_k, phi_q) = -(|T|/4) d_k phi_v
   c_l:  delta h_T^2 / nu_T |T| grad phi_a . grad phi_b,  h_T = |T|^(1/3)
   f~:   M I_h f on free velocity rows (M_T = |T|/20 (1 + delta_ab)),
@@ -62,7 +63,7 @@ def _macro_of(points, xyz, tet):
     return out
 
 
-def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f):
+def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f, op="laplace"):
     """Rows of f~ and of K x at the vertices verts [m,3] (integer lattice
     coordinates at 2^R per unit length).
 
@@ -98,6 +99,9 @@ def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f):
         Mrow = (vol / 20.0)[:, None] * (1.0 + (np.arange(4)[None, :] == a[:, None]))
         for k in range(3):
             au = (nuT * vol)[:, None] * GG * u[k]
+            if op == "D":
+                au = au + sum((nuT * vol)[:, None] * Ga[:, l, None] * G[:, :, k] * u[l]
+                              for l in range(3))
             btp = -(vol / 4.0)[:, None] * Ga[:, k, None] * p
             mf = Mrow * fk[k]
             kx[k, m] = 0.0 if dirich[m] else np.sum(au) + np.sum(btp)

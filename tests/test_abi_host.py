@@ -78,6 +78,24 @@ def test_plan_rejects_bad_arguments():
     _expect_einval(xyz, tet, nu, tags, coarse_maxit=0)
     _expect_einval(xyz, tet, nu, tags, coarse_solver=2)
     _expect_einval(xyz, tet, nu, tags, coarse_prec=2)
+    _expect_einval(xyz, tet, nu, tags, op=2)
+    _expect_einval(xyz, tet, nu, tags, op=-1)
+    assert "exact coarse" in _expect_einval(xyz, tet, nu, tags, op=1, coarse_solver=1)
+    _expect_einval(xyz, tet, nu, tags, krylov=2)
+    _expect_einval(xyz, tet, nu, tags, graphs=-1)
+
+
+def test_krylov_vectors_are_reserved_on_request():
+    """krylov = 1 reserves ten finest-level vectors of 4 fields (FP64) and
+    nothing else; the D form and graphs change no workspace size."""
+    xyz, tet, nu, tags = _mesh()
+    base = P.plan(xyz, tet, nu, tags, 4)
+    kry = P.plan(xyz, tet, nu, tags, 4, krylov=1)
+    s = P.Solver(xyz, tet, nu, tags, 4, host_only=True)
+    need = 10 * 4 * s.vec_len() * 8
+    assert need <= kry - base <= need + 10 * 256
+    assert P.plan(xyz, tet, nu, tags, 4, op=1) >= base
+    assert P.plan(xyz, tet, nu, tags, 4, graphs=1) == base
 
 
 def test_host_context_rejects_device_calls():
@@ -87,6 +105,13 @@ def test_host_context_rejects_device_calls():
     assert st == P.HHG_EINVAL
     assert b"host-only" in P.lib.hhg_last_error(s.ctx)
     st = P.lib.hhg_solve(s.ctx, ctypes.c_void_p(16), ctypes.c_void_p(32), 1e-8, 5, None, None)
+    assert st == P.HHG_EINVAL
+    st = P.lib.hhg_pminres(s.ctx, ctypes.c_void_p(16), ctypes.c_void_p(32), 1e-8, 5, 1, None, None)
+    assert st == P.HHG_EINVAL
+    st = P.lib.hhg_scg(s.ctx, ctypes.c_void_p(16), ctypes.c_void_p(32), 1e-8, 5, 3, 3, 1, 3, None,
+                       None)
+    assert st == P.HHG_EINVAL
+    st = P.lib.hhg_vel_cycle(s.ctx, 1, 1, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
     assert st == P.HHG_EINVAL
 
 

@@ -2,7 +2,7 @@
 oracle's full multigrid (Section 5): every level's solution, for one and two
 variable V(2,2) cycles per level, on the analytic solution of the efficiency
 study (non-homogeneous Dirichlet data) and on the box with per-macro
-viscosity."""
+viscosity, in the Laplace and the D form."""
 import numpy as np
 import pytest
 import torch
@@ -17,14 +17,16 @@ def _dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-@pytest.mark.parametrize("cid,R,cycles", [(6, 4, 1), (6, 4, 2), (4, 4, 1), (6, 3, 2)])
-def test_fmg_matches_oracle(cid, R, cycles):
+@pytest.mark.parametrize("cid,R,cycles,op", [(6, 4, 1, "laplace"), (6, 4, 2, "laplace"),
+                                             (4, 4, 1, "laplace"), (6, 3, 2, "laplace"),
+                                             (6, 4, 1, "D"), (4, 4, 2, "D")])
+def test_fmg_matches_oracle(cid, R, cycles, op):
     import paper_1511_02134_amd as P
     cfg = W.WORKLOADS[cid].with_R(R)
-    print(f"\n[case] fmg {cfg.name} R={R} cycles={cycles}", flush=True)
+    print(f"\n[case] fmg {cfg.name} R={R} cycles={cycles} form={op}", flush=True)
     xyz, tet, nu, tags = cfg.mesh()
-    s = P.Solver(xyz, tet, nu, tags, R, nu1=2, nu2=2, cycle=1)
-    umg = UMG(build_hierarchy(xyz, tet, nu, tags, R), nu1=2, nu2=2, variable=True)
+    s = P.Solver(xyz, tet, nu, tags, R, nu1=2, nu2=2, cycle=1, op=1 if op == "D" else 0)
+    umg = UMG(build_hierarchy(xyz, tet, nu, tags, R, op=op), nu1=2, nu2=2, variable=True)
     xs, bs, bs_o, xbc = [], [], [], []
     for l in range(s.L + 1):
         c = cfg.with_R(2 + l)

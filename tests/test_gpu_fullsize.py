@@ -1,7 +1,7 @@
 """Full-size checks in the benchmark's launch configuration (default options,
 XCD-aware tile order), on the target workloads themselves: unit cube at 7
-refinements in FP64, at 8 refinements in mixed precision, and the channel at
-7 refinements in mixed precision.
+refinements in FP64 (Laplace and D form), at 8 refinements in mixed precision,
+and the channel at 7 refinements in mixed precision.
 
 The oracle cannot assemble these systems, so it evaluates rows one by one
 (oracle.rows, pinned against its global assembly) at sampled vertices: every
@@ -67,14 +67,14 @@ def _sample(cfg, seed, per_set=40):
     return P[np.all((P >= 0) & (P <= ext), axis=1)]
 
 
-@pytest.mark.parametrize("cid", [2, 3, 5])
-def test_full_size_solve_residual_rows(cid):
+@pytest.mark.parametrize("cid,op", [(2, "laplace"), (3, "laplace"), (5, "laplace"), (2, "D")])
+def test_full_size_solve_residual_rows(cid, op):
     import paper_1511_02134_amd as P
     cfg = W.WORKLOADS[cid]
     xyz, tet, nu, tags = cfg.mesh()
     precision = 1 if cfg.precision == "mixed" else 0
-    _announce(f"{cfg.name}: R={cfg.R}, precision={cfg.precision}")
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision)
+    _announce(f"{cfg.name}: R={cfg.R}, precision={cfg.precision}, form={op}")
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if op == "D" else 0)
     dev = torch.device("cuda")
     f = cfg.forcing_field()
     x0 = np.zeros((4, s.num_nodes()))
@@ -95,7 +95,7 @@ def test_full_size_solve_residual_rows(cid):
     verts = _sample(cfg, seed=100 + cid)
     nx, ny = cfg.a * 2 ** cfg.R + 1, 2 ** cfg.R + 1
     idx = verts[:, 0] + nx * (verts[:, 1] + ny * verts[:, 2])
-    b_o, kx_o, dirich, scale = stokes_rows(xyz, tet, nu, tags, cfg.R, verts, xg, f)
+    b_o, kx_o, dirich, scale = stokes_rows(xyz, tet, nu, tags, cfg.R, verts, xg, f, op=op)
     assert np.array_equal(dirich, dmask[idx])
     # rows of f~ and of the final residual f~ - K x, each against the sum of
     # the magnitudes of its products (FP64 rounding of ~100 products in any

@@ -9,12 +9,13 @@ from oracle import UMG, build_hierarchy
 from oracle.rows import stokes_rows
 
 
-@pytest.mark.parametrize("cid", [1, 4, 5])
-def test_rows_match_assembled_system(cid):
+@pytest.mark.parametrize("cid,op", [(1, "laplace"), (4, "laplace"), (5, "laplace"), (4, "D"),
+                                   (5, "D")])
+def test_rows_match_assembled_system(cid, op):
     R = 3
     cfg = W.WORKLOADS[cid].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    umg = UMG(build_hierarchy(xyz, tet, nu, tags, R))
+    umg = UMG(build_hierarchy(xyz, tet, nu, tags, R, op=op))
     lv = umg.H.finest
     rng = np.random.default_rng(7)
     x = rng.normal(size=(4, lv.N))
@@ -22,7 +23,7 @@ def test_rows_match_assembled_system(cid):
     b_ref = umg.rhs(f)
     kx_ref = umg.apply(umg.L, x)
     verts = lv.X
-    b, kx, dirich, scale = stokes_rows(xyz, tet, nu, tags, R, verts, x, f)
+    b, kx, dirich, scale = stokes_rows(xyz, tet, nu, tags, R, verts, x, f, op=op)
     # the magnitude sums bound the rows themselves (triangle inequality)
     assert np.all(scale >= np.abs(kx)) and np.all(scale >= np.abs(b))
     assert np.array_equal(dirich, lv.dirichlet)
