@@ -357,6 +357,25 @@ def main():
     traffic = measured_traffic() if args.workload == 2 and precision == 0 and not dform else None
     achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
 
+    # practical ceiling: device copies moving the sweep's algorithmic bytes per
+    # launch (half read, half written), timed like the sweeps: back-to-back
+    # launches on a busy stream, each bracketed by its own pair of hipEvents
+    per_launch = bytes_vel / max(nvel, 1)
+    src = torch.empty(int(per_launch // 16), dtype=torch.float64, device=dev).normal_()
+    dst = torch.empty_like(src)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(40)]
+    for _ in range(5):
+        dst.copy_(src)
+    for a, b_ in pairs:
+        a.record()
+        dst.copy_(src)
+        b_.record()
+    torch.cuda.synchronize()
+    ctime = float(np.mean([a.elapsed_time(b_) for a, b_ in pairs]))
+    copy_gbs = 2 * src.numel() * 8 / (ctime * 1e-3) / 1e9
+    del src, dst
+
     line = {
         "metric": METRIC,
         "value": dofs / (ms_per_step * 1e-3),
@@ -399,6 +418,8 @@ def main():
             "launches": nvel,
             "avg_us": 1000.0 * vel_avg_ms,
             "bytes_per_launch": bytes_vel / max(nvel, 1),
+            "copy_probe": {"GB/s": copy_gbs, "bytes": 2 * int(per_launch // 16) * 8,
+                           "frac_of_copy": achieved / copy_gbs},
         },
         "kernel_classes": {
             "velocity_sweep": {"launches": nvel, "ms": ms_vel,

@@ -236,11 +236,10 @@ size_t layout(hhg_ctx* c, char* ws) {
         const size_t v4 = 4 * (size_t)h.len;
         a.r64 = cv.take<double>(v4);
         a.t64 = cv.take<double>(v4);
-        a.x64 = a.b64 = nullptr;
-        if (l < c->L || true) {
-            a.x64 = cv.take<double>(v4);
-            a.b64 = cv.take<double>(v4);
-        }
+        // corrections and right-hand sides of the coarser levels; on the finest
+        // level the caller's x and b take their place
+        a.x64 = l < c->L ? cv.take<double>(v4) : nullptr;
+        a.b64 = l < c->L ? cv.take<double>(v4) : nullptr;
         a.x32 = a.b32 = a.r32 = a.t32 = nullptr;
         if (mixed) {
             a.x32 = cv.take<float>(v4);
