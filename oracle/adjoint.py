@@ -15,6 +15,9 @@ and
     where u includes its Dirichlet values and lambda vanishes on Dirichlet
     nodes.
 The pressure constant of lambda does not enter either gradient (G_k^T 1 = 0).
+For the D form a_2 = 2 <nu D(u), D(v)>, also linear in nu_e, the velocity
+part becomes -sum_{T in e} |T| 2 D(lambda_u) : D(u)
+= -sum_{T in e} |T| (sum_k grad(lambda_k) . grad(u_k) + sum_{k,l} d_l lambda_k d_k u_l).
 """
 from __future__ import annotations
 
@@ -38,17 +41,22 @@ def grad_forcing(lv, lam):
     return np.stack([lv.M @ lu[k] + lv.Gf[k].T @ lam[3] for k in range(3)])
 
 
-def grad_viscosity(lv, x, lam, f_nodal, nu):
-    """x = (u, p) with Dirichlet values, lam = adjoint state, f_nodal [3,N]."""
+def grad_viscosity(lv, x, lam, f_nodal, nu, op="laplace"):
+    """x = (u, p) with Dirichlet values, lam = adjoint state, f_nodal [3,N];
+    op selects the velocity form (a_1 or a_2)."""
     from .fem import DELTA
     lu = lam[:3].copy()
     lu[:, lv.dirichlet] = 0.0
     T = lv.tets
     acc = np.zeros(T.shape[0])
+    gus = [np.einsum("ta,tai->ti", x[k][T], lv.G) for k in range(3)]
+    gls = [np.einsum("ta,tai->ti", lu[k][T], lv.G) for k in range(3)]
     for k in range(3):
-        gu = np.einsum("ta,tai->ti", x[k][T], lv.G)
-        gl = np.einsum("ta,tai->ti", lu[k][T], lv.G)
-        acc += lv.vol * np.einsum("ti,ti->t", gu, gl)
+        acc += lv.vol * np.einsum("ti,ti->t", gus[k], gls[k])
+    if op == "D":
+        for k in range(3):
+            for l in range(3):
+                acc += lv.vol * gls[k][:, l] * gus[l][:, k]
     glp = np.einsum("ta,tai->ti", lam[3][T], lv.G)
     gp = np.einsum("ta,tai->ti", x[3][T], lv.G)
     fbar = np.stack([f_nodal[k][T].mean(axis=1) for k in range(3)], axis=1)   # int_T f_h / |T|

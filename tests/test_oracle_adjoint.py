@@ -10,10 +10,10 @@ from oracle.adjoint import adjoint_rhs, grad_forcing, grad_viscosity, loss
 from oracle.umg import direct_solve
 
 
-def _forward(cfg, nu, f, R):
+def _forward(cfg, nu, f, R, op="laplace"):
     """Finest level only (R0 = R) and a sparse direct solve."""
     xyz, tet, _, tags = cfg.mesh()
-    H = build_hierarchy(xyz, tet, nu, tags, R, R0=R)
+    H = build_hierarchy(xyz, tet, nu, tags, R, R0=R, op=op)
     lv = H.finest
     x0 = np.zeros((4, lv.N))
     x0[:3] = cfg.dirichlet_field()
@@ -26,22 +26,22 @@ def _forward(cfg, nu, f, R):
     return H, direct_solve(lv, b, H.project, xbc=x0)
 
 
-@pytest.mark.parametrize("cfg_id", [4, 5])
-def test_gradients_match_finite_differences(cfg_id):
+@pytest.mark.parametrize("cfg_id,op", [(4, "laplace"), (5, "laplace"), (4, "D"), (5, "D")])
+def test_gradients_match_finite_differences(cfg_id, op):
     R = 3
     cfg = W.WORKLOADS[cfg_id].with_R(R)
     _, tet, nu, _ = cfg.mesh()
     f = cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 11, 0.3)
-    H, x = _forward(cfg, nu, f, R)
+    H, x = _forward(cfg, nu, f, R, op)
     lv = H.finest
-    _, xo = _forward(cfg, cfg.observation_viscosity(), f, R)
+    _, xo = _forward(cfg, cfg.observation_viscosity(), f, R, op)
     u_obs = xo[:3]
     lam = direct_solve(lv, adjoint_rhs(lv, x[:3], u_obs), H.project)
     gf = grad_forcing(lv, lam)
-    gnu = grad_viscosity(lv, x, lam, f, nu)
+    gnu = grad_viscosity(lv, x, lam, f, nu, op)
 
     def J(nu_, f_):
-        _, xx = _forward(cfg, nu_, f_, R)
+        _, xx = _forward(cfg, nu_, f_, R, op)
         return loss(xx[:3], u_obs)
 
     rng = np.random.default_rng(9)
