@@ -113,8 +113,8 @@ typedef struct {
                              components: the velocity sweeps become point-block Gauss-Seidel
                              (3x3 centre block solved exactly, same colours and order), also
                              in the velocity multigrid of hhg_vel_cycle, hhg_pminres and
-                             hhg_scg.  The D form needs coarse_solver = 0; hhg_grad returns
-                             HHG_EINVAL for it */
+                             hhg_scg, and the viscosity gradient of hhg_grad takes the
+                             coupled form.  The D form needs coarse_solver = 0 */
 } hhg_opts;
 
 /* Result of hhg_solve. */

@@ -1501,15 +1501,13 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
 hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, double* dnu,
                     void* df, hhg_stream stream) {
     CHECK_DEV(c);
-    if (c->opts.op != 0)
-        return fail(c, HHG_EINVAL, "available for the Laplace form only (op = 0)");
     CHECK_PTR(c, x);
     CHECK_PTR(c, lam);
     CHECK_PTR(c, dnu);
     hipStream_t s = (hipStream_t)stream;
     LevelDev<double>& v = c->D64[c->L];
     hipLaunchKernelGGL(k_grad_nu, dim3(v.n_ctiles), dim3(TPB), 0, s, v, (const double*)x,
-                       (const double*)lam, (const double*)f, c->gpart);
+                       (const double*)lam, (const double*)f, c->gpart, c->opts.op == 1 ? 1 : 0);
     hipLaunchKernelGGL(k_grad_reduce, dim3(v.nm), dim3(TPB), 0, s, c->A[c->L].ctile_macro0,
                        c->gpart, dnu);
     if (df) {

@@ -44,7 +44,8 @@ constexpr int ST_SIZE = 376;
 constexpr int GR_A = 0;
 constexpr int GR_C = 15;
 constexpr int GR_G = 30;
-constexpr int GR_SIZE = 75;
+constexpr int GR_A2 = 75;      // D form: the 9 coupled blocks of a_2 (block (k, l) at 15 (3 k + l))
+constexpr int GR_SIZE = 210;
 
 // Local offsets (di, dj, dk) of the 14 neighbours in macro index space, where
 // a vertex (i, j, k) of a macro with origin O and Kuhn path axes (a, b, c) is

@@ -134,15 +134,15 @@ void add_element(double* rec, const Incident& t, double h, double nuA, double nu
         double gg = G[a][0] * G[b][0] + G[a][1] * G[b][1] + G[a][2] * G[b][2];
         rec[ST_A + g] += nuA * vol * gg;
         rec[ST_C + g] += wC * vol * gg;
+        for (int k = 0; k < 3; ++k)
+            for (int l = 0; l < 3; ++l)
+                rec[ST_A2 + 15 * (3 * k + l) + g] +=
+                    nuA * vol * ((k == l ? gg : 0.0) + G[a][l] * G[b][k]);
         if (!full) {
             for (int k = 0; k < 3; ++k) rec[ST_G + 15 * k + g] += -wC * (vol / 4.0) * G[a][k];
             continue;
         }
         rec[ST_M + g] += vol / 20.0 * (a == b ? 2.0 : 1.0);
-        for (int k = 0; k < 3; ++k)
-            for (int l = 0; l < 3; ++l)
-                rec[ST_A2 + 15 * (3 * k + l) + g] +=
-                    nuA * vol * ((k == l ? gg : 0.0) + G[a][l] * G[b][k]);
         for (int k = 0; k < 3; ++k) {
             rec[ST_B + 15 * k + g] += -(vol / 4.0) * G[b][k];
             rec[ST_BT + 15 * k + g] += -(vol / 4.0) * G[a][k];
@@ -727,6 +727,7 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
             to_local(M, &g[ST_A], o + GR_A, 1);
             to_local(M, &g[ST_C], o + GR_C, 1);
             to_local(M, &g[ST_G], o + GR_G, 3);
+            to_local(M, &g[ST_A2], o + GR_A2, 9);
         }
     }
     return true;

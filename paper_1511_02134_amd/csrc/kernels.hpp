@@ -1048,9 +1048,11 @@ __device__ constexpr int LOFFD[15][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {-1
                                          {0, 1, 0},  {0, -1, 0}, {0, -1, 1}, {0, 1, -1}, {-1, 0, 1},
                                          {1, 0, -1}, {0, 0, 1},  {0, 0, -1}, {1, -1, 1}, {-1, 1, -1}};
 
+// dform: the velocity part from the coupled one-sided blocks of a_2.
 __global__ void __launch_bounds__(TPB) k_grad_nu(LevelDev<double> L, const double* __restrict__ x,
                                                  const double* __restrict__ lam,
-                                                 const double* __restrict__ f, double* partials) {
+                                                 const double* __restrict__ f, double* partials,
+                                                 int dform) {
     __shared__ double sh[4];
     const size_t len = (size_t)L.len;
     double acc = 0.0;
@@ -1075,13 +1077,25 @@ __global__ void __launch_bounds__(TPB) k_grad_nu(LevelDev<double> L, const doubl
                     s[g] = slot_checked(L.slab_base, n, mb, i + LOFFD[g][0], j + LOFFD[g][1],
                                         k + LOFFD[g][2]);
                 double v = 0.0;
+                if (dform) {
+                    for (int c = 0; c < 3; ++c) {
+                        double au = 0.0;
+                        for (int l = 0; l < 3; ++l)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    double au = 0.0;
+                            for (int g = 0; g < 15; ++g)
+                                if (s[g] >= 0)
+                                    au += gs[GR_A2 + 15 * (3 * c + l) + g] * x[l * len + s[g]];
+                        v += lam[c * len + s[0]] * au;
+                    }
+                } else {
 #pragma unroll
-                    for (int g = 0; g < 15; ++g)
-                        if (s[g] >= 0) au += gs[GR_A + g] * x[c * len + s[g]];
-                    v += lam[c * len + s[0]] * au;
+                    for (int c = 0; c < 3; ++c) {
+                        double au = 0.0;
+#pragma unroll
+                        for (int g = 0; g < 15; ++g)
+                            if (s[g] >= 0) au += gs[GR_A + g] * x[c * len + s[g]];
+                        v += lam[c * len + s[0]] * au;
+                    }
                 }
                 double cp = 0.0;
 #pragma unroll

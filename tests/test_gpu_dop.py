@@ -135,13 +135,9 @@ def test_mixed_precision_solve_meets_tolerance_in_fp64_operator():
     assert r <= 1.0e-8 * r0 * (1 + 1e-6)
 
 
-def test_d_form_rejects_unsupported_calls():
+def test_d_form_rejects_unsupported_options():
     import paper_1511_02134_amd as P
-    cfg, s, umg = _setup(1, 3, krylov=1)
-    x, b = s.vector(), s.vector()
-    with pytest.raises(P.HHGError) as e:
-        s.grad(x, b)
-    assert e.value.status == P.HHG_EINVAL
+    cfg = W.WORKLOADS[1].with_R(3)
     xyz, tet, nu, tags = cfg.mesh()
     with pytest.raises(P.HHGError):
         P.Solver(xyz, tet, nu, tags, 3, op=1, coarse_solver=1)

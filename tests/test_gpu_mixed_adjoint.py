@@ -51,20 +51,21 @@ def test_mixed_precision_solve_reaches_fp64_tolerance(cid, R):
     assert info["cycles"] <= len(hist) - 1 + 3
 
 
-def _problem(cid, R, rtol, precision=0):
+def _problem(cid, R, rtol, precision=0, op="laplace"):
     import paper_1511_02134_amd as P
     from paper_1511_02134_amd.autograd import StokesProblem
     cfg = W.WORKLOADS[cid].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    s = P.Solver(xyz, tet, nu, tags, R, precision=precision)
+    s = P.Solver(xyz, tet, nu, tags, R, precision=precision, op=1 if op == "D" else 0)
     return cfg, nu, StokesProblem(s, cfg.dirichlet_field(), rtol=rtol, max_cycles=100)
 
 
-@pytest.mark.parametrize("cid,R", [(4, 3), (5, 3), (4, 4)])
-def test_adjoint_gradient_matches_oracle(cid, R):
+@pytest.mark.parametrize("cid,R,op", [(4, 3, "laplace"), (5, 3, "laplace"), (4, 4, "laplace"),
+                                     (4, 3, "D"), (5, 3, "D")])
+def test_adjoint_gradient_matches_oracle(cid, R, op):
     from paper_1511_02134_amd.autograd import StokesSolve
-    _announce(f"adjoint config {cid} R={R}")
-    cfg, nu, prob = _problem(cid, R, rtol=1e-12)
+    _announce(f"adjoint config {cid} R={R} form={op}")
+    cfg, nu, prob = _problem(cid, R, rtol=1e-12, op=op)
     f = cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 11, 0.3)
     nu_obs = cfg.observation_viscosity()
     ft = _dev(f)
@@ -77,7 +78,7 @@ def test_adjoint_gradient_matches_oracle(cid, R):
     J.backward()
     # oracle: direct solves on the same inputs
     xyz, tet, _, tags = cfg.mesh()
-    Ho = build_hierarchy(xyz, tet, nu, tags, R, R0=R)
+    Ho = build_hierarchy(xyz, tet, nu, tags, R, R0=R, op=op)
     lv = Ho.finest
     b = np.zeros((4, lv.N))
     for k in range(3):
@@ -88,7 +89,7 @@ def test_adjoint_gradient_matches_oracle(cid, R):
     x0[:3] = cfg.dirichlet_field()
     x0[:3, lv.free] = 0.0
     x = direct_solve(lv, b, Ho.project, xbc=x0)
-    Hobs = build_hierarchy(xyz, tet, nu_obs, tags, R, R0=R)
+    Hobs = build_hierarchy(xyz, tet, nu_obs, tags, R, R0=R, op=op)
     bo = b.copy()
     lvo = Hobs.finest
     for k in range(3):
@@ -98,7 +99,7 @@ def test_adjoint_gradient_matches_oracle(cid, R):
     uo = direct_solve(lvo, bo, Hobs.project, xbc=x0)[:3]
     lam = direct_solve(lv, adjoint_rhs(lv, x[:3], uo), Ho.project)
     gf = grad_forcing(lv, lam)
-    gnu = grad_viscosity(lv, x, lam, f, nu)
+    gnu = grad_viscosity(lv, x, lam, f, nu, op)
     assert J.item() == pytest.approx(loss(x[:3], uo), rel=1e-8)
     gf_gpu = ft.grad.cpu().numpy()
     gnu_gpu = nut.grad.cpu().numpy()
@@ -106,17 +107,19 @@ def test_adjoint_gradient_matches_oracle(cid, R):
     assert np.abs(gnu_gpu - gnu).max() <= 1e-8 * np.abs(gnu).max()
 
 
-@pytest.mark.parametrize("cid,R,precision", [(4, 4, 0), (5, 4, 1), (4, 6, 0), (5, 7, 1)])
-def test_adjoint_gradient_matches_finite_differences(cid, R, precision):
+@pytest.mark.parametrize("cid,R,precision,op", [(4, 4, 0, "laplace"), (5, 4, 1, "laplace"),
+                                                (4, 6, 0, "laplace"), (5, 7, 1, "laplace"),
+                                                (4, 4, 0, "D")])
+def test_adjoint_gradient_matches_finite_differences(cid, R, precision, op):
     """Central differences with eps = 1e-6 per macro viscosity, forward solves
     driven to rtol 1e-13 (1e-12 with FP32 cycles); gradients within 1e-6.
     The last two cases are the full box (R = 6, FP64) and the full channel
     (R = 7, FP32 cycles in FP64 refinement) in the solver's default launch
     configuration."""
     from paper_1511_02134_amd.autograd import StokesSolve
-    _announce(f"finite differences config {cid} R={R} precision={precision}")
+    _announce(f"finite differences config {cid} R={R} precision={precision} form={op}")
     rtol = 1e-13 if precision == 0 else 1e-12
-    cfg, nu, prob = _problem(cid, R, rtol=rtol, precision=precision)
+    cfg, nu, prob = _problem(cid, R, rtol=rtol, precision=precision, op=op)
     f = _dev(cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 12, 0.3))
     with torch.no_grad():
         u_obs, _ = StokesSolve.apply(f, _dev(cfg.observation_viscosity()), prob)
