@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--fp64", action="store_true",
+                    help="run a mixed-precision workload in FP64 throughout (comparison run)")
     ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
                     help="velocity form: Laplace (a_1, default) or D (a_2 = 2<nu D(u), D(v)>)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -298,7 +300,7 @@ def main():
 
     cfg = W.WORKLOADS[args.workload]
     xyz, tet, nu, tags = cfg.mesh()
-    precision = 1 if cfg.precision == "mixed" else 0
+    precision = 1 if cfg.precision == "mixed" and not args.fp64 else 0
     dform = args.op == "D"
     s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0)
     dofs = s.num_dofs()
