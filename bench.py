@@ -233,6 +233,7 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     b = s.vector()
     x = torch.empty_like(x0)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    print(f"[bench] comparison set up: R={R}, {s.num_dofs()} DoFs", file=sys.stderr, flush=True)
     runs = {"UMG": lambda: s.solve(x, b, rtol=1e-8, max_cycles=100),
             "PMINRES": lambda: s.pminres(x, b, rtol=1e-8, maxit=2000, nu=1),
             "SCG": lambda: s.scg(x, b, rtol=1e-8, max_outer=255, n_A=3, n_S=3, n_I=1, nu=3)}
@@ -248,6 +249,7 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
             torch.cuda.synchronize()
             if k >= warmup:
                 t.append(ev[0].elapsed_time(ev[1]))
+        print(f"[bench] {name} done", file=sys.stderr, flush=True)
         out[name] = {"iterations": info["cycles"], "status": info["status"],
                      "rel_res": info["rel_res"], "ms": float(np.median(t)),
                      "n_op": {k: round(v, 2) for k, v in info["n_op"].items()}}
@@ -265,6 +267,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--R", type=int, default=0,
+                    help="refinements of the workload's mesh (default: the workload's own)")
     ap.add_argument("--fp64", action="store_true",
                     help="run a mixed-precision workload in FP64 throughout (comparison run)")
     ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
@@ -299,13 +303,17 @@ def main():
     import paper_1511_02134_amd as P
 
     cfg = W.WORKLOADS[args.workload]
+    if args.R:
+        cfg = cfg.with_R(args.R)
     xyz, tet, nu, tags = cfg.mesh()
     precision = 1 if cfg.precision == "mixed" and not args.fp64 else 0
     dform = args.op == "D"
     s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0)
     dofs = s.num_dofs()
+    print(f"[bench] solver ready: {cfg.name}, R={cfg.R}, {dofs} DoFs", file=sys.stderr, flush=True)
     dev = torch.device("cuda")
     f = torch.tensor(cfg.forcing_field(), dtype=torch.float64, device=dev)
+    print("[bench] inputs on the device", file=sys.stderr, flush=True)
     x0n = torch.zeros(4, s.num_nodes(), dtype=torch.float64, device=dev)
     x0n[:3] = torch.tensor(cfg.dirichlet_field(), device=dev)
     _, dmask = s.node_info()
@@ -323,6 +331,7 @@ def main():
     for _ in range(args.warmup):
         info = step()
     torch.cuda.synchronize()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         info = step()
@@ -356,7 +365,8 @@ def main():
     napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
     s.set_timing(False)
     vel_avg_ms = ms_vel / max(nvel, 1)
-    traffic = measured_traffic() if args.workload == 2 and precision == 0 and not dform else None
+    traffic = (measured_traffic() if args.workload == 2 and not args.R and precision == 0 and not dform
+               else None)
     achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
 
     # practical ceiling: device copies moving the sweep's algorithmic bytes per
