@@ -11,7 +11,8 @@ Printed as one JSON line with, besides the contract fields:
                paper's work unit, Section 5), both measured here;
   roofline     the velocity colour sweep (the dominant kernel) against the
                8 TB/s HBM peak, algorithmic bytes per launch / measured mean
-               launch time (hipEvents around every launch on its stream);
+               launch time (hipEvents on its stream, one pair around the six
+               back-to-back sweeps of each smoothing step);
   cpu_baseline the FP64 oracle (numpy/scipy) solving the same problem at a
                bounded size on the host cores, setup excluded.
 
@@ -355,7 +356,8 @@ def main():
     t_apply = float(np.median(times[5:]))
 
     # roofline of the dominant kernel: every finest-level velocity colour sweep
-    # of the same steps, bracketed by hipEvents on the solver's stream
+    # of the same steps, timed by hipEvents on the solver's stream (one pair
+    # around the consecutive sweeps of each smoothing step)
     s.set_timing(True)
     for _ in range(min(args.steps, 3)):
         step()
@@ -370,8 +372,8 @@ def main():
     achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
 
     # practical ceiling: device copies moving the sweep's algorithmic bytes per
-    # launch (half read, half written), timed like the sweeps: back-to-back
-    # launches on a busy stream, each bracketed by its own pair of hipEvents
+    # launch (half read, half written), timed like the sweeps: groups of six
+    # back-to-back launches, each group bracketed by one pair of hipEvents
     per_launch = bytes_vel / max(nvel, 1)
     src = torch.empty(int(per_launch // 16), dtype=torch.float64, device=dev).normal_()
     dst = torch.empty_like(src)
@@ -381,10 +383,11 @@ def main():
         dst.copy_(src)
     for a, b_ in pairs:
         a.record()
-        dst.copy_(src)
+        for _ in range(6):
+            dst.copy_(src)
         b_.record()
     torch.cuda.synchronize()
-    ctime = float(np.mean([a.elapsed_time(b_) for a, b_ in pairs]))
+    ctime = float(np.mean([a.elapsed_time(b_) for a, b_ in pairs])) / 6
     copy_gbs = 2 * src.numel() * 8 / (ctime * 1e-3) / 1e9
     del src, dst
 

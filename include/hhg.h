@@ -313,10 +313,12 @@ hhg_status hhg_grad(hhg_ctx* ctx, const void* d_x, const void* d_lambda, const v
  * stencil table; synchronises the device. */
 hhg_status hhg_set_viscosity(hhg_ctx* ctx, const double* nu);
 
-/* Per-kernel-class timing.  When enabled, every launch of the classes below
- * on the finest level is bracketed by hipEvents on its stream; hhg_kernel_time
- * synchronises and returns the number of timed launches, their summed
- * duration in ms and the algorithmic bytes they moved. */
+/* Per-kernel-class timing.  When enabled, the launches of the classes below
+ * on the finest level are bracketed by hipEvents on their stream: the
+ * velocity colour sweeps of one smoothing step, which run back to back, by
+ * one pair around all of them; every other launch by a pair of its own.
+ * hhg_kernel_time synchronises and returns the number of timed launches,
+ * their summed duration in ms and the algorithmic bytes they moved. */
 enum {
     HHG_K_VEL = 0,     /* velocity colour sweep, finest level */
     HHG_K_PRES = 1,    /* pressure colour sweep, finest level */

@@ -122,6 +122,43 @@ def test_uzawa_step_matches_oracle(cid, R):
         assert _relerr(_host(s.gather(xd, l)), xo) < 1e-12, l
 
 
+@pytest.mark.parametrize("cid", [1, 4])
+def test_large_level_passes_match_oracle(cid):
+    """64 intervals per macro edge, where K x and the residual run as separate
+    volume and interface launches and the B^T p and B u passes (with their
+    colour-0 sweeps) read quad windows: K x, the residual and Uzawa steps
+    against the oracle on the whole level, and two steps on the next coarser
+    level (32 intervals)."""
+    cfg, s, umg = _setup(cid, 6)
+    lv = umg.H.finest
+    x = _rand_state(lv, 81, None)
+    x[:3, lv.dirichlet] = np.random.default_rng(82).normal(size=(3, lv.N))[:, lv.dirichlet]
+    y = _host(s.gather(s.apply(s.scatter(_dev(x), umg.L), umg.L), umg.L))
+    err = _relerr(y, umg.apply(umg.L, x))
+    _announce(f"K x: max rel. difference {err:.2e}")
+    assert err < 1e-13
+    b = _rand_state(lv, 83)
+    x = _rand_state(lv, 84, cfg.dirichlet_field())
+    r, nrm = s.residual(s.scatter(_dev(x)), s.scatter(_dev(b)))
+    ro = umg.residual(umg.L, x, b)
+    err = _relerr(_host(s.gather(r)), ro)
+    _announce(f"residual: max rel. difference {err:.2e}")
+    assert err < 1e-13
+    assert nrm == pytest.approx(umg.norm(umg.L, ro), rel=1e-13)
+    for l in (umg.L, umg.L - 1):
+        lv = umg.H.levels[l]
+        x = _rand_state(lv, 90 + l, cfg.dirichlet_field() if l == umg.L else None)
+        b = _rand_state(lv, 95 + l)
+        xd, bd = s.scatter(_dev(x), l), s.scatter(_dev(b), l)
+        s.smooth(xd, bd, 2, l)
+        xo = x.copy()
+        for _ in range(2):
+            umg.uzawa(l, xo, b)
+        err = _relerr(_host(s.gather(xd, l)), xo)
+        _announce(f"Uzawa steps, level {l}: max rel. difference {err:.2e}")
+        assert err < 1e-12, l
+
+
 @pytest.mark.parametrize("cid,solver,prec", [(1, 0, 1), (4, 0, 1), (5, 0, 1),
                                              (1, 1, 0), (4, 1, 0), (5, 1, 0), (1, 1, 1), (5, 1, 1)])
 def test_coarse_solve_matches_dense(cid, solver, prec):
