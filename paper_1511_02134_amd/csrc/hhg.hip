@@ -39,7 +39,7 @@ struct Carver {
 };
 
 struct DevLevelArrays {
-    int32_t *slab_base, *if_self, *if_nb, *if_sid, *if_cptr, *if_copy, *if_flag, *rif_fine;
+    int32_t *slab_base, *if_self, *if_nb, *if_sid, *if_cptr, *if_copy, *if_flag, *rif_tap;
     Tile *vtiles, *ctiles;
     double *st64, *gst64, *nu64;
     float *st32, *gst32, *nu32;
@@ -220,7 +220,7 @@ size_t layout(hhg_ctx* c, char* ws) {
         a.if_cptr = cv.take<int32_t>(h.if_cptr.size());
         a.if_copy = cv.take<int32_t>(std::max<size_t>(1, h.if_copy.size()));
         a.if_flag = cv.take<int32_t>(std::max(1, h.nif));
-        a.rif_fine = cv.take<int32_t>(std::max(1, h.nif));
+        a.rif_tap = l < c->L ? cv.take<int32_t>((size_t)15 * std::max(1, h.nif)) : nullptr;
         a.st64 = cv.take<double>(h.st.size());
         a.gst64 = cv.take<double>(h.gst.size());
         a.nu64 = cv.take<double>(h.nm);
@@ -317,7 +317,7 @@ void fill_view(hhg_ctx* c, int l, LevelDev<T>& v) {
     v.if_flag = a.if_flag;
     for (int q = 0; q < 5; ++q) v.col_start[q] = h.col_start[q];
     for (int q = 0; q < 4; ++q) v.vel_end[q] = h.vel_end[q];
-    v.rif_fine = a.rif_fine;
+    v.rif_tap = a.rif_tap;
     v.ncomp = h.ncomp;
     v.cstride = mirror_stride(h.ncomp);
     v.if_tap = a.if_tap;
@@ -404,7 +404,7 @@ hhg_status upload_all(hhg_ctx* c) {
         UP(int32_t, a.if_cptr, h.if_cptr);
         UP(int32_t, a.if_copy, h.if_copy);
         UP(int32_t, a.if_flag, h.if_flag);
-        if (!h.rif_fine.empty()) UP(int32_t, a.rif_fine, h.rif_fine);
+        if (!h.rif_tap.empty()) UP(int32_t, a.rif_tap, h.rif_tap);
         UP(int32_t, a.slot_node, h.slot_node);
         UP(int32_t, a.node_slot, h.node_slot);
         UP(int32_t, a.if_tap, h.if_tap);
@@ -802,7 +802,8 @@ constexpr int WIN_MIN_N = 32;
 template <typename T, int MODE>
 void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
-    const int ib = iface_blocks(v.nif);
+    // f - B^T p takes a lane per interface vertex and velocity component
+    const int ib = iface_blocks(MODE == MODE_RU ? 3 * v.nif : v.nif);
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
@@ -822,7 +823,8 @@ template <typename T>
 void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
-    const int ib = iface_blocks(cnt);
+    // the Laplace form's velocity sweep takes a lane per interface vertex and component
+    const int ib = iface_blocks(vel && c->opts.op == 0 ? 3 * cnt : cnt);
     const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);
@@ -898,7 +900,7 @@ template <typename T, int NF = 4>
 void restrict_to(hhg_ctx* c, int l, const T* rf, T* bc, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
-    const int ib = iface_blocks(C.nif);
+    const int ib = iface_blocks(NF * C.nif);   // a lane per interface vertex and field
     const int grid = ib + full_blocks(C.n_vtiles);
     hipLaunchKernelGGL((k_restrict<T, NF>), dim3(grid), dim3(TPB), 0, s, C, F, rf, bc, ib);
 }

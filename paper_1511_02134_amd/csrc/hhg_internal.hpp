@@ -101,8 +101,9 @@ struct LevelDev {
     const T* st;             // stencil records
     const T* gst;            // gradient one-sided stencils [nm][16][GR_SIZE]
     // restriction of coarse interface vertices (this level as the coarse one):
-    // index of the same vertex in the finer level's interface list
-    const int32_t* rif_fine;
+    // [15][nif] fine slots summed at each vertex, the coincident one first
+    // (-1: no neighbour in that direction)
+    const int32_t* rif_tap;
     const T* macro_nu;       // [nm]
     // compact mirror of the smoothed iterate x: interface vertices (list
     // order) then their volume neighbours; field f of entry e is cx[f * cstride + e]

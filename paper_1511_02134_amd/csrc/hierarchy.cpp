@@ -746,6 +746,18 @@ void link_levels(HostLevel* coarse, const HostLevel& fine) {
         auto it = idx.find(lf);
         coarse->rif_fine[t] = it == idx.end() ? -1 : it->second;
     }
+    const int nif = coarse->nif;
+    coarse->rif_tap.assign((size_t)15 * std::max(nif, 1), -1);
+    for (int t = 0; t < nif; ++t) {
+        const int tf = coarse->rif_fine[t];
+        if (tf < 0) continue;
+        const int32_t self = fine.if_self[tf];
+        coarse->rif_tap[t] = self;
+        for (int g = 0; g < 14; ++g) {
+            const int32_t nb = fine.if_nb[(size_t)g * fine.nif + tf];
+            coarse->rif_tap[(size_t)(g + 1) * nif + t] = nb != self ? nb : -1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -56,6 +56,10 @@ struct HostLevel {
     std::vector<int32_t> node_sid;         // [N] stencil id (interface) or -(m+1) (volume of m)
     std::vector<int8_t> node_dir;          // [N] velocity Dirichlet
     std::vector<int32_t> rif_fine;         // [nif] index in the finer level's interface list
+    // [15][nif] fine slots that the restriction sums at each interface vertex:
+    // the coincident vertex, then its 14 neighbours (-1 where the finer
+    // level's neighbour table points back at the vertex: no neighbour)
+    std::vector<int32_t> rif_tap;
     // compact mirror of x: entries 0..nif-1 are the interface vertices (in
     // list order), entries nif.. the volume vertices they couple to (halo)
     int32_t ncomp = 0;

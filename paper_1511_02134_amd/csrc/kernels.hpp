@@ -196,7 +196,8 @@ __device__ __forceinline__ void dform_block(const T* __restrict__ st, const int*
 // DOP: the velocity update of the D form (all 14 neighbours, 3x3 block).
 template <typename T, bool VEL, bool DOP = false>
 __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
-                                             T* __restrict__ x, const T* __restrict__ rhs, T omega) {
+                                             T* __restrict__ x, const T* __restrict__ rhs, T omega,
+                                             int fa = 0, int fb = 3) {
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
     const int self = L.if_self[t];
@@ -222,8 +223,8 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
 #pragma unroll
     for (int g = 0; g < 6; ++g) nb[g] = L.if_tap[g * nif + t];
     if (VEL) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
+        // components fa .. fb-1 (the Laplace form updates each on its own)
+        for (int f = fa; f < fb; ++f) {
             const T* u = cx + f * cs;
             T acc = T(0);
 #pragma unroll
@@ -305,8 +306,18 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         return;
     }
     const int t0 = L.col_start[c];
-    const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
+    if (VEL && !DOP) {
+        // a lane per interface vertex and velocity component: the scattered
+        // loads of a colour's interface vertices spread over three times as
+        // many workgroups (on small levels they are the launch's longest path)
+        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = t0 + q / 3, f = q % 3;
+        if (t >= tend) return;
+        iface_colour<T, VEL, DOP>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f,
+                                  f + 1);
+        return;
+    }
+    const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     if (t >= tend) return;
     iface_colour<T, VEL, DOP>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
 }
@@ -360,7 +371,7 @@ template <typename T, int MODE, bool DOP = false>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
                                           const T* __restrict__ x, size_t xs,
                                           const T* __restrict__ b, size_t bs, int bslot,
-                                          T out[4]) {
+                                          T out[4], int fa = 0, int fb = 3) {
     if (MODE == MODE_ARES && DOP) {
         // D form: every tap of all three components
         T ru[3] = {T(0), T(0), T(0)};
@@ -406,9 +417,9 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
         return;
     }
     if (MODE == MODE_RU) {
+        // components fa .. fb-1
         const T* p = x + 3 * xs;
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
+        for (int f = fa; f < fb; ++f) {
             T acc = T(0);
 #pragma unroll
             for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * p[s[g]];
@@ -587,11 +598,12 @@ __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
 template <typename T, int MODE, bool IFACE>
 __device__ __forceinline__ void fused_update(const T* __restrict__ st, const int* tp, const T* xr,
                                              size_t rs, T* xw, size_t len, const T out[4], T omega,
-                                             int ncopy, const int* copies, T* cx, size_t cs, int cm) {
+                                             int ncopy, const int* copies, T* cx, size_t cs, int cm,
+                                             int fa = 0, int fb = 3) {
     constexpr int q5 = IFACE ? 5 : 7, q6 = IFACE ? 6 : 8;
     if (MODE == MODE_RU) {
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
+        // components fa .. fb-1
+        for (int f = fa; f < fb; ++f) {
             const T* u = xr + f * rs;
             const T v = out[f] - (st[ST_A + 1] * u[tp[1]] + st[ST_A + 2] * u[tp[2]] +
                                   st[ST_A + 3] * u[tp[3]] + st[ST_A + 4] * u[tp[4]] +
@@ -726,7 +738,7 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
 template <typename T, int MODE, bool FUSE, bool MIRROR, bool DOP = false>
 __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                            const T* __restrict__ x, const T* __restrict__ b, T* xw,
-                                           int fcol, T omega, T out[4]) {
+                                           int fcol, T omega, T out[4], int fa = 0, int fb = 3) {
     static_assert(!FUSE || MIRROR, "fused updates keep the mirror current");
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
@@ -737,12 +749,13 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
 #pragma unroll
     for (int g = 1; g < 15; ++g) s[g] = taps[(g - 1) * nif + t];
     const bool dir = (L.if_flag[t] & 1) != 0;
-    eval_node<T, MODE, DOP>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out);
+    eval_node<T, MODE, DOP>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out, fa,
+                            fb);
     if (FUSE && t >= L.col_start[fcol] &&
         t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
         const int c0 = L.if_cptr[t];
         fused_update<T, MODE, true>(st, s, L.cx, cs, xw, len, out, omega, L.if_cptr[t + 1] - c0,
-                                    L.if_copy + c0, L.cx, cs, t);
+                                    L.if_copy + c0, L.cx, cs, t, fa, fb);
     }
 }
 
@@ -878,6 +891,19 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 }
             }
         }
+    } else if (MODE == MODE_RU && FUSE) {
+        // a lane per interface vertex and velocity component (the components
+        // of f - B^T p and of the colour-fcol update are independent): the
+        // scattered loads of the interface vertices spread over three times
+        // as many workgroups
+        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = q / 3, f = q % 3;
+        if (t < L.nif) {
+            const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+            T out[4];
+            iface_full<T, MODE, FUSE, MIRROR, DOP>(L, st, t, x, b, xw, fcol, omega, out, f, f + 1);
+            const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+            for (int q2 = c0; q2 < c1; ++q2) y[f * len + L.if_copy[q2]] = out[f];
+        }
     } else {
         if ((int)blockIdx.x * TPB < L.nif)
             slot = (quad_lanes(MODE) && PART == 0 ? 1 : 4) * L.nv_nat + (int)blockIdx.x;
@@ -935,27 +961,27 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
         }
         return;
     }
-    const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    // interface vertices: one lane per vertex and field, so that the
+    // scattered loads of the few interface vertices of a small level spread
+    // over NF times as many workgroups (and CUs)
+    const int tf = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    const int t = tf / NF, f = tf - t * NF;
     if (t >= C.nif) return;
-    const int tf = C.rif_fine[t];
-    const int nif = F.nif;
-    const int self = F.if_self[tf];
+    const int nif = C.nif;
+    const int self = C.rif_tap[t];
     int nb[14];
 #pragma unroll
-    for (int g = 0; g < 14; ++g) nb[g] = F.if_nb[g * nif + tf];
+    for (int g = 0; g < 14; ++g) nb[g] = C.rif_tap[(g + 1) * nif + t];
     const bool dir = (C.if_flag[t] & 1) != 0;
     const int c0 = C.if_cptr[t], c1 = C.if_cptr[t + 1];
+    const T* v = rf + f * lf;
+    T acc = T(0);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const T* v = rf + f * lf;
-        T acc = T(0);
-#pragma unroll
-        for (int g = 0; g < 14; ++g)
-            if (nb[g] != self) acc += v[nb[g]];
-        T val = v[self] + T(0.5) * acc;
-        if (f < 3 && dir) val = T(0);
-        for (int q = c0; q < c1; ++q) bc[f * lc + C.if_copy[q]] = val;
-    }
+    for (int g = 0; g < 14; ++g)
+        if (nb[g] >= 0) acc += v[nb[g]];
+    T val = v[self] + T(0.5) * acc;
+    if (f < 3 && dir) val = T(0);
+    for (int q = c0; q < c1; ++q) bc[f * lc + C.if_copy[q]] = val;
 }
 
 // ---------------------------------------------------------------------------
