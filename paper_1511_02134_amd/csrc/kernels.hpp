@@ -1176,9 +1176,16 @@ __global__ void k_grad_reduce(const int* __restrict__ macro_tile0, const double*
 __global__ void k_reduce_sum(const double* __restrict__ partials, int n, double* __restrict__ out,
                              int sqrt_out) {
     __shared__ double sh[4];
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < n; b += TPB) acc += partials[b];
-    const double tot = block_sum256(acc, sh);
+    // four running sums per lane (entries b, b + TPB, b + 2 TPB, b + 3 TPB of
+    // each stride of 4 TPB), so that four loads are in flight; fixed order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int b = threadIdx.x; b < n; b += 4 * TPB) {
+        a0 += partials[b];
+        if (b + TPB < n) a1 += partials[b + TPB];
+        if (b + 2 * TPB < n) a2 += partials[b + 2 * TPB];
+        if (b + 3 * TPB < n) a3 += partials[b + 3 * TPB];
+    }
+    const double tot = block_sum256((a0 + a1) + (a2 + a3), sh);
     if (threadIdx.x == 0) out[0] = sqrt_out ? sqrt(tot) : tot;
 }
 
