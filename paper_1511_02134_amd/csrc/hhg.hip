@@ -802,8 +802,9 @@ constexpr int WIN_MIN_N = 32;
 template <typename T, int MODE>
 void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
-    // f - B^T p takes a lane per interface vertex and velocity component
-    const int ib = iface_blocks(MODE == MODE_RU ? 3 * v.nif : v.nif);
+    // f - B^T p takes a lane per interface vertex and velocity component, B u
+    // - g four lanes per interface vertex on levels without quad windows
+    const int ib = iface_blocks(MODE == MODE_RU ? 3 * v.nif : v.n < WIN_MIN_N ? 4 * v.nif : v.nif);
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
@@ -823,8 +824,9 @@ template <typename T>
 void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
     const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
-    // the Laplace form's velocity sweep takes a lane per interface vertex and component
-    const int ib = iface_blocks(vel && c->opts.op == 0 ? 3 * cnt : cnt);
+    // velocity sweeps: a lane per interface vertex and component (Laplace
+    // form), four lanes per interface vertex (D form)
+    const int ib = iface_blocks(!vel ? cnt : c->opts.op == 0 ? 3 * cnt : 4 * cnt);
     const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);

@@ -307,6 +307,41 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
     }
     const int t0 = L.col_start[c];
     const int tend = VEL ? L.vel_end[c] : L.col_start[c + 1];
+    if (VEL && DOP) {
+        // D form: four lanes per interface vertex (groups of four consecutive
+        // lanes, never split across waves).  Lane k < 3 forms row k of the
+        // block residual (the rows of dform_block, in its order), the lanes
+        // exchange the three rows, and lane k applies row k of the inverse
+        // centre block and writes component k.
+        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = t0 + (q >> 2), k = q & 3;
+        const bool act = t < tend && k < 3;
+        const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
+        const int nif = L.nif;
+        const int tt = t < tend ? t : t0;
+        const T* st = L.st + (size_t)L.if_sid[tt] * ST_SIZE;
+        T r = T(0);
+        if (act) {
+            int v[15];
+#pragma unroll
+            for (int g = 1; g < 15; ++g) v[g] = L.if_tap[(g - 1) * nif + tt];
+            r = rhs[k * len + L.if_self[tt]];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const T* ul = L.cx + l * cs;
+#pragma unroll
+                for (int g = 1; g < 15; ++g) r -= st[ST_A2 + 15 * (3 * k + l) + g] * ul[v[g]];
+            }
+        }
+        const int g0 = (int)threadIdx.x & ~3;
+        const T r0 = __shfl(r, g0), r1 = __shfl(r, g0 + 1), r2 = __shfl(r, g0 + 2);
+        if (act) {
+            const T* di = st + ST_DINV;
+            const T val = di[3 * k] * r0 + di[3 * k + 1] * r1 + di[3 * k + 2] * r2;
+            for (int qq = L.if_cptr[tt]; qq < L.if_cptr[tt + 1]; ++qq) x[k * len + L.if_copy[qq]] = val;
+            L.cx[k * cs + tt] = val;
+        }
+        return;
+    }
     if (VEL && !DOP) {
         // a lane per interface vertex and velocity component: the scattered
         // loads of a colour's interface vertices spread over three times as
@@ -903,6 +938,41 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             iface_full<T, MODE, FUSE, MIRROR, DOP>(L, st, t, x, b, xw, fcol, omega, out, f, f + 1);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int q2 = c0; q2 < c1; ++q2) y[f * len + L.if_copy[q2]] = out[f];
+        }
+    } else if (MODE == MODE_BP && FUSE && MIRROR && !WIN) {
+        // small levels: four lanes per interface vertex (groups of four
+        // consecutive lanes, never split across waves): lane k < 3 sums B_k u_k
+        // over the taps, two lane exchanges add the three sums, and lane 3 forms
+        // B u - b_3, writes it and relaxes the pressure of a colour-fcol vertex.
+        // The scattered loads of the few interface vertices spread over four
+        // times as many lanes and workgroups.  (With quad windows the launch
+        // carries the windows' register budget, and one lane per vertex is
+        // faster.)
+        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = q >> 2, k = q & 3;
+        const bool act = t < L.nif;
+        const size_t cs = (size_t)L.cstride;
+        const int tt = act ? t : 0;
+        const T* st = L.st + (size_t)L.if_sid[tt] * ST_SIZE;
+        int sl[15];
+        sl[0] = tt;
+#pragma unroll
+        for (int g = 1; g < 15; ++g) sl[g] = L.if_tap[(g - 1) * L.nif + tt];
+        T part = T(0);
+        if (act && k < 3) {
+            const T* u = L.cx + k * cs;
+#pragma unroll
+            for (int g = 0; g < 15; ++g) part += st[ST_B + 15 * k + g] * u[sl[g]];
+        }
+        part += __shfl_xor(part, 1);
+        part += __shfl_xor(part, 2);
+        if (act && k == 3) {
+            T out[4];
+            out[3] = part - b[3 * len + L.if_self[t]];
+            const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+            for (int qq = c0; qq < c1; ++qq) y[3 * len + L.if_copy[qq]] = out[3];
+            if (t >= L.col_start[fcol] && t < L.col_start[fcol + 1])
+                fused_update<T, MODE, true>(st, sl, L.cx, cs, xw, len, out, omega, c1 - c0,
+                                            L.if_copy + c0, L.cx, cs, t);
         }
     } else {
         if ((int)blockIdx.x * TPB < L.nif)
