@@ -193,8 +193,8 @@ __device__ __forceinline__ void dform_block(const T* __restrict__ st, const int*
 // One interface vertex t of a colour sweep: its neighbours come from the
 // mirror (unit-stride runs), the new value goes to every macro copy of the
 // vertex (the ghost exchange fused into the update) and to the mirror.
-// DOP: the velocity update of the D form (all 14 neighbours, 3x3 block).
-template <typename T, bool VEL, bool DOP = false>
+// (The D form's interface sweep runs in k_colour, four lanes per vertex.)
+template <typename T, bool VEL>
 __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                              T* __restrict__ x, const T* __restrict__ rhs, T omega,
                                              int fa = 0, int fb = 3) {
@@ -203,22 +203,6 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
     const int self = L.if_self[t];
     T* cx = L.cx;
     const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
-    if (VEL && DOP) {
-        int v[15];
-        v[0] = t;
-#pragma unroll
-        for (int g = 1; g < 15; ++g) v[g] = L.if_tap[(g - 1) * nif + t];
-        T res[3];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) res[f] = rhs[f * len + self];
-        dform_block<T>(st, v, cx, cs, res);
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            for (int q = c0; q < c1; ++q) x[f * len + L.if_copy[q]] = res[f];
-            cx[f * cs + t] = res[f];
-        }
-        return;
-    }
     int nb[6];
 #pragma unroll
     for (int g = 0; g < 6; ++g) nb[g] = L.if_tap[g * nif + t];
@@ -348,13 +332,12 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         // many workgroups (on small levels they are the launch's longest path)
         const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = t0 + q / 3, f = q % 3;
         if (t >= tend) return;
-        iface_colour<T, VEL, DOP>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f,
-                                  f + 1);
+        iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f, f + 1);
         return;
     }
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     if (t >= tend) return;
-    iface_colour<T, VEL, DOP>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
+    iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,8 +697,7 @@ __device__ __forceinline__ void quad_window_load(const T* __restrict__ f, const 
     typedef T tpair __attribute__((ext_vector_type(2), aligned(sizeof(T))));
 #pragma unroll
     for (int rho = 0; rho < 7; ++rho) {
-        constexpr int cnt6 = 6, cnt5 = 5;
-        const int cnt = rho == 0 ? cnt6 : cnt5;
+        const int cnt = rho == 0 ? 6 : 5;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const uint32_t off = (uint32_t)w[rho][e] * (uint32_t)sizeof(T);
