@@ -71,8 +71,8 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(workload_id: int, R: int, timeout: float = 600.0):
-    """Times the oracle's solve in a single-threaded child process."""
+def cpu_baseline(workload_id: int, R: int, cycle: int, timeout: float = 600.0):
+    """Times the oracle's solve (setup excluded) in a child process."""
     code = f"""
 import json, time, sys
 sys.path.insert(0, {ROOT!r})
@@ -82,7 +82,7 @@ from oracle import build_hierarchy, UMG
 cfg = W.WORKLOADS[{workload_id}].with_R({R})
 xyz, tet, nu, tags = cfg.mesh()
 H = build_hierarchy(xyz, tet, nu, tags, {R})
-umg = UMG(H)
+umg = UMG(H, variable={bool(cycle)})
 lv = H.finest
 f = cfg.forcing_field()
 t0 = time.perf_counter()
@@ -92,11 +92,8 @@ x, hist = umg.solve(x0, b, rtol=1e-8, max_cycles=100)
 t = time.perf_counter() - t0
 print(json.dumps({{"seconds": t, "dofs": lv.ndofs(), "cycles": len(hist) - 1}}))
 """
-    env = dict(os.environ)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        env[k] = "1"
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
-                         timeout=timeout, env=env)
+                         timeout=timeout)
     if out.returncode != 0:
         raise RuntimeError(out.stderr[-2000:])
     return json.loads(out.stdout.strip().splitlines()[-1])
@@ -262,18 +259,59 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     print(json.dumps(line), flush=True)
 
 
+def host_cpu():
+    """(nproc, CPU model name) of the host."""
+    model = "unknown"
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return os.cpu_count() or 0, model
+
+
+def timed_solves(s, f_int, x0, x, steps, warmup):
+    """`warmup` then `steps` complete solves (right-hand side, every cycle,
+    the per-cycle stopping test); returns (ms per solve, info of the last)."""
+    import torch
+
+    def step():
+        b = s.rhs(f_int)
+        x.copy_(x0)
+        return s.solve(x, b, rtol=1e-8, max_cycles=100)
+
+    info = None
+    for _ in range(warmup):
+        info = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = step()
+    torch.cuda.synchronize()
+    return 1000.0 * (time.perf_counter() - t0) / steps, info, step
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--R", type=int, default=0,
                     help="refinements of the workload's mesh (default: the workload's own)")
-    ap.add_argument("--fp64", action="store_true",
-                    help="run a mixed-precision workload in FP64 throughout (comparison run)")
+    ap.add_argument("--precision", choices=("fp64", "mixed", "workload"), default="fp64",
+                    help="precision of the timed solve (default FP64, the paper's; 'workload': "
+                         "the workload's own)")
+    ap.add_argument("--cycle", choices=("V", "Vvar", "workload"), default="workload",
+                    help="V(3,3) or the variable V(3,3) (default: Vvar on the unit cube at 8 "
+                         "refinements and the channel, V otherwise)")
     ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
                     help="velocity form: Laplace (a_1, default) or D (a_2 = 2<nu D(u), D(v)>)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-precision solve reported beside the FP64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-R", type=int, default=6,
                     help="refinements of the oracle's bounded sample")
@@ -307,15 +345,24 @@ def main():
     if args.R:
         cfg = cfg.with_R(args.R)
     xyz, tet, nu, tags = cfg.mesh()
-    precision = 1 if cfg.precision == "mixed" and not args.fp64 else 0
+    if args.precision == "workload":
+        precision = 1 if cfg.precision == "mixed" else 0
+    else:
+        precision = 1 if args.precision == "mixed" else 0
+    if args.cycle == "workload":
+        cycle = 1 if args.workload in (3, 5) else 0
+    else:
+        cycle = 1 if args.cycle == "Vvar" else 0
     dform = args.op == "D"
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0)
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0,
+                 cycle=cycle)
     dofs = s.num_dofs()
-    print(f"[bench] solver ready: {cfg.name}, R={cfg.R}, {dofs} DoFs", file=sys.stderr, flush=True)
+    nvert = s.num_nodes()
+    name = cfg.name.rsplit("-", 1)[0] + ("-fp64" if precision == 0 else "-mixed")
+    print(f"[bench] solver ready: {name}, R={cfg.R}, {dofs} DoFs", file=sys.stderr, flush=True)
     dev = torch.device("cuda")
     f = torch.tensor(cfg.forcing_field(), dtype=torch.float64, device=dev)
-    print("[bench] inputs on the device", file=sys.stderr, flush=True)
-    x0n = torch.zeros(4, s.num_nodes(), dtype=torch.float64, device=dev)
+    x0n = torch.zeros(4, nvert, dtype=torch.float64, device=dev)
     x0n[:3] = torch.tensor(cfg.dirichlet_field(), device=dev)
     _, dmask = s.node_info()
     x0n[:3, ~torch.tensor(dmask, device=dev)] = 0.0
@@ -323,27 +370,17 @@ def main():
     x0 = s.scatter(x0n)
     x = torch.empty_like(x0)
     torch.cuda.synchronize()
+    print("[bench] inputs on the device", file=sys.stderr, flush=True)
 
-    def step():
-        b = s.rhs(f_int)
-        x.copy_(x0)
-        return s.solve(x, b, rtol=1e-8, max_cycles=100)
-
-    for _ in range(args.warmup):
-        info = step()
-    torch.cuda.synchronize()
-    print("[bench] warm-up done", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
+    ms_per_step, info, step = timed_solves(s, f_int, x0, x, args.steps, args.warmup)
     if info["status"] != 0:
         print(f"solve did not converge: {info}", file=sys.stderr)
         sys.exit(1)
+    print(f"[bench] timed solves done: {ms_per_step:.2f} ms, {info['cycles']} cycles",
+          file=sys.stderr, flush=True)
 
-    # work unit: one K apply on the finest level, FP64
+    # work unit: one K apply on the finest level in the solve's precision of
+    # the finest sweeps (FP64 here)
     y = torch.empty_like(x)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     times = []
@@ -354,6 +391,12 @@ def main():
         torch.cuda.synchronize()
         times.append(ev[0].elapsed_time(ev[1]))
     t_apply = float(np.median(times[5:]))
+
+    # phase split of one solve (hipEvent pairs around every phase)
+    s.set_phase_timing(True)
+    pinfo = step()
+    s.set_phase_timing(False)
+    torch.cuda.synchronize()
 
     # roofline of the dominant kernel: every finest-level velocity colour sweep
     # of the same steps, timed by hipEvents on the solver's stream (one pair
@@ -367,15 +410,19 @@ def main():
     napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
     s.set_timing(False)
     vel_avg_ms = ms_vel / max(nvel, 1)
-    traffic = (measured_traffic() if args.workload == 2 and not args.R and precision == 0 and not dform
-               else None)
-    achieved = (bytes_vel / max(nvel, 1)) / (vel_avg_ms * 1e-3) / 1e9
+    vs = 8.0 if precision == 0 else 4.0
+    # algorithmic bytes of one colour launch: one direction of the velocity
+    # Gauss-Seidel reads u (3 values), f (3) and p and writes u (3) per finest
+    # vertex, 10 values; its four colour launches share them
+    alg_bytes = 10.0 * vs * nvert / 4.0
+    achieved = alg_bytes / (vel_avg_ms * 1e-3) / 1e9
+    traffic = (measured_traffic() if args.workload == 3 and not args.R and precision == 0
+               and not dform else None)
 
-    # practical ceiling: device copies moving the sweep's algorithmic bytes per
-    # launch (half read, half written), timed like the sweeps: groups of six
-    # back-to-back launches, each group bracketed by one pair of hipEvents
-    per_launch = bytes_vel / max(nvel, 1)
-    src = torch.empty(int(per_launch // 16), dtype=torch.float64, device=dev).normal_()
+    # practical ceiling: device copies moving the same bytes (half read, half
+    # written), timed like the sweeps: groups of six back-to-back launches,
+    # each group bracketed by one pair of hipEvents
+    src = torch.empty(int(alg_bytes // 16), dtype=torch.float64, device=dev).normal_()
     dst = torch.empty_like(src)
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
              for _ in range(40)]
@@ -405,11 +452,12 @@ def main():
         "dtype": "f64" if precision == 0 else "f32-in-f64",
         "data": "synthetic",
         "config": {
-            "workload": cfg.name,
+            "workload": name,
             "mesh": f"box [0,{cfg.a}]x[0,1]^2, {tet.shape[0]} Kuhn macro tetrahedra",
             "refinements": cfg.R,
             "dofs": dofs,
-            "cycle": "V(3,3)",
+            "vertices": nvert,
+            "cycle": "Vvar(3,3)" if cycle else "V(3,3)",
             "form": "D (a_2)" if dform else "Laplace (a_1)",
             "rtol": 1e-8,
             "cycles": info["cycles"],
@@ -419,42 +467,56 @@ def main():
         },
         "tme_factor": ms_per_step / t_apply,
         "t_apply_ms": t_apply,
+        "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
         "roofline": {
             "bound": "hbm",
             "kernel": (f"k_colour<{'double' if precision == 0 else 'float'},velocity"
-                       f"{',D' if dform else ''}> "
-                       f"(finest level)"),
+                       f"{',D' if dform else ''}> (finest level)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "bytes_model": ("10 values per finest vertex per sweep direction (read u, f, p; "
+                            "write u), a quarter per colour launch"),
+            "bytes_per_launch": alg_bytes,
             "launches": nvel,
             "avg_us": 1000.0 * vel_avg_ms,
-            "bytes_per_launch": bytes_vel / max(nvel, 1),
-            "copy_probe": {"GB/s": copy_gbs, "bytes": 2 * int(per_launch // 16) * 8,
+            "copy_probe": {"GB/s": copy_gbs, "bytes": 2 * int(alg_bytes // 16) * 8,
                            "frac_of_copy": achieved / copy_gbs},
         },
         "kernel_classes": {
-            "velocity_sweep": {"launches": nvel, "ms": ms_vel,
-                               "GB/s": bytes_vel / max(ms_vel, 1e-12) / 1e6},
-            "pressure_sweep": {"launches": npres, "ms": ms_pres,
-                               "GB/s": bytes_pres / max(ms_pres, 1e-12) / 1e6},
-            "full_passes": {"launches": napp, "ms": ms_app,
-                            "GB/s": bytes_app / max(ms_app, 1e-12) / 1e6},
+            "velocity_sweep": {"launches": nvel, "ms": ms_vel},
+            "pressure_sweep": {"launches": npres, "ms": ms_pres},
+            "full_passes": {"launches": napp, "ms": ms_app},
         },
     }
+    if precision == 0 and not args.no_mixed:
+        sm = P.Solver(xyz, tet, nu, tags, cfg.R, precision=1, op=1 if dform else 0, cycle=cycle)
+        xm = torch.empty_like(x0)
+        ms_m, info_m, _ = timed_solves(sm, f_int, x0, xm, args.steps, args.warmup)
+        line["mixed_precision"] = {
+            "value": dofs / (ms_m * 1e-3), "unit": "DoF/s", "ms_per_step": ms_m,
+            "cycles": info_m["cycles"], "rho_mean": info_m["rho_mean"],
+            "status": info_m["status"], "dtype": "f32 cycles in f64 iterative refinement"}
+        print("[bench] mixed-precision solves done", file=sys.stderr, flush=True)
+        del sm, xm
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(args.workload, args.cpu_R)
+        cb = cpu_baseline(args.workload, args.cpu_R, cycle)
+        nproc, model = host_cpu()
         line["cpu_baseline"] = {
             "value": cb["dofs"] / cb["seconds"],
             "unit": "DoF/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": (f"oracle (numpy/scipy, single thread) full solve of the same problem "
-                       f"at {args.cpu_R} refinements ({cb['dofs']} DoFs, {cb['cycles']} cycles, "
-                       f"{cb['seconds']:.1f} s; setup excluded)"),
+            "host": {"nproc": nproc, "cpu_model": model},
+            "sample": (f"oracle (numpy/scipy FP64; its sparse products run on one thread of "
+                       f"the {nproc} host cores) full solve of the same problem at "
+                       f"{args.cpu_R} refinements instead of {cfg.R} ({cb['dofs']} DoFs, "
+                       f"{'Vvar' if cycle else 'V'}(3,3), {cb['cycles']} cycles, "
+                       f"{cb['seconds']:.1f} s; setup excluded): the oracle's assembly of the "
+                       f"full size does not fit a benchmark run"),
         }
     print(json.dumps(line), flush=True)
 

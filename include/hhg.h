@@ -133,6 +133,16 @@ typedef struct {
                               eq. op_count); a colour sweep counts a quarter of its
                               operator, B and B^T count as B, the exact level-0
                               solves count nothing */
+    /* Phase times of hhg_solve in ms, summed over all cycles and levels, from
+     * hipEvent pairs on the stream; 0 unless hhg_set_phase_timing(ctx, 1)
+     * (the events cost a few microseconds each and disable graph replay):
+     *   smooth    Uzawa smoothing steps on levels 1..L;
+     *   transfer  restriction, zeroing of the coarse iterate, prolongation;
+     *   coarse    the level-0 solve (with its residual and correction);
+     *   residual  the residual before each restriction and the stopping test.
+     * t_solve_ms minus their sum is the rest (projection, mixed-precision
+     * scaling, event gaps). */
+    double t_smooth_ms, t_transfer_ms, t_coarse_ms, t_residual_ms;
 } hhg_solve_info;
 
 /* Fills opts with the defaults above. */
@@ -148,7 +158,7 @@ hhg_status hhg_plan(const hhg_mesh* mesh, int32_t n_refine, const hhg_opts* opts
  * matrices of a_1, b, c_l and g_l, Section 2.1) and index tables, and uploads
  * them into d_workspace (device memory of at least hhg_plan's size,
  * 256-byte aligned).  Synchronises the device.  With d_workspace == NULL a
- * host-only context is built for inspection (hhg_node_coords, counts); every
+ * host-only context is built for inspection (hhg_node_info, counts); every
  * device call on it returns HHG_EINVAL. */
 hhg_status hhg_create(const hhg_mesh* mesh, int32_t n_refine, const hhg_opts* opts,
                       void* d_workspace, size_t workspace_bytes, hhg_ctx** ctx);
@@ -309,8 +319,22 @@ hhg_status hhg_scg(hhg_ctx* ctx, void* d_x, const void* d_b, double rtol, int32_
 hhg_status hhg_grad(hhg_ctx* ctx, const void* d_x, const void* d_lambda, const void* d_f,
                     double* d_dJ_dnu, void* d_dJ_df, hhg_stream stream);
 
+/* Right-hand side of the adjoint system of J (not in the paper; K is
+ * symmetric, eq. linear-system): d_rhs = (dJ/du with its velocity Dirichlet
+ * rows zeroed, Pi^T dJ/dp) on the finest level, where Pi p = p - m (m.p) /
+ * sum(m) is the mean-zero pressure projection (Section 2.1, L^2_0; m_i =
+ * int phi_i) and Pi^T q = q - m (sum_i q_i) / sum(m) its transpose.  When a
+ * natural boundary removes the pressure null space, Pi is the identity.
+ * d_g: 4 fields (dJ/du_x, dJ/du_y, dJ/du_z, dJ/dp) in the internal layout of
+ * the finest level (every copy of a vertex equal, as hhg_scatter writes
+ * them); d_rhs: 4 fields, every slot written.  EINVAL if they alias. */
+hhg_status hhg_adjoint_rhs(hhg_ctx* ctx, const void* d_g, void* d_rhs, hhg_stream stream);
+
 /* Replaces the per-macro viscosity (host array [nt], > 0) and rebuilds every
- * stencil table; synchronises the device. */
+ * viscosity-dependent table (stencils, level-0 system, the pressure
+ * preconditioner of hhg_pminres and hhg_scg).  Synchronises the device
+ * before and after the upload, so work queued on any stream finishes with
+ * the old tables. */
 hhg_status hhg_set_viscosity(hhg_ctx* ctx, const double* nu);
 
 /* Per-kernel-class timing.  When enabled, the launches of the classes below
@@ -326,6 +350,10 @@ enum {
     HHG_K_NCLASS = 3
 };
 hhg_status hhg_set_timing(hhg_ctx* ctx, int32_t on);
+/* Phase timers of hhg_solve (the t_*_ms fields of hhg_solve_info): on = 1
+ * brackets every phase of every cycle by a hipEvent pair, on = 0 (default)
+ * records nothing.  Host only. */
+hhg_status hhg_set_phase_timing(hhg_ctx* ctx, int32_t on);
 hhg_status hhg_kernel_time(hhg_ctx* ctx, int32_t kclass, int64_t* launches, double* ms,
                            double* bytes);
 

@@ -35,6 +35,25 @@ def adjoint_rhs(lv, u, u_obs):
     return b
 
 
+def project_transpose(lv, q):
+    """Pi^T q for the mean-zero projection Pi p = p - 1 (m . p) / sum(m) of the
+    pressure (Section 2.1: the pressure lives in L^2_0; m_i = int phi_i):
+    Pi^T q = q - m (1 . q) / sum(m)."""
+    return q - lv.mass * (q.sum() / lv.mass.sum())
+
+
+def adjoint_rhs_general(lv, gu, gp, project):
+    """Right-hand side of K lambda = dJ/dx for a loss J(u, Pi p) with
+    gradients gu [3,N] (velocity) and gp [N] (pressure): gu on the free
+    velocity rows (Dirichlet rows are not unknowns), Pi^T gp on the pressure
+    rows (the identity when `project` is False, i.e. without a null space)."""
+    b = np.zeros((4, lv.N))
+    b[:3] = gu
+    b[:3, lv.dirichlet] = 0.0
+    b[3] = project_transpose(lv, gp) if project else gp
+    return b
+
+
 def grad_forcing(lv, lam):
     lu = lam[:3].copy()
     lu[:, lv.dirichlet] = 0.0

@@ -91,17 +91,3 @@ def pminres_ops(L: int, iterations: int, nu: int = 1) -> dict:
     k = iterations + 1
     return {"A": k * (1.0 + velocity_cycle_ops(L, nu, nu)), "B": 2.0 * k, "C": float(k),
             "M": float(k)}
-
-
-def scg_ops(L: int, outer: int, n_A: int = 3, n_S: int = 3, n_I: int = 1, nu: int = 3) -> dict:
-    """Operator evaluations of the Schur-complement CG (Algorithm 1) with
-    `outer` outer iterations: per outer iteration B^T p for the velocity
-    right-hand side, n_A velocity V(nu, nu) cycles, the Schur residual
-    B u - C p - g and its preconditioning by M, then n_S CG steps each with
-    B^T d, n_I cycles, B w, C d and M; the stopping test applies K once per
-    outer iteration and once at the start."""
-    cyc = velocity_cycle_ops(L, nu, nu)
-    return {"A": (outer + 1) + outer * (n_A + n_S * n_I) * cyc,
-            "B": 2.0 * (outer + 1) + outer * (2 + 2 * n_S),
-            "C": (outer + 1) + outer * (1 + n_S),
-            "M": float(outer * (1 + n_S))}

@@ -53,7 +53,9 @@ class SolveInfo(ctypes.Structure):
                 ("r_final", ctypes.c_double), ("rel_res", ctypes.c_double),
                 ("rho_mean", ctypes.c_double), ("rho_max", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("res_hist", ctypes.c_double * 256),
-                ("n_op", ctypes.c_double * 4)]
+                ("n_op", ctypes.c_double * 4), ("t_smooth_ms", ctypes.c_double),
+                ("t_transfer_ms", ctypes.c_double), ("t_coarse_ms", ctypes.c_double),
+                ("t_residual_ms", ctypes.c_double)]
 
 
 def _load():
@@ -99,6 +101,8 @@ def _load():
         "hhg_pminres": (S, [P, P, P, D, I32, I32, ctypes.POINTER(SolveInfo), P]),
         "hhg_scg": (S, [P, P, P, D, I32, I32, I32, I32, I32, ctypes.POINTER(SolveInfo), P]),
         "hhg_grad": (S, [P, P, P, P, P, P, P]),
+        "hhg_adjoint_rhs": (S, [P, P, P, P]),
+        "hhg_set_phase_timing": (S, [P, I32]),
         "hhg_set_viscosity": (S, [P, P]),
         "hhg_set_timing": (S, [P, I32]),
         "hhg_kernel_time": (S, [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D),
@@ -121,8 +125,8 @@ ABI_FUNCTIONS = ("hhg_default_opts", "hhg_plan", "hhg_create", "hhg_destroy", "h
                  "hhg_apply", "hhg_residual",
                  "hhg_smooth", "hhg_restrict", "hhg_prolong_add", "hhg_coarse_solve",
                  "hhg_project", "hhg_vcycle", "hhg_solve", "hhg_vel_cycle", "hhg_pminres",
-                 "hhg_scg", "hhg_grad", "hhg_set_viscosity",
-                 "hhg_set_timing", "hhg_kernel_time")
+                 "hhg_scg", "hhg_grad", "hhg_adjoint_rhs", "hhg_set_viscosity",
+                 "hhg_set_timing", "hhg_set_phase_timing", "hhg_kernel_time")
 
 
 def default_opts(**kw) -> Opts:
@@ -340,7 +344,9 @@ class Solver:
         return {"status": st, "cycles": k, "r0": info.r0, "r_final": info.r_final,
                 "rel_res": info.rel_res, "rho_mean": info.rho_mean, "rho_max": info.rho_max,
                 "t_solve_ms": info.t_solve_ms, "res_hist": list(info.res_hist[:min(k, 255) + 1]),
-                "n_op": dict(zip("ABCM", list(info.n_op)))}
+                "n_op": dict(zip("ABCM", list(info.n_op))),
+                "t_phase_ms": {"smooth": info.t_smooth_ms, "transfer": info.t_transfer_ms,
+                               "coarse": info.t_coarse_ms, "residual": info.t_residual_ms}}
 
     def solve(self, x, b, rtol=1e-8, max_cycles=100, raise_on_noconv=False):
         info = SolveInfo()
@@ -377,6 +383,13 @@ class Solver:
                             _stream()), self.ctx)
         return dnu, df
 
+    def adjoint_rhs(self, g):
+        """(dJ/du with Dirichlet rows zeroed, Pi^T dJ/dp) from g (4 fields,
+        internal layout of the finest level)."""
+        y = self.vector()
+        _check(lib.hhg_adjoint_rhs(self.ctx, _ptr(g), _ptr(y), _stream()), self.ctx)
+        return y
+
     def set_viscosity(self, nu):
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         self._nu_keep = nu
@@ -384,6 +397,9 @@ class Solver:
 
     def set_timing(self, on=True):
         _check(lib.hhg_set_timing(self.ctx, int(on)), self.ctx)
+
+    def set_phase_timing(self, on=True):
+        _check(lib.hhg_set_phase_timing(self.ctx, int(on)), self.ctx)
 
     def kernel_time(self, cls):
         n = ctypes.c_int64(0)

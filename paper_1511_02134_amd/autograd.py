@@ -1,11 +1,14 @@
 """torch.autograd wrapper of the Stokes solve (adjoint through the C ABI).
 
 Forward: u, p = K(nu)^-1 f~(f) with the Dirichlet data of the problem.
-Backward: the adjoint system K lambda = (dL/du on free velocity rows,
-Pi^T dL/dp) reuses the same symmetric saddle-point multigrid (hhg_solve), then
-hhg_grad evaluates dL/df = R^T lambda and dL/dnu_e = lambda^T (df~/dnu_e -
-dK/dnu_e x) in a kernel.  Pi is the mean-zero projection of the pressure
-(p - (m.p)/sum(m)), applied only when the pressure has a null space.
+Backward: hhg_adjoint_rhs forms the adjoint right-hand side (dL/du on free
+velocity rows, Pi^T dL/dp, with Pi the mean-zero projection of the pressure
+when it has a null space), the adjoint system K lambda = that right-hand side
+reuses the same symmetric saddle-point multigrid (hhg_solve), and hhg_grad
+evaluates dL/df = R^T lambda and dL/dnu_e = lambda^T (df~/dnu_e - dK/dnu_e x)
+in a kernel.  Everything past the argument marshalling runs in the library.
+The backward pass re-installs the viscosity of its own forward call, so
+solves at other viscosities in between do not change the gradient.
 """
 from __future__ import annotations
 
@@ -31,24 +34,13 @@ class StokesProblem:
             x0[:3] = torch.where(self.dirichlet[None, :], bc, torch.zeros_like(bc))
         self.x0 = x0
         self._nu = None
-        self.project = self._has_null_space()
         self.last_info = None
-
-    def _has_null_space(self):
-        # hhg_project is a no-op without a null space; detect it from the mesh tags
-        return not bool(np.any(self.s._mesh.face_bc == 2))
 
     def set_viscosity(self, nu):
         nu_np = nu.detach().double().cpu().numpy()
         if self._nu is None or not np.array_equal(nu_np, self._nu):
             self.s.set_viscosity(nu_np)
             self._nu = nu_np.copy()
-
-    def mass(self):
-        """int phi_i per node: the weights of the mean-zero projection."""
-        if getattr(self, "_mass", None) is None:
-            self._mass = torch.tensor(self.s.mass_weights(), device=self.s.device)
-        return self._mass
 
     def solve(self, rhs_internal, x0_nodal):
         x = self.s.scatter(x0_nodal)
@@ -73,23 +65,22 @@ class StokesSolve(torch.autograd.Function):
         ctx.prob = prob
         ctx.x = x
         ctx.f_int = f_int
+        ctx.nu = nu.detach().clone()
         return out[:3].clone(), out[3].clone()
 
     @staticmethod
     def backward(ctx, gu, gp):
         prob = ctx.prob
         s = prob.s
+        prob.set_viscosity(ctx.nu)
         N = s.num_nodes()
         g = torch.zeros(4, N, dtype=torch.float64, device=s.device)
         if gu is not None:
-            g[:3] = torch.where(prob.dirichlet[None, :], torch.zeros_like(gu), gu)
+            g[:3] = gu
         if gp is not None:
-            gpp = gp.clone()
-            if prob.project:
-                m = prob.mass()
-                gpp = gpp - m * gpp.sum() / m.sum()       # Pi^T gp
-            g[3] = gpp
-        lam = prob.solve(s.scatter(g), torch.zeros(4, N, dtype=torch.float64, device=s.device))
+            g[3] = gp
+        lam = prob.solve(s.adjoint_rhs(s.scatter(g)),
+                         torch.zeros(4, N, dtype=torch.float64, device=s.device))
         dnu, df_int = s.grad(ctx.x, lam, ctx.f_int)
         df = s.gather(df_int)
         return df, dnu, None

@@ -113,6 +113,9 @@ struct hhg_ctx {
     double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
     double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
     double bytes_ru_fused[4] = {0, 0, 0, 0}, bytes_bp_fused[4] = {0, 0, 0, 0};
+    // phase timing of hhg_solve (smoothing, transfers, coarse solve, residuals)
+    bool phase_timing = false, phase_active = false;
+    std::vector<TimerPair> ppairs[4];
 };
 
 namespace {
@@ -380,6 +383,22 @@ hhg_status upload_stencils(hhg_ctx* c) {
     if ((s = upload<double>(c, (double*)c->cd.mass, C.mass.data(), C.mass.size())) != HHG_OK)
         return s;
     c->cd.inv_mass = c->inv_mass[0];
+    {
+        // pressure preconditioner of the Krylov solvers on the finest level:
+        // 1 / (lumped pressure mass weighted by 1/nu) on every copy; it
+        // depends on the viscosity, so it is rebuilt with the stencils
+        HostLevel& h = c->H[c->L];
+        std::vector<double> pinv((size_t)h.len, 0.0);
+        for (int64_t q = 0; q < h.len; ++q) {
+            const int32_t nd = h.slot_node[q];
+            if (nd < 0) continue;
+            const int32_t sid = h.node_sid[nd];
+            const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
+                                        : &h.st[(size_t)sid * ST_SIZE];
+            pinv[q] = 1.0 / rec[ST_MASSNU];
+        }
+        if ((s = upload<double>(c, c->A[c->L].pinv, pinv.data(), pinv.size())) != HHG_OK) return s;
+    }
     return HHG_OK;
 }
 
@@ -473,22 +492,16 @@ hhg_status upload_all(hhg_ctx* c) {
     }
     if ((s = upload_stencils(c)) != HHG_OK) return s;
     {
-        // primary-slot flags and the pressure preconditioner of the finest level
+        // primary-slot flags of the finest level (inner products count each
+        // vertex once); the pressure preconditioner came with the stencils
         HostLevel& h = c->H[c->L];
         std::vector<uint8_t> own((size_t)h.len, 0);
-        std::vector<double> pinv((size_t)h.len, 0.0);
         for (int64_t q = 0; q < h.len; ++q) {
             const int32_t nd = h.slot_node[q];
-            if (nd < 0) continue;
-            if (h.node_slot[nd] == q) own[q] = 1;
-            const int32_t sid = h.node_sid[nd];
-            const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
-                                        : &h.st[(size_t)sid * ST_SIZE];
-            pinv[q] = 1.0 / rec[ST_MASSNU];
+            if (nd >= 0 && h.node_slot[nd] == q) own[q] = 1;
         }
         DevLevelArrays& a = c->A[c->L];
         if ((s = upload<uint8_t>(c, a.owned, own.data(), own.size())) != HHG_OK) return s;
-        if ((s = upload<double>(c, a.pinv, pinv.data(), pinv.size())) != HHG_OK) return s;
     }
     // algorithmic bytes of the timed kernel classes on the finest level
     HostLevel& h = c->H[c->L];
@@ -594,6 +607,33 @@ struct TimedGroup {
         tp.n = c->tgroup_n;
         c->tgroup_cls = -1;
         if (tp.n > 0) c->tpairs[cls].push_back(tp);
+    }
+};
+
+// Event pair around the launches of one phase of a cycle, on all levels
+// (hhg_solve's phase timers; off unless requested).
+enum { PH_SMOOTH = 0, PH_TRANSFER = 1, PH_COARSE = 2, PH_RESIDUAL = 3 };
+struct PhaseTimed {
+    hhg_ctx* c;
+    int ph;
+    hipStream_t s;
+    TimerPair tp{nullptr, nullptr, 1};
+    bool on;
+    PhaseTimed(hhg_ctx* c_, int ph_, hipStream_t s_)
+        : c(c_), ph(ph_), s(s_), on(c_->phase_timing && c_->phase_active) {
+        if (!on) return;
+        tp.a = next_event(c);
+        tp.b = next_event(c);
+        if (!tp.a || !tp.b) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(tp.a, s);
+    }
+    ~PhaseTimed() {
+        if (!on) return;
+        (void)hipEventRecord(tp.b, s);
+        c->ppairs[ph].push_back(tp);
     }
 };
 
@@ -952,6 +992,7 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     vecs<T>(c, l, &xl, &bl, &rl, &tl);
     if (l == 0) {
         // x += K_0^-1 (b - K_0 x)
+        PhaseTimed pt(c, PH_COARSE, s);
         full_pass<T, MODE_RES>(c, 0, x, b, rl, s);
         coarse_solve<T>(c, rl, tl, s);
         const size_t n4 = 4 * (size_t)c->H[0].len;
@@ -961,18 +1002,35 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     // the mirror of x is current on entry (refreshed, filled, or written by
     // the previous cycle's sweeps and projection) and the sweeps keep it so
     const int extra = c->opts.cycle == 1 ? 2 * (top - l) : 0;
-    for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
-    residual_mirror<T>(c, l, x, b, rl, s);
+    {
+        PhaseTimed pt(c, PH_SMOOTH, s);
+        for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
+    }
+    {
+        PhaseTimed pt(c, PH_RESIDUAL, s);
+        residual_mirror<T>(c, l, x, b, rl, s);
+    }
     T *xc, *bc, *rc, *tc;
     vecs<T>(c, l - 1, &xc, &bc, &rc, &tc);
-    restrict_to<T>(c, l, rl, bc, s);
+    {
+        PhaseTimed pt(c, PH_TRANSFER, s);
+        restrict_to<T>(c, l, rl, bc, s);
+    }
     if (l - 1 == 0) {
+        PhaseTimed pt(c, PH_COARSE, s);
         coarse_solve<T>(c, bc, xc, s);
     } else {
-        fill_iterate<T>(c, l - 1, xc, s);
+        {
+            PhaseTimed pt(c, PH_TRANSFER, s);
+            fill_iterate<T>(c, l - 1, xc, s);
+        }
         vcycle<T>(c, l - 1, top, xc, bc, s);
     }
-    prolong_add<T>(c, l, xc, x, s);
+    {
+        PhaseTimed pt(c, PH_TRANSFER, s);
+        prolong_add<T>(c, l, xc, x, s);
+    }
+    PhaseTimed pt(c, PH_SMOOTH, s);
     for (int q = 0; q < c->opts.nu2 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
 }
 
@@ -1498,10 +1556,14 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
             cycle_mixed(c, x, st);
         else
             cycle_fp64(c, x, b, st);
+        PhaseTimed pt(c, PH_RESIDUAL, st);
         residual_norm<double>(c, c->L, x, b, r, c->scal, st, fp64);
     };
-    hhg_ctx::CycleGraph* graph =
-        (c->opts.graphs && !c->timing) ? cycle_graph(c, x, b, body) : nullptr;
+    for (auto& v : c->ppairs) v.clear();
+    c->phase_active = c->phase_timing;
+    hhg_ctx::CycleGraph* graph = (c->opts.graphs && !c->timing && !c->phase_timing)
+                                     ? cycle_graph(c, x, b, body)
+                                     : nullptr;
     for (k = 1; k <= max_cycles; ++k) {
         if (graph)
             HIPCHECK(c, replay(c, graph, s));
@@ -1528,6 +1590,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
         stagn = rho > 0.99 ? stagn + 1 : 0;      // stagnation
         if (stagn >= 5) break;
     }
+    c->phase_active = false;
     if (e1) (void)hipEventRecord(e1, s);
     if (e0 && e1) {
         (void)hipEventSynchronize(e1);
@@ -1537,6 +1600,15 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     }
     if (I->cycles > 0) I->rho_mean = std::pow(I->rel_res, 1.0 / I->cycles);
     put_ops(c, I);
+    {
+        double* dst[4] = {&I->t_smooth_ms, &I->t_transfer_ms, &I->t_coarse_ms, &I->t_residual_ms};
+        for (int ph = 0; ph < 4; ++ph) {
+            double t = 0.0;
+            for (const TimerPair& tp : c->ppairs[ph]) t += event_ms(tp.a, tp.b);
+            *dst[ph] = t;
+            c->ppairs[ph].clear();
+        }
+    }
     I->status = st;
     c->evused = c->timing ? c->evused : 0;
     LAUNCH_CHECK(c);
@@ -1565,6 +1637,30 @@ hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, d
     return HHG_OK;
 }
 
+hhg_status hhg_adjoint_rhs(hhg_ctx* c, const void* g, void* y, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_PTR(c, g);
+    CHECK_PTR(c, y);
+    if (g == y) return fail(c, HHG_EINVAL, "g and rhs must not alias");
+    hipStream_t s = (hipStream_t)stream;
+    const int L = c->L;
+    LevelDev<double>& v = view<double>(c, L);
+    const int ib = iface_blocks(v.nif);
+    const int grid = ib + v.n_vtiles;
+    const size_t len = (size_t)v.len;
+    if (c->mi.project) {
+        hipLaunchKernelGGL((k_mass_dot<double, true>), dim3(grid), dim3(TPB), 0, s, v,
+                           (const double*)g + 3 * len, c->partials, ib);
+        hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+                           v.nv_nat + (v.nif + TPB - 1) / TPB, c->scal + 16, 0);
+    }
+    fill<double>((double*)y, 4 * len, 0.0, s);
+    hipLaunchKernelGGL(k_adjoint_rhs, dim3(grid), dim3(TPB), 0, s, v, (const double*)g, (double*)y,
+                       (const double*)(c->scal + 16), c->inv_mass[L], c->mi.project ? 1 : 0, ib);
+    LAUNCH_CHECK(c);
+    return HHG_OK;
+}
+
 hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
     if (!c) return fail(nullptr, HHG_EINVAL, "context is NULL");
     CHECK_PTR(c, nu);
@@ -1579,6 +1675,9 @@ hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
         return fail(c, HHG_EINVAL, err);
     if (!c->device) return HHG_OK;
     drop_graphs(c);
+    // kernels queued on any stream may still read the old tables: the
+    // uploads below are not ordered after them
+    HIPCHECK(c, hipDeviceSynchronize());
     hhg_status st = upload_stencils(c);
     if (st != HHG_OK) return st;
     HIPCHECK(c, hipDeviceSynchronize());
@@ -1859,6 +1958,14 @@ extern "C" hhg_status hhg_check_layout(const hhg_ctx* c) {
 }
 
 extern "C" {
+
+hhg_status hhg_set_phase_timing(hhg_ctx* c, int32_t on) {
+    if (!c) return fail(nullptr, HHG_EINVAL, "context is NULL");
+    if (on != 0 && on != 1) return fail(c, HHG_EINVAL, "on must be 0 or 1");
+    c->phase_timing = on == 1;
+    for (auto& v : c->ppairs) v.clear();
+    return HHG_OK;
+}
 
 hhg_status hhg_set_timing(hhg_ctx* c, int32_t on) {
     CHECK_DEV(c);

@@ -1275,8 +1275,9 @@ __global__ void k_axpy_cast(double* __restrict__ x, const double* __restrict__ s
         x[i] += sc * (double)e[i];
 }
 
-// weighted pressure sum sum_i m_i p_i over unique vertices (block partials)
-template <typename T>
+// weighted pressure sum sum_i m_i p_i over unique vertices (block partials);
+// UNIT: the plain sum sum_i p_i
+template <typename T, bool UNIT = false>
 __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __restrict__ p,
                                                   double* __restrict__ partials, int ib) {
     __shared__ double sh[4];
@@ -1292,7 +1293,7 @@ __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __rest
                 const int j = P.j;
                 const int b0 = (int)(tl.macro * L.mstride) + L.slab_base[k] + row_off(mm, j);
                 const int Q0 = sub_stride(mm);
-                const double w = (double)L.st[(size_t)tl.macro * ST_SIZE + ST_MASS];
+                const double w = UNIT ? 1.0 : (double)L.st[(size_t)tl.macro * ST_SIZE + ST_MASS];
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * P.q + r;
                     if (i < 1 || i > mm - 1 - j) continue;
@@ -1304,10 +1305,59 @@ __global__ void __launch_bounds__(TPB) k_mass_dot(LevelDev<T> L, const T* __rest
         if ((int)blockIdx.x * TPB < L.nif) slot = L.nv_nat + (int)blockIdx.x;
         const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif)
-            acc = (double)L.st[(size_t)L.if_sid[t] * ST_SIZE + ST_MASS] * (double)p[L.if_self[t]];
+            acc = (UNIT ? 1.0 : (double)L.st[(size_t)L.if_sid[t] * ST_SIZE + ST_MASS]) *
+                  (double)p[L.if_self[t]];
     }
     const double tot = block_sum256(acc, sh);
     if (threadIdx.x == 0 && slot >= 0) partials[slot] = tot;
+}
+
+// Right-hand side of the adjoint system K lambda = (dJ/du on free velocity
+// rows, Pi^T dJ/dp) from g = (dJ/du, dJ/dp) in the internal layout, with
+// Pi^T q = q - m (sum_i q_i) / (sum_i m_i) the transpose of the mean-zero
+// projection (applied when `project`); *psum holds sum_i q_i.  Launched
+// over the volume tiles and the interface list like k_mass_dot; writes
+// every vertex slot (all copies of interface vertices), padding untouched.
+__global__ void __launch_bounds__(TPB) k_adjoint_rhs(LevelDev<double> L, const double* __restrict__ g,
+                                                     double* __restrict__ y,
+                                                     const double* __restrict__ psum,
+                                                     double inv_mass, int project, int ib) {
+    const size_t len = (size_t)L.len;
+    const double mean = project ? psum[0] * inv_mass : 0.0;
+    if ((int)blockIdx.x >= ib) {
+        const Tile tl = L.vtiles[blockIdx.x - ib];
+        if (tl.macro < 0) return;
+        const int n = L.n, k = tl.k, mm = n - k;
+        const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+        if (!P.ok) return;
+        const int j = P.j;
+        const int b0 = (int)(tl.macro * L.mstride) + L.slab_base[k] + row_off(mm, j);
+        const int Q0 = sub_stride(mm);
+        const double w = L.st[(size_t)tl.macro * ST_SIZE + ST_MASS];
+        for (int r = 0; r < 4; ++r) {
+            const int i = 4 * P.q + r;
+            if (i < 1 || i > mm - 1 - j) continue;
+            const size_t sl = (size_t)at(b0, Q0, i);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) y[f * len + sl] = g[f * len + sl];
+            y[3 * len + sl] = g[3 * len + sl] - w * mean;
+        }
+        return;
+    }
+    const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    if (t >= L.nif) return;
+    const int self = L.if_self[t];
+    const bool dir = (L.if_flag[t] & 1) != 0;
+    const double w = L.st[(size_t)L.if_sid[t] * ST_SIZE + ST_MASS];
+    double v[4];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) v[f] = dir ? 0.0 : g[f * len + self];
+    v[3] = g[3 * len + self] - w * mean;
+    for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q) {
+        const size_t sl = (size_t)L.if_copy[q];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) y[f * len + sl] = v[f];
+    }
 }
 
 // p -= mean, mean = (sum_i m_i p_i) / (sum_i m_i) from a device scalar

@@ -1,7 +1,7 @@
 """Full-size checks in the benchmark's launch configuration (default options,
 XCD-aware tile order), on the target workloads themselves: unit cube at 7
-refinements in FP64 (Laplace and D form), at 8 refinements in mixed precision,
-and the channel at 7 refinements in mixed precision.
+refinements in FP64 (Laplace and D form), at 8 refinements in mixed precision
+and in FP64, and the channel at 7 refinements in mixed precision.
 
 The oracle cannot assemble these systems, so it evaluates rows one by one
 (oracle.rows, pinned against its global assembly) at sampled vertices: every
@@ -67,14 +67,24 @@ def _sample(cfg, seed, per_set=40):
     return P[np.all((P >= 0) & (P <= ext), axis=1)]
 
 
-@pytest.mark.parametrize("cid,op", [(2, "laplace"), (3, "laplace"), (5, "laplace"), (2, "D")])
-def test_full_size_solve_residual_rows(cid, op):
+# (workload, velocity form, precision, cycle): the unit cube at 7 refinements
+# in V(3,3) (Laplace and D form); the unit cube at 8 refinements in mixed
+# precision and in FP64 (the benchmark's workload) and the channel in mixed
+# precision, all three in the variable V(3,3) cycle, where the plain V(3,3)
+# cycle contracts by more than 0.3 per cycle at these sizes
+FULL = [(2, "laplace", "fp64", 0), (3, "laplace", "mixed", 1), (3, "laplace", "fp64", 1),
+        (5, "laplace", "mixed", 1), (2, "D", "fp64", 0)]
+
+
+@pytest.mark.parametrize("cid,op,prec,cycle", FULL)
+def test_full_size_solve_residual_rows(cid, op, prec, cycle):
     import paper_1511_02134_amd as P
     cfg = W.WORKLOADS[cid]
     xyz, tet, nu, tags = cfg.mesh()
-    precision = 1 if cfg.precision == "mixed" else 0
-    _announce(f"{cfg.name}: R={cfg.R}, precision={cfg.precision}, form={op}")
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if op == "D" else 0)
+    precision = 1 if prec == "mixed" else 0
+    _announce(f"{cfg.name}: R={cfg.R}, precision={prec}, form={op}, cycle={'Vvar' if cycle else 'V'}")
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if op == "D" else 0,
+                 cycle=cycle)
     dev = torch.device("cuda")
     f = cfg.forcing_field()
     x0 = np.zeros((4, s.num_nodes()))
@@ -83,9 +93,12 @@ def test_full_size_solve_residual_rows(cid, op):
     b = s.rhs(s.scatter(torch.tensor(f, device=dev)))
     x = s.scatter(torch.tensor(x0, device=dev))
     info = s.solve(x, b, rtol=1e-8, max_cycles=100)
-    print(f"{info['cycles']} cycles, rel. residual {info['rel_res']:.2e}", flush=True)
+    print(f"{info['cycles']} cycles, rel. residual {info['rel_res']:.2e}, "
+          f"mean contraction {info['rho_mean']:.3f}, {info['t_solve_ms']:.1f} ms", flush=True)
     assert info["status"] == P.HHG_OK
     assert info["rel_res"] <= 1e-8
+    if cycle == 1:
+        assert info["rho_mean"] <= 0.3
     r, rnorm = s.residual(x, b)
     assert rnorm <= 1e-8 * info["r0"] * (1 + 1e-12)
 

@@ -150,3 +150,56 @@ def test_adjoint_gradient_matches_finite_differences(cid, R, precision, op):
         return 0.5 * ((uu - u_obs) ** 2).sum().item()
     fd = (Jf(f + eps * d) - Jf(f - eps * d)) / (2 * eps)
     assert (fg.grad * d).sum().item() == pytest.approx(fd, rel=1e-6)
+
+
+@pytest.mark.parametrize("cid", [4, 5])
+def test_backward_after_another_forward(cid):
+    """The observation is solved after the forward solve whose gradient is
+    taken (so the problem holds another viscosity when backward runs), and
+    the loss observes the pressure too: J = 1/2 ||u - u_obs||^2 +
+    1/2 ||p - p_obs||^2.  The gradients equal the oracle's direct-solve
+    gradients, whose adjoint right-hand side carries Pi^T (p - p_obs) when
+    the pressure has a null space (box) and p - p_obs when it has none
+    (channel)."""
+    from oracle.adjoint import adjoint_rhs_general
+    from paper_1511_02134_amd.autograd import StokesSolve
+    R = 3
+    _announce(f"backward after another forward, config {cid} R={R}")
+    cfg, nu, prob = _problem(cid, R, rtol=1e-12)
+    f = cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 13, 0.3)
+    nu_obs = cfg.observation_viscosity()
+    ft = _dev(f).requires_grad_(True)
+    nut = _dev(nu).requires_grad_(True)
+    u, p = StokesSolve.apply(ft, nut, prob)
+    with torch.no_grad():
+        u_obs, p_obs = StokesSolve.apply(_dev(f), _dev(nu_obs), prob)
+    J = 0.5 * ((u - u_obs) ** 2).sum() + 0.5 * ((p - p_obs) ** 2).sum()
+    J.backward()
+    xyz, tet, _, tags = cfg.mesh()
+    x0 = np.zeros((4, cfg.points().shape[0]))
+    x0[:3] = cfg.dirichlet_field()
+
+    def solve(nu_):
+        H = build_hierarchy(xyz, tet, nu_, tags, R, R0=R)
+        lv = H.finest
+        b = np.zeros((4, lv.N))
+        for k in range(3):
+            b[k] = lv.M @ f[k]
+            b[k][lv.dirichlet] = 0.0
+        b[3] = sum(lv.Gf[k] @ f[k] for k in range(3))
+        xb = x0.copy()
+        xb[:3, lv.free] = 0.0
+        return H, direct_solve(lv, b, H.project, xbc=xb)
+
+    H, x = solve(nu)
+    _, xo = solve(nu_obs)
+    lv = H.finest
+    lam = direct_solve(lv, adjoint_rhs_general(lv, x[:3] - xo[:3], x[3] - xo[3], H.project),
+                       H.project)
+    gf = grad_forcing(lv, lam)
+    gnu = grad_viscosity(lv, x, lam, f, nu)
+    e_f = np.abs(ft.grad.cpu().numpy() - gf).max() / np.abs(gf).max()
+    e_nu = np.abs(nut.grad.cpu().numpy() - gnu).max() / np.abs(gnu).max()
+    _announce(f"dJ/df rel. difference {e_f:.2e}, dJ/dnu {e_nu:.2e}")
+    assert e_f <= 1e-8
+    assert e_nu <= 1e-8

@@ -59,10 +59,30 @@ def test_scatter_gather_exchange(cid, R):
         x = _rand_state(lv, 10 + l)
         xi = s.scatter(_dev(x), l)
         assert np.array_equal(_host(s.gather(xi, l)), x)
-        # corrupt every copy, then the exchange restores them from the primary
+        # the exchange of a consistent vector changes nothing
         y = xi.clone()
         s.exchange(y, l)
         assert torch.equal(y, xi)
+        # slot -> node (scatter of node ids) and node -> primary slot (gather
+        # of slot ids), both through the ABI
+        N, ln = lv.N, s.vec_len(l)
+        ids = _host(s.scatter(_dev(np.arange(1, N + 1, dtype=np.float64)[None, :]), l))[0]
+        node_of = ids.astype(np.int64) - 1                       # -1 on padding
+        prim = _host(s.gather(_dev(np.arange(ln, dtype=np.float64)[None, :]), l))[0].astype(np.int64)
+        assert np.array_equal(node_of[prim], np.arange(N))
+        copies = np.nonzero((node_of >= 0) & (np.arange(ln) != prim[np.maximum(node_of, 0)]))[0]
+        if l >= 1:
+            assert copies.size > 0
+        # overwrite every non-primary copy with other values; the exchange
+        # restores all of them from the primary, and gather is unchanged
+        bad = xi.clone()
+        noise = torch.tensor(np.random.default_rng(90 + l).normal(size=(4, copies.size)),
+                             dtype=torch.float64, device="cuda")
+        bad[:, torch.tensor(copies, device="cuda")] += 1.0 + noise
+        assert np.array_equal(_host(s.gather(bad, l)), x)
+        assert not torch.equal(bad, xi) or copies.size == 0
+        s.exchange(bad, l)
+        assert torch.equal(bad, xi)
 
 
 @pytest.mark.parametrize("cid,R", CASES)

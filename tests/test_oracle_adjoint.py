@@ -58,3 +58,55 @@ def test_gradients_match_finite_differences(cfg_id, op):
         dn[e] = eps
         fd[i] = (J(nu + dn, f) - J(nu - dn, f)) / (2 * eps)
     assert np.abs(gnu[macros] - fd).max() <= 1e-6 * np.abs(gnu).max()
+
+
+def test_projection_transpose_identity():
+    """Pi^T is the transpose of the mean-zero projection: <Pi p, q> = <p, Pi^T q>
+    for random p, q, and Pi^T q has zero sum (it is orthogonal to the
+    constants, the null space of the pressure)."""
+    from oracle.adjoint import project_transpose
+    cfg = W.WORKLOADS[1].with_R(3)
+    xyz, tet, nu, tags = cfg.mesh()
+    lv = build_hierarchy(xyz, tet, nu, tags, 3).finest
+    rng = np.random.default_rng(3)
+    p, q = rng.normal(size=lv.N), rng.normal(size=lv.N)
+    proj = p - (lv.mass @ p) / lv.mass.sum()
+    assert np.dot(proj, q) == pytest.approx(np.dot(p, project_transpose(lv, q)), rel=1e-13)
+    assert abs(project_transpose(lv, q).sum()) < 1e-13 * np.abs(q).sum()
+
+
+def test_pressure_loss_gradient_matches_finite_differences():
+    """A loss that observes the pressure as well, J = 1/2 ||u - u_obs||^2 +
+    1/2 ||p - p_obs||^2 with p the mean-zero discrete pressure: the adjoint
+    right-hand side (u - u_obs on free rows, Pi^T (p - p_obs)) gives dJ/df
+    equal to central differences of J through direct solves (exact up to
+    rounding, J being quadratic in f).  Without Pi^T the pressure part of
+    the right-hand side is incompatible with the null space and the
+    gradient is wrong, which the test also checks."""
+    from oracle.adjoint import adjoint_rhs_general
+    R = 3
+    cfg = W.WORKLOADS[4].with_R(R)
+    _, tet, nu, _ = cfg.mesh()
+    f = cfg.forcing_field() + W.nodal_noise(cfg.points().shape[0], 12, 0.3)
+    H, x = _forward(cfg, nu, f, R)
+    lv = H.finest
+    assert H.project
+    rng = np.random.default_rng(21)
+    u_obs = x[:3] + rng.normal(size=x[:3].shape)
+    p_obs = rng.normal(size=lv.N)
+
+    def J(f_):
+        _, xx = _forward(cfg, nu, f_, R)
+        return loss(xx[:3], u_obs) + 0.5 * float(np.sum((xx[3] - p_obs) ** 2))
+
+    gu, gp = x[:3] - u_obs, x[3] - p_obs
+    lam = direct_solve(lv, adjoint_rhs_general(lv, gu, gp, True), H.project)
+    gf = grad_forcing(lv, lam)
+    bad = adjoint_rhs_general(lv, gu, gp, False)
+    lam_bad = direct_solve(lv, bad, H.project)
+    gf_bad = grad_forcing(lv, lam_bad)
+    for _ in range(2):
+        d = rng.normal(size=f.shape)
+        fd = (J(f + d) - J(f - d)) / 2.0
+        assert np.sum(gf * d) == pytest.approx(fd, rel=1e-8)
+        assert abs(np.sum(gf_bad * d) - fd) > 1e-6 * abs(fd)

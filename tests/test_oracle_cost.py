@@ -50,14 +50,3 @@ def test_pminres_counts_match_figure():
     assert c["A"] == pytest.approx(g["PMINRES"]["A"], rel=0.02)
     # UMG needs less than half the A evaluations of PMINRES (the figure's point)
     assert cost.n_op("A", 6, 8) < 0.5 * c["A"]
-
-
-def test_scg_counts_structure():
-    """SCG: C is half of B, as in the figure; every outer iteration costs
-    n_A + n_S n_I velocity cycles."""
-    for outer in (1, 7, 13):
-        c = cost.scg_ops(6, outer)
-        assert c["B"] == pytest.approx(2 * c["C"])
-        assert c["A"] == pytest.approx((outer + 1) + outer * 6 * cost.velocity_cycle_ops(6, 3, 3))
-    # the V(3,3) cycle: 7 A evaluations per level
-    assert cost.velocity_cycle_ops(0, 3, 3) == 7.0

@@ -61,6 +61,36 @@ def test_sor_is_forward_relaxed_gauss_seidel(box_r3):
                        rtol=1e-11)
 
 
+def test_symmetric_sor_is_textbook_ssor(box_r3):
+    """With p_sweep = 'symmetric', Shat^{-1} s is one forward SOR sweep (colours
+    0..3) followed by one backward sweep (colours 3..0) from zero.  Its
+    operator is the textbook SSOR preconditioner in product form,
+    Shat = omega/(2-omega) (D/omega + L) D^{-1} (D/omega + U), with L and U the
+    strictly lower and upper parts of C in the colour ordering: a closed form
+    that shares nothing with the sweep loop.  A wrong backward order, a
+    missing repeat of colour 3 or a relaxation on the wrong side breaks the
+    equality; the symmetry of Shat is checked as well."""
+    cfg, _ = box_r3
+    xyz, tet, nu, tags = cfg.mesh()
+    umg = UMG(build_hierarchy(xyz, tet, nu, tags, 3), p_sweep="symmetric")
+    l = 1
+    lv = umg.H.levels[l]
+    p = _colour_perm(lv, np.arange(lv.N))
+    C = lv.C[p][:, p].toarray()
+    w = umg.omega
+    D = np.diag(np.diag(C))
+    Lo, Up = np.tril(C, -1), np.triu(C, 1)
+    Shat = w / (2.0 - w) * (D / w + Lo) @ np.linalg.solve(D, D / w + Up)
+    assert np.allclose(Shat, Shat.T, rtol=0, atol=1e-13 * np.abs(Shat).max())
+    s = np.random.default_rng(11).normal(size=lv.N)
+    d = umg.sor(l, s)
+    ref = np.linalg.solve(Shat, s[p])
+    assert np.allclose(d[p], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+    # forward half alone differs (the backward half is not a no-op)
+    fwd = UMG(umg.H, p_sweep="forward").sor(l, s)
+    assert np.abs(fwd - d).max() > 1e-3 * np.abs(d).max()
+
+
 def test_exact_solution_is_fixed_point(box_r3):
     """The discrete solution is a fixed point of the Uzawa step and of the
     V-cycle (consistency of eq. Uzawa_smooth and the coarse correction)."""
