@@ -218,6 +218,22 @@ hhg_status hhg_apply(hhg_ctx* ctx, int32_t level, const void* d_x, void* d_y,
  * stream and stores ||r||_2 (free velocity rows and all pressure rows). */
 hhg_status hhg_residual(hhg_ctx* ctx, int32_t level, const void* d_x, const void* d_b,
                         void* d_r, double* h_norm, hhg_stream stream);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the residual of
+ * hhg_residual, r = b - K x on level l, with ||r||_2 (free velocity rows and
+ * all pressure rows) written to the device scalar *d_norm instead of host
+ * memory.  It allocates nothing, records no event and never synchronises:
+ * its per-block partial sums live in a static device array of the library
+ * (8 MiB, 2^20 doubles, one per GPU, held until the process ends); levels
+ * needing more partial sums than that (beyond about 9 refinements of the
+ * unit cube) return HHG_EINVAL.  Every call on one GPU shares that array, so
+ * calls that overlap in time on one GPU (on different streams or host
+ * threads) race; calls ordered on one stream do not.  The context's device
+ * must be the current device (HHG_EINVAL otherwise); r must not alias x or
+ * b.  Results equal hhg_residual's bit for bit. */
+hhg_status hhg_residual_noalloc(hhg_ctx* ctx, int32_t level, const void* d_x, const void* d_b,
+                                void* d_r, double* d_norm, hhg_stream stream);
+
 /* `steps` inexact Uzawa smoothing steps (eq. Uzawa_smooth) in place on x:
  * symmetric 4-colour Gauss-Seidel on the velocity, then the pressure sweep
  * on C with relaxation omega.  Colour of vertex (X,Y,Z) = (X+Y+Z) mod 4. */

@@ -90,6 +90,7 @@ def _load():
         "hhg_fmg": (S, [P, P, P, I32, P]),
         "hhg_apply": (S, [P, I32, P, P, P]),
         "hhg_residual": (S, [P, I32, P, P, P, ctypes.POINTER(D), P]),
+        "hhg_residual_noalloc": (S, [P, I32, P, P, P, P, P]),
         "hhg_smooth": (S, [P, I32, P, P, I32, P]),
         "hhg_restrict": (S, [P, I32, P, P, P]),
         "hhg_prolong_add": (S, [P, I32, P, P, P]),
@@ -122,7 +123,7 @@ ABI_FUNCTIONS = ("hhg_default_opts", "hhg_plan", "hhg_create", "hhg_destroy", "h
                  "hhg_global_error", "hhg_num_levels", "hhg_vec_len", "hhg_num_nodes",
                  "hhg_num_dofs", "hhg_num_interface", "hhg_node_info", "hhg_mass_weights", "hhg_check_layout", "hhg_scatter",
                  "hhg_gather", "hhg_exchange", "hhg_rhs", "hhg_rhs_level", "hhg_fmg",
-                 "hhg_apply", "hhg_residual",
+                 "hhg_apply", "hhg_residual", "hhg_residual_noalloc",
                  "hhg_smooth", "hhg_restrict", "hhg_prolong_add", "hhg_coarse_solve",
                  "hhg_project", "hhg_vcycle", "hhg_solve", "hhg_vel_cycle", "hhg_pminres",
                  "hhg_scg", "hhg_grad", "hhg_adjoint_rhs", "hhg_set_viscosity",
@@ -307,6 +308,13 @@ class Solver:
         _check(lib.hhg_residual(self.ctx, level, _ptr(x), _ptr(b), _ptr(r),
                                 ctypes.byref(nrm) if norm else None, _stream()), self.ctx)
         return r, nrm.value
+
+    def residual_noalloc(self, x, b, r, norm, level=None):
+        """r = b - K x and ||r||_2 into the device scalar `norm` (a float64
+        tensor of one element); allocates nothing (static library scratch)."""
+        level = self.L if level is None else level
+        _check(lib.hhg_residual_noalloc(self.ctx, level, _ptr(x), _ptr(b), _ptr(r), _ptr(norm),
+                                        _stream()), self.ctx)
 
     def smooth(self, x, b, steps=1, level=None):
         level = self.L if level is None else level

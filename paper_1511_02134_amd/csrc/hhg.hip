@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,7 +19,33 @@
 
 using namespace hhg;
 
+// Static scratch of hhg_residual_noalloc: the per-block partial sums of the
+// residual norm, for callers that cannot allocate.  Every GPU the library
+// runs on holds its own copy until the process ends.  In host code the
+// array's name is not a device address: the address of the current device's
+// copy comes from hipGetSymbolAddress (scratch_address below).
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 20;   // 8 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
 namespace {
+
+// device address of `scratch` on device dev (which must be current), looked
+// up once per device and kept
+std::mutex g_scratch_mu;
+double* g_scratch_addr[256] = {};
+
+hipError_t scratch_address(int dev, double** out) {
+    if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
 
 thread_local std::string g_error;
 
@@ -113,6 +140,8 @@ struct hhg_ctx {
     double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
     double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
     double bytes_ru_fused[4] = {0, 0, 0, 0}, bytes_bp_fused[4] = {0, 0, 0, 0};
+    int dev = -1;                  // device of the workspace
+    double* scratch = nullptr;     // that device's copy of the static scratch
     // phase timing of hhg_solve (smoothing, transfers, coarse solve, residuals)
     bool phase_timing = false, phase_active = false;
     std::vector<TimerPair> ppairs[4];
@@ -758,28 +787,39 @@ constexpr int SPLIT_MIN_N = 64;
 // K x or the residual (MODE_APPLY / MODE_RES); MIRROR: interface taps from
 // the level's mirror of x
 template <typename T, int MODE, bool MIRROR, bool DOP>
-void launch_kx_op(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
+void launch_kx_op(LevelDev<T>& v, int ib, const T* x, const T* b, T* y, double* partials,
+                  hipStream_t s) {
     if (v.n >= SPLIT_MIN_N) {
         // volume launch: one vertex per lane (four blocks per tile)
         hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1, DOP>),
-                           dim3(full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, x, b, y, c->partials, 0,
+                           dim3(full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, x, b, y, partials, 0,
                            (T*)nullptr, -1, T(0));
         if (ib > 0)
             hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 2, DOP>), dim3(ib), dim3(TPB), 0,
-                               s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+                               s, v, x, b, y, partials, ib, (T*)nullptr, -1, T(0));
         return;
     }
     hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 0, DOP>), dim3(ib + v.n_vtiles),
-                       dim3(TPB), 0, s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+                       dim3(TPB), 0, s, v, x, b, y, partials, ib, (T*)nullptr, -1, T(0));
 }
 
-// the velocity form of the context: Laplace (a_1) or D (a_2)
+// the velocity form of the context: Laplace (a_1) or D (a_2); the residual's
+// per-block partial sums go to `partials` (the workspace's by default)
 template <typename T, int MODE, bool MIRROR>
-void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s) {
+void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s,
+               double* partials = nullptr) {
+    if (!partials) partials = c->partials;
     if (c->opts.op == 1)
-        launch_kx_op<T, MODE, MIRROR, true>(c, v, ib, x, b, y, s);
+        launch_kx_op<T, MODE, MIRROR, true>(v, ib, x, b, y, partials, s);
     else
-        launch_kx_op<T, MODE, MIRROR, false>(c, v, ib, x, b, y, s);
+        launch_kx_op<T, MODE, MIRROR, false>(v, ib, x, b, y, partials, s);
+}
+
+// number of per-block partial sums of a residual on level l (the entries
+// k_reduce_sum adds up): the volume ones, then one per interface block
+template <typename T>
+inline int residual_partials(const LevelDev<T>& v) {
+    return (v.n >= SPLIT_MIN_N ? 4 : 1) * v.nv_nat + (v.nif + TPB - 1) / TPB;
 }
 
 template <typename T, int MODE>
@@ -931,11 +971,8 @@ void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out,
         ops(c, l, 1, 2, 1, 0);
         launch_kx<T, MODE_RES, false>(c, v, ib, x, b, r, s);
     }
-    // partial sums: per tile (one block per tile) or per tile and sub-row
-    // (split launches, one vertex per lane), then per interface block
-    const int nvol = (v.n >= SPLIT_MIN_N ? 4 : 1) * v.nv_nat;
     hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
-                       nvol + (v.nif + TPB - 1) / TPB, out, 1);
+                       residual_partials(v), out, 1);
 }
 
 template <typename T, int NF = 4>
@@ -1201,6 +1238,11 @@ hhg_status hhg_create(const hhg_mesh* mesh, int32_t R, const hhg_opts* opts, voi
         }
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return fail(nullptr, HHG_EDEVICE, hipGetErrorString(e));
+        if ((e = hipGetDevice(&c->dev)) != hipSuccess)
+            return fail(nullptr, HHG_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+        if ((e = scratch_address(c->dev, &c->scratch)) != hipSuccess)
+            return fail(nullptr, HHG_EDEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
         c->device = true;
     }
     *out = c.release();
@@ -1359,6 +1401,35 @@ hhg_status hhg_residual(hhg_ctx* c, int32_t l, const void* x, const void* b, voi
         HIPCHECK(c, hipMemcpyAsync(h_norm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHECK(c, hipStreamSynchronize(s));
     }
+    return HHG_OK;
+}
+
+hhg_status hhg_residual_noalloc(hhg_ctx* c, int32_t l, const void* x, const void* b, void* r,
+                                double* d_norm, hhg_stream stream) {
+    CHECK_DEV(c);
+    CHECK_LEVEL(c, l);
+    CHECK_PTR(c, x);
+    CHECK_PTR(c, b);
+    CHECK_PTR(c, r);
+    CHECK_PTR(c, d_norm);
+    if (r == x || r == b) return fail(c, HHG_EINVAL, "r must not alias x or b");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != c->dev)
+        return fail(c, HHG_EINVAL, "the context's device must be the current device");
+    LevelDev<double>& v = view<double>(c, l);
+    const int np = residual_partials(v);
+    if ((size_t)np > NOALLOC_SCRATCH_DOUBLES)
+        return fail(c, HHG_EINVAL,
+                    "level too large for the static scratch: " + std::to_string(np) +
+                        " partial sums, at most " + std::to_string(NOALLOC_SCRATCH_DOUBLES));
+    hipStream_t s = (hipStream_t)stream;
+    // every partial in [0, np) is written by its block before the sum reads
+    // it, so the scratch needs no clearing between calls
+    launch_kx<double, MODE_RES, false>(c, v, iface_blocks(v.nif), (const double*)x,
+                                       (const double*)b, (double*)r, s, c->scratch);
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, (const double*)c->scratch, np, d_norm,
+                       1);
+    LAUNCH_CHECK(c);
     return HHG_OK;
 }
 
