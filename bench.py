@@ -1,22 +1,28 @@
 """Benchmark: Stokes DoFs solved per second on one MI355X.
 
-One step = one complete solve of the unit-cube Stokes problem refined 7 times
-(129^3 lattice, 8,291,838 DoFs, FP64, manufactured forcing plus N(0, 0.01)
-nodal noise, V(3,3) Uzawa multigrid to a 1e-8 relative residual from x0 = 0):
-right-hand side assembly, every V-cycle and the per-cycle residual check.
-Inputs are resident in HBM before the timed region.
+One step = one complete solve of the unit-cube Stokes problem refined 8 times
+(257^3 lattice, 66,718,718 DoFs, FP64, manufactured forcing, variable V(3,3)
+Uzawa multigrid to a 1e-8 relative residual from x0 = 0): right-hand side
+assembly, every cycle and the per-cycle residual check.  Inputs are resident
+in HBM before the timed region.  The same problem in mixed precision (FP32
+cycles inside FP64 refinement) is timed beside it.
 
 Printed as one JSON line with, besides the contract fields:
-  tme_factor   solve time / time of one K apply on the finest level (the
-               paper's work unit, Section 5), both measured here;
-  roofline     the velocity colour sweep (the dominant kernel) against the
-               8 TB/s HBM peak, algorithmic bytes per launch / measured mean
-               launch time (hipEvents on its stream, one pair around the six
-               back-to-back sweeps of each smoothing step);
-  cpu_baseline the FP64 oracle (numpy/scipy) solving the same problem at a
-               bounded size on the host cores, setup excluded.
+  tme_factor      solve time / time of one K apply on the finest level (the
+                  paper's work unit, Section 5), both measured here;
+  phases_ms       smoothing, transfers, coarse solves and residuals of one
+                  solve (hipEvent pairs around every phase);
+  roofline        the finest velocity colour sweep (the dominant kernel)
+                  against the 8 TB/s HBM peak: algorithmic bytes per launch
+                  (10 values per finest vertex per sweep direction, a quarter
+                  per colour launch) / its mean launch time (hipEvents on its
+                  stream, one pair around the six back-to-back sweeps of each
+                  smoothing step);
+  mixed_precision the FP32-in-FP64 solve of the same problem;
+  cpu_baseline    the FP64 oracle (numpy/scipy) solving the same problem at a
+                  bounded size on the host, setup excluded.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
     python bench.py --tme R        (full multigrid efficiency study)
     python bench.py --compare R    (UMG / PMINRES / SCG comparison)
 """
@@ -36,7 +42,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "Stokes DoFs solved/s to 1e-8 rel. residual; TME factor; smoother HBM GB/s"
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_unitcube_R7_fp64.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_unitcube_R8_fp64.md")
 
 
 def sources_digest() -> str:
@@ -63,9 +69,10 @@ def measured_traffic():
         return None
     vals = {}
     for ln in lines:
+        ln = ln.strip().lstrip("-").strip()
         if ":" in ln and ln.split(":", 1)[0].strip() in ("sources_sha256", "traffic_bytes_per_launch"):
             k, v = ln.split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
+            vals[k.strip()] = v.strip().split()[0].strip("`")
     if vals.get("sources_sha256") != sources_digest() or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])
