@@ -25,6 +25,7 @@ Printed as one JSON line with, besides the contract fields:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
     python bench.py --tme R        (full multigrid efficiency study)
     python bench.py --compare R    (UMG / PMINRES / SCG comparison)
+    python bench.py --shell R      (spherical shell, general macro geometry)
 """
 from __future__ import annotations
 
@@ -266,6 +267,64 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     print(json.dumps(line), flush=True)
 
 
+def run_shell(R: int, steps: int, warmup: int):
+    """The spherical shell 0.55 < |x| < 1 (Section 4.4) as 156 affinely mapped
+    macros: f = 0, homogeneous Dirichlet data on both spheres, a seeded random
+    start (the paper's setting), variable V(3,3) to a 1e-8 relative residual
+    with the MINRES coarse solver.  Reports DoFs solved per second, the phase
+    split of one solve and the mean time and algorithmic HBM rate of the
+    finest velocity colour sweep (15-tap stencils)."""
+    import torch
+    import workloads as W
+    import paper_1511_02134_amd as P
+
+    cfg = W.WORKLOADS[7].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, R, phys=cfg.physical(), cycle=1, coarse_solver=1)
+    dev = torch.device("cuda")
+    dofs, N = s.num_dofs(), s.num_nodes()
+    nvert = int(np.count_nonzero(s.mass_weights() > 0))
+    x0n = np.random.default_rng(0).uniform(0.0, 1.0, size=(4, N))
+    _, dmask = s.node_info()
+    x0n[:3, dmask.astype(bool)] = 0.0
+    x0 = s.scatter(torch.tensor(x0n, device=dev))
+    f_int = s.scatter(torch.zeros(3, N, dtype=torch.float64, device=dev))
+    x = torch.empty_like(x0)
+    print(f"[bench] shell set up: R={R}, {dofs} DoFs", file=sys.stderr, flush=True)
+    ms, info, step = timed_solves(s, f_int, x0, x, steps, warmup)
+    s.set_phase_timing(True)
+    pinfo = step()
+    s.set_phase_timing(False)
+    s.set_timing(True)
+    for _ in range(min(steps, 3)):
+        step()
+    torch.cuda.synchronize()
+    nvel, ms_vel, _ = s.kernel_time(P.K_VEL)
+    npres, ms_pres, _ = s.kernel_time(P.K_PRES)
+    napp, ms_app, _ = s.kernel_time(P.K_APPLY)
+    s.set_timing(False)
+    vel_us = 1000.0 * ms_vel / max(nvel, 1)
+    alg_bytes = 10.0 * 8.0 * nvert / 4.0
+    achieved = alg_bytes / (vel_us * 1e-6) / 1e9
+    line = {"metric": "Stokes DoFs solved/s to 1e-8 rel. residual (spherical shell)",
+            "value": dofs / (ms * 1e-3), "unit": "DoF/s", "ms_per_step": ms,
+            "steps": steps, "warmup": warmup, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"shell-R{R}-fp64", "mesh": "spherical shell 0.55<|x|<1, "
+                       "156 affinely mapped macros (hollow cube [0,3]^3 minus its centre cell)",
+                       "refinements": R, "dofs": dofs, "vertices": nvert,
+                       "cycle": "Vvar(3,3)", "coarse": "block-diagonal PMINRES (lumped mass)",
+                       "cycles": info["cycles"], "rho_mean": info["rho_mean"],
+                       "status": info["status"]},
+            "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
+            "velocity_sweep": {"kernel": "k_colour<double,velocity,15 taps> (finest level)",
+                               "avg_us": vel_us, "bytes_per_launch": alg_bytes,
+                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
+            "kernel_classes": {"velocity_sweep": {"launches": nvel, "ms": ms_vel},
+                               "pressure_sweep": {"launches": npres, "ms": ms_pres},
+                               "full_passes": {"launches": napp, "ms": ms_app}}}
+    print(json.dumps(line), flush=True)
+
+
 def host_cpu():
     """(nproc, CPU model name) of the host."""
     model = "unknown"
@@ -328,6 +387,9 @@ def main():
                     help="full multigrid efficiency study at R refinements (prints its own line)")
     ap.add_argument("--compare", type=int, default=0, metavar="R",
                     help="UMG / PMINRES / SCG comparison at R refinements (prints its own line)")
+    ap.add_argument("--shell", type=int, default=0, metavar="R",
+                    help="spherical shell 0.55 < |x| < 1 at R refinements: the paper's setting "
+                         "(f = 0, random start) on general macro geometry (prints its own line)")
     args = ap.parse_args()
     if args.ops:
         run_ops(args.workload)
@@ -338,6 +400,9 @@ def main():
     if args.compare:
         run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1),
                     args.op == "D")
+        return
+    if args.shell:
+        run_shell(args.shell, args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "

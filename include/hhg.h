@@ -34,6 +34,8 @@
  *  * Nodal (lattice) order: node (X, Y, Z) of the level-l lattice, integer
  *    coordinates in units of 2^-R_l, has index X + nx*(Y + ny*Z) where
  *    nx, ny, nz are the lattice extents of the bounding box of the mesh.
+ *    Lattice points that lie in no macro (a hole of the mesh) are not
+ *    vertices: scatter ignores their values and gather writes 0 there.
  *  * Dirichlet data live in the Dirichlet velocity entries of the solution
  *    vector x and are never modified; the residual and K x vanish on those
  *    rows.  Pressure is an unknown at every vertex.
@@ -62,13 +64,24 @@ typedef enum {
 
 /* Macro mesh T_{-2} (Section 2.1).  All arrays are host memory, read during
  * the call only.  Requirements checked by hhg_plan / hhg_create:
- *   xyz [nv][3]   vertex coordinates on the integer lattice;
+ *   xyz [nv][3]   vertex coordinates on the integer lattice (the topology:
+ *                 refinement, node numbering and colouring follow it);
  *   tet [nt][4]   vertex ids in Kuhn path order: tet[1]-tet[0], tet[2]-tet[1],
  *                 tet[3]-tet[2] are the three distinct positive unit vectors;
- *                 the tetrahedra tile the bounding box of xyz conformingly;
+ *                 the tetrahedra are conforming (a face is shared by at most
+ *                 two) and lie in the bounding box of xyz, which they tile
+ *                 unless `phys` is given (then lattice points of the box may
+ *                 lie in no macro: a hole, such as the inside of a shell);
  *   nu  [nt]      per-macro viscosity > 0 (NULL: all 1);
  *   face_bc [nt][4] tag of the face opposite vertex f: 0 interior (shared by
- *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing). */
+ *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing);
+ *   phys [nv][3]  physical coordinates of the vertices (NULL: xyz).  Every
+ *                 macro carries its refinement affinely (Section 2.1: uniform
+ *                 refinement splits a tetrahedron into 8 by its edge
+ *                 midpoints), so its stencils are those of its own affine
+ *                 image: general 15-point stencils for a_1 and c_l.  Each
+ *                 macro must keep its orientation (positive volume when its
+ *                 lattice image has one). */
 typedef struct {
     int32_t nv;
     const double* xyz;
@@ -76,6 +89,7 @@ typedef struct {
     const int32_t* tet;
     const double* nu;
     const int8_t* face_bc;
+    const double* phys;
 } hhg_mesh;
 
 /* Solver options (Section 3.5 and Table "settings", UMG column). */

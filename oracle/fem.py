@@ -110,6 +110,7 @@ class Level:
     Gf: list = field(default_factory=list)   # g_l as a map of nodal f_k: g = sum_k Gf_k f_k
     colour: np.ndarray = None  # [N] (X+Y+Z) mod 4
     mass: np.ndarray = None    # [N] int phi_i (row sums of M)
+    Xphys: np.ndarray = None   # [N,3] physical coordinates
     E: list = None             # D form only: E[k][l] coupling blocks (N x N)
     A2: sp.csr_matrix = None   # D form only: the 3N x 3N velocity block (component major)
 
@@ -200,7 +201,22 @@ def _dirichlet_nodes(X, n, macro_int, tet, face_bc):
     return mask
 
 
-def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu, op="laplace"):
+def macro_maps(macro_int, tet, phys):
+    """Affine maps of the macro tetrahedra from the integer lattice to physical
+    space: x_phys = o_m + (x - L0_m) F_m, with F_m [3,3] (row vectors) taking
+    the lattice edge vectors L_q - L0 of macro m to P_q - P0.  Uniform
+    refinement is affine on every macro (Section 2.1: each tetrahedron is split
+    into 8 by its edge midpoints), so a refined vertex with lattice
+    coordinates x sits at that image."""
+    L = macro_int[tet].astype(np.float64)                 # [nt,4,3]
+    Pp = np.asarray(phys, dtype=np.float64)[tet]          # [nt,4,3]
+    EL = L[:, 1:] - L[:, :1]
+    EP = Pp[:, 1:] - Pp[:, :1]
+    F = np.linalg.solve(EL, EP)                           # EL F = EP
+    return L[:, 0], Pp[:, 0], F
+
+
+def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu, op="laplace", maps=None):
     n = 1 << R
     ext = macro_int.max(axis=0).astype(np.int64) * n + 1
     shape = (int(ext[0]), int(ext[1]), int(ext[2]))
@@ -210,9 +226,22 @@ def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu, op="laplace"):
     tets = inv.reshape(-1, 4).astype(np.int64)
     X = np.stack([lat % shape[0], (lat // shape[0]) % shape[1], lat // (shape[0] * shape[1])],
                  axis=1)
-    vol, G = p1_geometry(Pint.astype(np.float64) / n)
+    if maps is None:
+        Pphys = Pint.astype(np.float64) / n
+    else:
+        L0, O, F = maps
+        m = tet_macro
+        Pphys = O[m][:, None, :] + np.einsum("tqd,tde->tqe",
+                                             Pint.astype(np.float64) / n - L0[m][:, None, :], F[m])
+    vol, G = p1_geometry(Pphys)
     lv = Level(R=R, n=n, shape=shape, lat=lat, X=X, tets=tets, tet_macro=tet_macro,
                vol=vol, G=G, dirichlet=_dirichlet_nodes(X, n, macro_int, tet, face_bc))
+    # physical coordinates of the nodes (from the first element holding each)
+    first = np.full(lat.shape[0], -1, dtype=np.int64)
+    flat = tets.ravel()
+    order = np.arange(flat.shape[0])
+    first[flat[::-1]] = order[::-1]
+    lv.Xphys = Pphys.reshape(-1, 3)[first]
     lv.colour = (X.sum(axis=1) % 4).astype(np.int64)
     assemble_level(lv, nu, op=op)
     return lv
@@ -261,26 +290,32 @@ class Hierarchy:
         return self.levels[-1]
 
 
-def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2, op="laplace"):
-    """Levels R0..R of the uniformly refined macro mesh (xyz must be integer);
-    op selects the velocity form, "laplace" (a_1) or "D" (a_2)."""
+def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2, op="laplace", phys=None):
+    """Levels R0..R of the uniformly refined macro mesh; op selects the velocity
+    form, "laplace" (a_1) or "D" (a_2).  xyz are integer lattice coordinates of
+    the macro vertices (the topology: refinement, node numbering, colours);
+    phys, if given, their physical coordinates, which every macro carries
+    affinely into its refinement (general macro geometry); otherwise the
+    lattice coordinates are physical.  Lattice points outside every macro
+    (a hole in the bounding box) are not nodes."""
     if op not in ("laplace", "D"):
         raise ValueError(op)
     macro_int = np.rint(xyz).astype(np.int64)
     if not np.array_equal(macro_int, xyz):
         raise ValueError("oracle expects macro vertices on the integer lattice")
+    maps = None if phys is None else macro_maps(macro_int, tet, phys)
     nu = np.asarray(nu, dtype=np.float64)
     P = macro_int[tet]                                  # [nt,4,3] at scale 1
     tet_macro = np.arange(tet.shape[0])
     for _ in range(R0):
         P = refine(P)
         tet_macro = np.repeat(tet_macro, 8)
-    levels = [_make_level(P, tet_macro, R0, macro_int, tet, face_bc, nu, op)]
+    levels = [_make_level(P, tet_macro, R0, macro_int, tet, face_bc, nu, op, maps)]
     prol = [None]
     for r in range(R0 + 1, R + 1):
         P = refine(P)
         tet_macro = np.repeat(tet_macro, 8)
-        lv = _make_level(P, tet_macro, r, macro_int, tet, face_bc, nu, op)
+        lv = _make_level(P, tet_macro, r, macro_int, tet, face_bc, nu, op, maps)
         prol.append(_prolongation(levels[-1], None, lv))
         levels.append(lv)
     project = not np.any(face_bc == 2)

@@ -23,7 +23,7 @@ import itertools
 
 import numpy as np
 
-from .fem import DELTA, _dirichlet_nodes, p1_geometry
+from .fem import DELTA, _dirichlet_nodes, macro_maps, p1_geometry
 
 _E = np.eye(3, dtype=np.int64)
 _KUHN = [np.array([np.zeros(3, np.int64), _E[s[0]], _E[s[0]] + _E[s[1]], np.ones(3, np.int64)])
@@ -47,8 +47,9 @@ def _patch(X, ext):
     return np.array(tets), np.array(loc)
 
 
-def _macro_of(points, xyz, tet):
-    """Index of the macro tetrahedron containing each point (strictly inside)."""
+def _macro_of(points, xyz, tet, holes=False):
+    """Index of the macro tetrahedron containing each point (strictly inside);
+    with holes, -1 for points in no macro."""
     P = xyz[tet]                                   # [nt,4,3]
     J = P[:, 1:, :] - P[:, :1, :]
     Jinv = np.linalg.inv(np.transpose(J, (0, 2, 1)))   # maps x - x0 to (l1, l2, l3)
@@ -58,14 +59,19 @@ def _macro_of(points, xyz, tet):
         lam = np.concatenate([1.0 - lam.sum(axis=1, keepdims=True), lam], axis=1)
         inside = np.all(lam > 1e-12, axis=1) & (out < 0)
         out[inside] = t
-    if np.any(out < 0):
+    if np.any(out < 0) and not holes:
         raise ValueError("a lattice tetrahedron lies in no macro")
     return out
 
 
-def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f, op="laplace"):
+def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f, op="laplace", phys=None):
     """Rows of f~ and of K x at the vertices verts [m,3] (integer lattice
     coordinates at 2^R per unit length).
+
+    phys: physical coordinates of the macro vertices (general geometry, as in
+    fem.build_hierarchy); the lattice tetrahedra around a vertex then keep
+    only those inside a macro and are carried to physical space by their
+    macro's affine map.
 
     x [4,N] (velocity with its Dirichlet values, pressure) and f [3,N] are
     nodal fields in lattice order (index X + nx (Y + ny Z)).  Returns
@@ -81,14 +87,25 @@ def stokes_rows(xyz, tet, nu, face_bc, R, verts, x, f, op="laplace"):
     nu = np.asarray(nu, dtype=np.float64)
     verts = np.asarray(verts, dtype=np.int64)
     dirich = _dirichlet_nodes(verts, n, macro_int, tet, face_bc)
+    maps = None if phys is None else macro_maps(macro_int, tet, phys)
     b = np.zeros((4, verts.shape[0]))
     kx = np.zeros((4, verts.shape[0]))
     scale = np.zeros((4, verts.shape[0]))
     for m, X in enumerate(verts):
         T, a = _patch(X, ext)
-        vol, G = p1_geometry(T.astype(np.float64) / n)
         cen = T.mean(axis=1).astype(np.float64) / n
-        nuT = nu[_macro_of(cen, macro_int.astype(np.float64), tet)]
+        mac = _macro_of(cen, macro_int.astype(np.float64), tet, holes=maps is not None)
+        keep = mac >= 0
+        T, a, mac = T[keep], a[keep], mac[keep]
+        if maps is None:
+            vol, G = p1_geometry(T.astype(np.float64) / n)
+        else:
+            L0, O, F = maps
+            Pt = O[mac][:, None, :] + np.einsum("tqd,tde->tqe",
+                                                T.astype(np.float64) / n - L0[mac][:, None, :],
+                                                F[mac])
+            vol, G = p1_geometry(Pt)
+        nuT = nu[mac]
         hT2 = vol ** (2.0 / 3.0)
         idx = T[..., 0] + nx * (T[..., 1] + ny * T[..., 2])      # [m,4] node indices
         Ga = G[np.arange(T.shape[0]), a]                          # [m,3] grad phi of the vertex

@@ -36,7 +36,8 @@ class Mesh(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int32), ("xyz", ctypes.POINTER(ctypes.c_double)),
                 ("nt", ctypes.c_int32), ("tet", ctypes.POINTER(ctypes.c_int32)),
                 ("nu", ctypes.POINTER(ctypes.c_double)),
-                ("face_bc", ctypes.POINTER(ctypes.c_int8))]
+                ("face_bc", ctypes.POINTER(ctypes.c_int8)),
+                ("phys", ctypes.POINTER(ctypes.c_double))]
 
 
 class Opts(ctypes.Structure):
@@ -143,11 +144,12 @@ def default_opts(**kw) -> Opts:
 class _MeshArrays:
     """Keeps the host arrays of a Mesh struct alive."""
 
-    def __init__(self, xyz, tet, nu, face_bc):
+    def __init__(self, xyz, tet, nu, face_bc, phys=None):
         self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         self.tet = np.ascontiguousarray(tet, dtype=np.int32)
         self.nu = None if nu is None else np.ascontiguousarray(nu, dtype=np.float64)
         self.face_bc = np.ascontiguousarray(face_bc, dtype=np.int8)
+        self.phys = None if phys is None else np.ascontiguousarray(phys, dtype=np.float64)
         m = Mesh()
         m.nv = self.xyz.shape[0]
         m.xyz = self.xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -156,6 +158,8 @@ class _MeshArrays:
         m.nu = (self.nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                 if self.nu is not None else ctypes.POINTER(ctypes.c_double)())
         m.face_bc = self.face_bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        m.phys = (self.phys.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                  if self.phys is not None else ctypes.POINTER(ctypes.c_double)())
         self.struct = m
 
 
@@ -165,9 +169,9 @@ def _check(status, ctx=None):
         raise HHGError(status, msg.decode())
 
 
-def plan(xyz, tet, nu, face_bc, R, **opts) -> int:
+def plan(xyz, tet, nu, face_bc, R, phys=None, **opts) -> int:
     """Workspace bytes for the mesh (host only, validates the inputs)."""
-    m = _MeshArrays(xyz, tet, nu, face_bc)
+    m = _MeshArrays(xyz, tet, nu, face_bc, phys)
     o = default_opts(**opts)
     nbytes = ctypes.c_size_t(0)
     _check(lib.hhg_plan(ctypes.byref(m.struct), R, ctypes.byref(o), ctypes.byref(nbytes)))
@@ -186,8 +190,9 @@ def _stream():
 class Solver:
     """Hierarchy, stencils and work space of one macro mesh refined R times."""
 
-    def __init__(self, xyz, tet, nu, face_bc, R, device="cuda", host_only=False, **opts):
-        self._mesh = _MeshArrays(xyz, tet, nu, face_bc)
+    def __init__(self, xyz, tet, nu, face_bc, R, device="cuda", host_only=False, phys=None,
+                 **opts):
+        self._mesh = _MeshArrays(xyz, tet, nu, face_bc, phys)
         self.opts = default_opts(**opts)
         self.R = R
         self.nt = self._mesh.tet.shape[0]
@@ -423,4 +428,5 @@ def solver_for(workload, R=None, device="cuda", **opts):
     xyz, tet, nu, tags = workload.mesh()
     if "precision" not in opts:
         opts["precision"] = 1 if workload.precision == "mixed" else 0
-    return Solver(xyz, tet, nu, tags, workload.R if R is None else R, device=device, **opts)
+    return Solver(xyz, tet, nu, tags, workload.R if R is None else R, device=device,
+                  phys=workload.physical(), **opts)

@@ -196,6 +196,22 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
     return true;
 }
 
+// The full passes over velocity rows run the point-block kernels, which read
+// every tap of the coupled blocks: the D form, and general meshes (whose a_1
+// stencils couple all 14 neighbours; their records hold the blocks
+// delta_kl A).  The colour sweeps of general meshes with a_1 read the 15
+// taps of A per component instead.
+inline bool dpath(const hhg_ctx* c) { return c->opts.op == 1 || c->mi.general; }
+
+// level-0 system of the context's options: the solution operator for the
+// direct solver, the dense Schur complement only for MINRES preconditioned
+// with it
+bool build_coarse_for(hhg_ctx* c, std::string* err) {
+    const bool direct = c->opts.coarse_solver == 0;
+    const bool schur = c->opts.coarse_solver == 1 && c->opts.coarse_prec == 0;
+    return build_coarse(c->mi, c->H[0], direct, schur, c->opts.op == 1, &c->CH, err);
+}
+
 // Builds the host hierarchy and computes the workspace layout (when ws is
 // NULL only the size).
 hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* opts) {
@@ -207,6 +223,7 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
     if (opts) o = *opts;
     if (!opts_ok(&o, &err)) return fail(c, HHG_EINVAL, err);
     if (!validate_mesh(mesh, &c->mi, &err)) return fail(c, HHG_EINVAL, err);
+    c->mi.lap_blocks = c->mi.general && o.op == 0;
     c->opts = o;
     c->R = R;
     c->L = R - 2;
@@ -219,9 +236,7 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
         for (int32_t t : c->H[l].rif_fine)
             if (t < 0) return fail(c, HHG_EINVAL, "internal error: coarse interface vertex missing");
     }
-    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, c->opts.op == 1, &c->CH, &err))
-        return fail(c, HHG_EINVAL, err);
-    if (c->CH.nd > 4096) return fail(c, HHG_EINVAL, "coarse system larger than 4096 unknowns");
+    if (!build_coarse_for(c, &err)) return fail(c, HHG_EINVAL, err);
     return HHG_OK;
 }
 
@@ -311,7 +326,7 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.val = cv.take<double>(std::max<size_t>(1, C.val.size()));
     d.ainv = cv.take<double>(std::max<size_t>(1, C.ainv.size()));
     d.pdinv = cv.take<double>(C.N);
-    d.sinv = cv.take<double>((size_t)C.N * C.N);
+    d.sinv = cv.take<double>(std::max<size_t>(1, C.sinv.size()));
     d.mass = cv.take<double>(C.N);
     d.vel_node = cv.take<int32_t>(std::max(1, C.nfv));
     d.node_vidx = cv.take<int32_t>(C.N);
@@ -388,6 +403,7 @@ hhg_status upload_stencils(hhg_ctx* c) {
         c->D32[l].macro_nu = a.nu32;
         double msum = 0.0;
         for (int64_t v = 0; v < h.N; ++v) {
+            if (h.node_slot[v] < 0) continue;   // hole
             int sid = h.node_sid[v];
             const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
                                         : &h.st[(size_t)sid * ST_SIZE];
@@ -536,6 +552,7 @@ hhg_status upload_all(hhg_ctx* c) {
     HostLevel& h = c->H[c->L];
     double Nc[4] = {0, 0, 0, 0}, Nfc[4] = {0, 0, 0, 0}, Nf = 0;
     for (int64_t v = 0; v < h.N; ++v) {
+        if (h.node_slot[v] < 0) continue;   // hole
         int X = (int)(v % h.lat[0]), Y = (int)((v / h.lat[0]) % h.lat[1]),
             Z = (int)(v / ((int64_t)h.lat[0] * h.lat[1]));
         int col = (X + Y + Z) & 3;
@@ -545,14 +562,14 @@ hhg_status upload_all(hhg_ctx* c) {
             Nf += 1;
         }
     }
-    const double Nall = (double)h.N;
+    const double Nall = (double)h.nnodes;
     const double vs = c->opts.precision == 1 ? 4.0 : 8.0;
     for (int col = 0; col < 4; ++col) {
         const double nbr = Nc[(col + 1) & 3] + Nc[(col + 3) & 3];
         // the D form's velocity sweep reads the neighbours of every other colour
-        const double vnbr = c->opts.op == 1 ? Nall - Nc[col] : nbr;
+        const double vnbr = dpath(c) ? Nall - Nc[col] : nbr;   // 15-tap rows read every other colour
         c->bytes_vel[col] = vs * 3.0 * (vnbr + 2.0 * Nfc[col]);
-        c->bytes_pres[col] = vs * (nbr + 3.0 * Nc[col]);
+        c->bytes_pres[col] = vs * ((c->mi.general ? Nall - Nc[col] : nbr) + 3.0 * Nc[col]);
     }
     c->bytes_ru = vs * (Nall + 6.0 * Nf);
     c->bytes_bp = vs * (3.0 * Nall + 2.0 * Nall);
@@ -809,7 +826,7 @@ template <typename T, int MODE, bool MIRROR>
 void launch_kx(hhg_ctx* c, LevelDev<T>& v, int ib, const T* x, const T* b, T* y, hipStream_t s,
                double* partials = nullptr) {
     if (!partials) partials = c->partials;
-    if (c->opts.op == 1)
+    if (dpath(c))
         launch_kx_op<T, MODE, MIRROR, true>(v, ib, x, b, y, partials, s);
     else
         launch_kx_op<T, MODE, MIRROR, false>(v, ib, x, b, y, partials, s);
@@ -837,7 +854,7 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     if (MODE == MODE_SCHUR) ops(c, l, 0, 1, 1, 0);
     if (MODE == MODE_APPLY || MODE == MODE_RES)
         launch_kx<T, (MODE == MODE_RES ? MODE_RES : MODE_APPLY), false>(c, v, ib, x, b, y, s);
-    else if (MODE == MODE_ARES && c->opts.op == 1)
+    else if (MODE == MODE_ARES && dpath(c))
         hipLaunchKernelGGL((k_full<T, MODE_ARES, false, false, false, 0, true>), dim3(grid),
                            dim3(TPB), 0, s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
     else
@@ -906,7 +923,7 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
     const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
     // velocity sweeps: a lane per interface vertex and component (Laplace
     // form), four lanes per interface vertex (D form)
-    const int ib = iface_blocks(!vel ? cnt : c->opts.op == 0 ? 3 * cnt : 4 * cnt);
+    const int ib = iface_blocks(!vel ? cnt : c->opts.op == 1 ? 4 * cnt : 3 * cnt);
     const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);
@@ -915,13 +932,20 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
         if (c->opts.op == 1)
             hipLaunchKernelGGL((k_colour<T, true, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
                                T(0), ib);
+        else if (c->mi.general)
+            hipLaunchKernelGGL((k_colour<T, true, false, true>), dim3(grid), dim3(TPB), 0, s, v, col,
+                               x, rhs, T(0), ib);
         else
             hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0),
                                ib);
     } else {
         Timed tm(c, HHG_K_PRES, s, finest, c->bytes_pres[col]);
-        hipLaunchKernelGGL((k_colour<T, false>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
-                           (T)c->opts.omega, ib);
+        if (c->mi.general)
+            hipLaunchKernelGGL((k_colour<T, false, false, true>), dim3(grid), dim3(TPB), 0, s, v, col,
+                               x, rhs, (T)c->opts.omega, ib);
+        else
+            hipLaunchKernelGGL((k_colour<T, false>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
+                               (T)c->opts.omega, ib);
     }
 }
 
@@ -933,18 +957,24 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     // first sweep runs inside the pass that forms f - B^T p, except for the D
     // form, whose point-block sweeps run on their own
     static const int vorder[6] = {1, 2, 3, 2, 1, 0};
-    if (c->opts.op == 1) {
+    if (dpath(c)) {
         full_pass<T, MODE_RU>(c, l, x, b, t, s);
     } else {
         full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
     }
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
-        if (c->opts.op == 1) colour_pass<T>(c, l, 0, true, x, t, s);
+        if (dpath(c)) colour_pass<T>(c, l, 0, true, x, t, s);
         for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
     }
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
-    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
+    // (on general meshes, whose c_l stencils couple all 14 neighbours, on its own)
+    if (c->mi.general) {
+        full_pass<T, MODE_BP>(c, l, x, b, t, s);
+        colour_pass<T>(c, l, 0, false, x, t, s);
+    } else {
+        full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
+    }
     for (int col = 1; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
     if (c->opts.p_sweep == 1)
         for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, false, x, t, s);
@@ -1265,7 +1295,7 @@ int64_t hhg_num_nodes(const hhg_ctx* c, int32_t l) {
     return (c && l >= 0 && l <= c->L) ? c->H[l].N : -1;
 }
 int64_t hhg_num_dofs(const hhg_ctx* c, int32_t l) {
-    return (c && l >= 0 && l <= c->L) ? 3 * c->H[l].nfree + c->H[l].N : -1;
+    return (c && l >= 0 && l <= c->L) ? 3 * c->H[l].nfree + c->H[l].nnodes : -1;
 }
 int64_t hhg_num_interface(const hhg_ctx* c, int32_t l) {
     return (c && l >= 0 && l <= c->L) ? c->H[l].nif : -1;
@@ -1289,6 +1319,10 @@ hhg_status hhg_mass_weights(const hhg_ctx* c, int32_t l, double* m) {
     if (!c || l < 0 || l > c->L || !m) return fail(nullptr, HHG_EINVAL, "bad context, level or array");
     const HostLevel& h = c->H[l];
     for (int64_t v = 0; v < h.N; ++v) {
+        if (h.node_slot[v] < 0) {   // hole
+            m[v] = 0.0;
+            continue;
+        }
         const int sid = h.node_sid[v];
         const double* rec = sid < 0 ? &h.st_vol_global[(size_t)(-sid - 1) * ST_SIZE]
                                     : &h.st[(size_t)sid * ST_SIZE];
@@ -1742,8 +1776,7 @@ hhg_status hhg_set_viscosity(hhg_ctx* c, const double* nu) {
     std::string err;
     for (int l = 0; l <= c->L; ++l)
         if (!compute_stencils(c->mi, &c->H[l], &err)) return fail(c, HHG_EINVAL, err);
-    if (!build_coarse(c->mi, c->H[0], c->opts.coarse_solver == 0, c->opts.op == 1, &c->CH, &err))
-        return fail(c, HHG_EINVAL, err);
+    if (!build_coarse_for(c, &err)) return fail(c, HHG_EINVAL, err);
     if (!c->device) return HHG_OK;
     drop_graphs(c);
     // kernels queued on any stream may still read the old tables: the

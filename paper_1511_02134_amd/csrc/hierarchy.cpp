@@ -119,12 +119,14 @@ std::vector<Incident> incident_tets() {
 
 // Adds the element contributions of one tetrahedron to the stencil record of
 // its vertex a (global direction order).  nu_A multiplies a_1, wC the PSPG
-// weight delta h_T^2 / nu_T is divided by nu_C.
-void add_element(double* rec, const Incident& t, double h, double nuA, double nuC, double nuM,
-                 bool full) {
+// weight delta h_T^2 / nu_T is divided by nu_C.  F is the linear part of the
+// affine map of the macro the tetrahedron lies in (lattice to physical).
+void add_element(double* rec, const Incident& t, const double F[3][3], double h, double nuA,
+                 double nuC, double nuM, bool full) {
     double P[4][3], G[4][3], vol;
     for (int q = 0; q < 4; ++q)
-        for (int c = 0; c < 3; ++c) P[q][c] = t.off[q][c] * h;
+        for (int r = 0; r < 3; ++r)
+            P[q][r] = (F[r][0] * t.off[q][0] + F[r][1] * t.off[q][1] + F[r][2] * t.off[q][2]) * h;
     tet_geom(P, G, &vol);
     const int a = t.a;
     const double h2 = std::pow(vol, 2.0 / 3.0);       // h_T^2, h_T = |T|^(1/3)
@@ -154,6 +156,13 @@ void add_element(double* rec, const Incident& t, double h, double nuA, double nu
         rec[ST_MASS] += vol / 4.0;
         rec[ST_MASSNU] += vol / 4.0 / nuM;
     }
+}
+
+// The coupled blocks of the Laplace form: block (k, l) = delta_kl A.
+void laplace_blocks(double* rec) {
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l)
+            for (int g = 0; g < 15; ++g) rec[ST_A2 + 15 * (3 * k + l) + g] = k == l ? rec[ST_A + g] : 0.0;
 }
 
 void finish_record(double* rec) {
@@ -274,6 +283,30 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
             *err = "viscosity must be finite and positive";
             return false;
         }
+        // affine map to physical space: column ax[q] of F is the physical
+        // edge from path vertex q to q + 1
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) m.F[r][c] = r == c ? 1.0 : 0.0;
+        if (mesh->phys) {
+            for (int q = 0; q < 3; ++q)
+                for (int r = 0; r < 3; ++r) {
+                    const double a = mesh->phys[3 * id[q + 1] + r], b = mesh->phys[3 * id[q] + r];
+                    if (!std::isfinite(a) || !std::isfinite(b)) {
+                        *err = "physical coordinates must be finite";
+                        return false;
+                    }
+                    m.F[r][m.ax[q]] = a - b;
+                }
+            const double (*F)[3] = m.F;
+            const double det = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                               F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                               F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+            if (!(det > 0.0)) {
+                *err = "macro " + std::to_string(t) +
+                       " is degenerate or inverted by its physical coordinates";
+                return false;
+            }
+        }
         m.nu = nu;
         for (int f = 0; f < 4; ++f) {
             int8_t b = mesh->face_bc[4 * t + f];
@@ -291,10 +324,13 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
         }
         out->ext[c] = hi[c];
     }
-    // conforming tiling of the bounding box: every Kuhn tetrahedron has volume
-    // 1/6, faces are shared by exactly two macros (tag 0) or lie on the box
-    // boundary (tag 1 or 2)
-    if ((int64_t)nt != 6LL * out->ext[0] * out->ext[1] * out->ext[2]) {
+    // conforming: faces are shared by exactly two macros (tag 0) or lie on
+    // the boundary (tag 1 or 2).  Without physical coordinates the macros
+    // tile their bounding box (every Kuhn tetrahedron has volume 1/6) and the
+    // boundary faces lie on its planes; with them the box may hold a hole.
+    out->general = mesh->phys != nullptr;
+    out->holes = false;
+    if (!mesh->phys && (int64_t)nt != 6LL * out->ext[0] * out->ext[1] * out->ext[2]) {
         *err = "macro tetrahedra do not tile their bounding box";
         return false;
     }
@@ -338,7 +374,7 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
                         if (V[vv][c] != val) all = false;
                     if (all) onplane = true;
                 }
-            if (!onplane) {
+            if (!onplane && !mesh->phys) {
                 *err = "macro tetrahedra do not tile their bounding box (open face inside)";
                 return false;
             }
@@ -593,13 +629,17 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         L.comp_of_slot.swap(comp);
     }
     L.nfree = 0;
+    L.nnodes = 0;
     for (int64_t v = 0; v < L.N; ++v)
-        if (L.node_slot[v] >= 0 && !L.node_dir[v]) ++L.nfree;
-    for (int64_t v = 0; v < L.N; ++v)
-        if (L.node_slot[v] < 0) {
-            *err = "internal error: lattice node without a macro";
-            return false;
+        if (L.node_slot[v] >= 0) {
+            ++L.nnodes;
+            if (!L.node_dir[v]) ++L.nfree;
         }
+    // lattice points in no macro: a hole of a mesh with physical coordinates
+    if (L.nnodes != L.N && !mi.general) {
+        *err = "internal error: lattice node without a macro";
+        return false;
+    }
     L.vtiles = make_tiles(n, nm, true, block_order);
     L.ctiles = make_tiles(n, nm, false, block_order);
     return compute_stencils(mi, &L, err);
@@ -660,8 +700,10 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
     for (int m = 0; m < nm; ++m) {
         const MacroInfo& M = mi.macros[m];
         std::fill(g.begin(), g.end(), 0.0);
-        for (const Incident& t : inc) add_element(g.data(), t, h, M.nu, M.nu, M.nu, true);
-        if (!clean_axis_only(&g[ST_A], err) || !clean_axis_only(&g[ST_C], err)) return false;
+        for (const Incident& t : inc) add_element(g.data(), t, M.F, h, M.nu, M.nu, M.nu, true);
+        if (!mi.general && (!clean_axis_only(&g[ST_A], err) || !clean_axis_only(&g[ST_C], err)))
+            return false;
+        if (mi.lap_blocks) laplace_blocks(g.data());
         // at an interior vertex the B, B^T, G and G^T centre taps vanish
         // (the gradients of a basis function integrate to zero); clear the
         // round-off so the volume kernels may skip them
@@ -698,13 +740,16 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
                 for (int z = 0; z < 4; ++z)
                     if ((mp.second >> z & 1) && dl[z] <= 0) in = false;
                 if (in) {
-                    double nu = mi.macros[mp.first].nu;
-                    add_element(rec, t, h, nu, nu, nu, true);
+                    const MacroInfo& M = mi.macros[mp.first];
+                    add_element(rec, t, M.F, h, M.nu, M.nu, M.nu, true);
                     break;
                 }
             }
         }
-        if (!clean_axis_only(&rec[ST_A], err) || !clean_axis_only(&rec[ST_C], err)) return false;
+        if (!mi.general &&
+            (!clean_axis_only(&rec[ST_A], err) || !clean_axis_only(&rec[ST_C], err)))
+            return false;
+        if (mi.lap_blocks) laplace_blocks(rec);
         finish_record(rec);
     }
     // one-sided per-macro stencils at unit viscosity for the gradient
@@ -721,7 +766,7 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
                 bool in = true;
                 for (int z = 0; z < 4; ++z)
                     if ((pat >> z & 1) && dl[z] <= 0) in = false;
-                if (in) add_element(g.data(), t, h, 1.0, 1.0, 1.0, false);
+                if (in) add_element(g.data(), t, M.F, h, 1.0, 1.0, 1.0, false);
             }
             double* o = &L.gst[((size_t)m * 16 + pat) * GR_SIZE];
             to_local(M, &g[ST_A], o + GR_A, 1);
@@ -798,33 +843,49 @@ static bool invert_dense(std::vector<double>& M, int n) {
     return true;
 }
 
-bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dform,
+bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schur, bool dform,
                   CoarseHost* out, std::string* err) {
     CoarseHost& C = *out;
-    const int N = (int)L.N;
+    // vertices in lattice order (the lattice points of a hole are skipped)
+    std::vector<int32_t> cidx(L.N, -1);
+    C.node_lat.clear();
+    for (int64_t v = 0; v < L.N; ++v)
+        if (L.node_slot[v] >= 0) {
+            cidx[v] = (int32_t)C.node_lat.size();
+            C.node_lat.push_back((int32_t)v);
+        }
+    const int N = (int)C.node_lat.size();
     C.N = N;
     std::vector<int32_t> vidx(N, -1);
     C.vel_node.clear();
     for (int v = 0; v < N; ++v)
-        if (!L.node_dir[v]) {
+        if (!L.node_dir[C.node_lat[v]]) {
             vidx[v] = (int32_t)C.vel_node.size();
             C.vel_node.push_back(v);
         }
     const int nfv = (int)C.vel_node.size();
     C.nfv = nfv;
     C.nd = 3 * nfv + N;
+    if (C.nd > COARSE_DIRECT_MAX) {
+        *err = "level-0 system too large (" + std::to_string(C.nd) + " unknowns, at most " +
+               std::to_string(COARSE_DIRECT_MAX) + ")";
+        return false;
+    }
     auto rec_of = [&](int v) -> const double* {
-        int sid = L.node_sid[v];
+        int sid = L.node_sid[C.node_lat[v]];
         if (sid < 0) return &L.st_vol_global[(size_t)(-sid - 1) * ST_SIZE];
         return &L.st[(size_t)sid * ST_SIZE];
     };
+    // vertex next to v in direction g, or -1 (outside the box or in a hole,
+    // where every tap of the record is zero)
     auto nbr = [&](int v, int g) -> int {
-        int X = v % L.lat[0], Y = (v / L.lat[0]) % L.lat[1], Z = v / (L.lat[0] * L.lat[1]);
+        const int lv = C.node_lat[v];
+        int X = lv % L.lat[0], Y = (lv / L.lat[0]) % L.lat[1], Z = lv / (L.lat[0] * L.lat[1]);
         X += GDIR[g][0];
         Y += GDIR[g][1];
         Z += GDIR[g][2];
         if (X < 0 || Y < 0 || Z < 0 || X >= L.lat[0] || Y >= L.lat[1] || Z >= L.lat[2]) return -1;
-        return X + L.lat[0] * (Y + L.lat[1] * Z);
+        return cidx[X + L.lat[0] * (Y + L.lat[1] * Z)];
     };
     C.rowptr.assign(1, 0);
     C.col.clear();
@@ -903,7 +964,8 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dfor
     // system (dense); a rank-one term alpha m m^T on the constant pressure
     // makes it SPD when the pressure has a null space.  Its inverse is the
     // pressure block of the block-diagonal MINRES preconditioner.
-    {
+    C.sinv.clear();
+    if (schur) {
         std::vector<double> Bk((size_t)N * nfv), BA((size_t)N * nfv), S((size_t)N * N, 0.0);
         for (int k = 0; k < 3; ++k) {
             std::fill(Bk.begin(), Bk.end(), 0.0);
@@ -1003,11 +1065,6 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dfor
     C.zinv.clear();
     if (direct) {
         const int nd = C.nd;
-        if (nd > COARSE_DIRECT_MAX) {
-            *err = "level-0 system too large for the direct coarse solver (" + std::to_string(nd) +
-                   " unknowns); use the MINRES coarse solver";
-            return false;
-        }
         const int nb = nd + (mi.project ? 1 : 0);
         std::vector<double> K((size_t)nb * nb, 0.0);
         for (int r = 0; r < nd; ++r)
@@ -1037,10 +1094,10 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool dfor
         const double* r = rec_of(v);
         C.pdinv[v] = 1.0 / r[ST_MASSNU];
         C.mass[v] = r[ST_MASS];
-        C.node_slot[v] = L.node_slot[v];
-        auto it = ifidx.find(v);
+        C.node_slot[v] = L.node_slot[C.node_lat[v]];
+        auto it = ifidx.find(C.node_lat[v]);
         if (it == ifidx.end()) {
-            C.node_copy.push_back(L.node_slot[v]);
+            C.node_copy.push_back(C.node_slot[v]);
         } else {
             int t = it->second;
             for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q) C.node_copy.push_back(L.if_copy[q]);

@@ -19,12 +19,22 @@ struct MacroInfo {
     int ax[3];       // Kuhn path axes a, b, c
     double nu;
     int8_t bc[4];    // tag of the face opposite vertex f
+    // linear part of the macro's affine map from lattice to physical
+    // coordinates: a lattice displacement d moves the point by F d (identity
+    // on Kuhn lattices without physical coordinates)
+    double F[3][3];
 };
 
 struct MeshInfo {
     std::vector<MacroInfo> macros;
     int ext[3];      // bounding box extents (macro units), origin at 0
     bool project;    // pressure has a null space (no natural face)
+    bool general;    // physical coordinates given: general 15-point A and C
+    bool holes;      // some lattice points of the bounding box lie in no macro
+    // the coupled velocity blocks of the records (ST_A2, ST_DINV) hold the
+    // Laplace form delta_kl A: general meshes with a_1 run the point-block
+    // velocity kernels, which read every tap
+    bool lap_blocks = false;
 };
 
 bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err);
@@ -67,6 +77,7 @@ struct HostLevel {
     std::vector<int32_t> halo_slot;        // [ncomp - nif] slot of each halo vertex
     std::vector<int32_t> comp_of_slot;     // [len] mirror index of a slot or -1
     int64_t nfree = 0;                     // free velocity vertices
+    int64_t nnodes = 0;                    // vertices (N minus the lattice points of a hole)
 };
 
 // Slot of macro-local vertex (i, j, k): tetrahedral slabs k; slab k (m = n-k)
@@ -97,9 +108,11 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* L, std::string* err);
 void link_levels(HostLevel* coarse, const HostLevel& fine);
 
 // Level-0 system in compact numbering: free velocity vertices x 3, then the
-// pressure of every vertex.
+// pressure of every vertex.  Vertices are numbered in lattice order, skipping
+// the lattice points of a hole.
 struct CoarseHost {
     int32_t nfv = 0, N = 0, nd = 0;
+    std::vector<int32_t> node_lat;  // [N] lattice index of each vertex
     std::vector<int32_t> rowptr, col;
     std::vector<double> val;
     std::vector<double> ainv;       // [nfv][nfv] inverse of the free-free A block
@@ -112,13 +125,14 @@ struct CoarseHost {
     std::vector<double> a2inv;      // D form: [3 nfv][3 nfv] inverse of the coupled
                                     // free velocity block
     std::vector<double> mass;       // [N] int phi_i
-    std::vector<int32_t> vel_node;  // [nfv] lattice node of compact velocity vertex
+    std::vector<int32_t> vel_node;  // [nfv] vertex of each compact velocity vertex
     std::vector<int32_t> node_slot; // [N]
     std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
 };
 constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns of the direct solver
-bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, bool dform,
-                  CoarseHost* out,
-                  std::string* err);
+// direct: the solution operator (zinv); schur: the dense Schur complement
+// inverse (sinv) of the MINRES preconditioner; dform: coupled velocity rows
+bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, bool schur, bool dform,
+                  CoarseHost* out, std::string* err);
 
 }  // namespace hhg

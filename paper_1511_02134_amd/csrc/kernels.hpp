@@ -194,25 +194,27 @@ __device__ __forceinline__ void dform_block(const T* __restrict__ st, const int*
 // mirror (unit-stride runs), the new value goes to every macro copy of the
 // vertex (the ghost exchange fused into the update) and to the mirror.
 // (The D form's interface sweep runs in k_colour, four lanes per vertex.)
-template <typename T, bool VEL>
+// GEN: general meshes, where a_1 and c_l couple all 14 neighbours.
+template <typename T, bool VEL, bool GEN = false>
 __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                              T* __restrict__ x, const T* __restrict__ rhs, T omega,
                                              int fa = 0, int fb = 3) {
+    constexpr int NT = GEN ? 14 : 6;   // neighbour taps of A and C (global order)
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
     const int self = L.if_self[t];
     T* cx = L.cx;
     const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
-    int nb[6];
+    int nb[NT];
 #pragma unroll
-    for (int g = 0; g < 6; ++g) nb[g] = L.if_tap[g * nif + t];
+    for (int g = 0; g < NT; ++g) nb[g] = L.if_tap[g * nif + t];
     if (VEL) {
         // components fa .. fb-1 (the Laplace form updates each on its own)
         for (int f = fa; f < fb; ++f) {
             const T* u = cx + f * cs;
             T acc = T(0);
 #pragma unroll
-            for (int g = 0; g < 6; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
+            for (int g = 0; g < NT; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
             const T v = (rhs[f * len + self] - acc) * st[ST_INVA];
             for (int q = c0; q < c1; ++q) x[f * len + L.if_copy[q]] = v;
             cx[f * cs + t] = v;
@@ -222,7 +224,7 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
         const T p0 = p[t];
         T cp = st[ST_C] * p0;
 #pragma unroll
-        for (int g = 0; g < 6; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
+        for (int g = 0; g < NT; ++g) cp += st[ST_C + 1 + g] * p[nb[g]];
         const T v = p0 + omega * (rhs[3 * len + self] - cp) * st[ST_INVC];
         for (int q = c0; q < c1; ++q) x[3 * len + L.if_copy[q]] = v;
         cx[3 * cs + t] = v;
@@ -231,9 +233,12 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
 
 // Colour sweeps keep the mirror of x current: a level's smoothing starts
 // with a current mirror (refreshed, filled or written by the prolongation).
-template <typename T, bool VEL, bool DOP = false>
+// DOP: point-block velocity sweeps (D form); GEN: sweeps over all 15 taps of
+// a_1 or c_l (general meshes).
+template <typename T, bool VEL, bool DOP = false, bool GEN = false>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
                                                 const T* __restrict__ rhs, T omega, int ib) {
+    static_assert(!(DOP && GEN), "one velocity form per launch");
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     if ((int)blockIdx.x >= ib) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
@@ -260,6 +265,36 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
                 x[f * len + v[0]] = res[f];
                 if (cm >= 0) L.cx[f * cs + cm] = res[f];
             }
+            return;
+        }
+        if (VEL && GEN) {
+            int v[15];
+            nbr_slots(R, i, v);
+            const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[v[0]] : -1;
+            const T ia = st[ST_INVA];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                T* u = x + f * len;
+                T acc = rhs[f * len + v[0]];
+#pragma unroll
+                for (int g = 1; g < 15; ++g) acc -= st[ST_A + g] * u[v[g]];
+                const T val = acc * ia;
+                u[v[0]] = val;
+                if (cm >= 0) L.cx[f * cs + cm] = val;
+            }
+            return;
+        }
+        if (!VEL && GEN) {
+            int v[15];
+            nbr_slots(R, i, v);
+            const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[v[0]] : -1;
+            T* p = x + 3 * len;
+            T cp = T(0);
+#pragma unroll
+            for (int g = 0; g < 15; ++g) cp += st[ST_C + g] * p[v[g]];
+            const T val = p[v[0]] + omega * (rhs[3 * len + v[0]] - cp) * st[ST_INVC];
+            p[v[0]] = val;
+            if (cm >= 0) L.cx[3 * cs + cm] = val;
             return;
         }
         int s[7];
@@ -332,12 +367,13 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
         // many workgroups (on small levels they are the launch's longest path)
         const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = t0 + q / 3, f = q % 3;
         if (t >= tend) return;
-        iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f, f + 1);
+        iface_colour<T, VEL, GEN>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f,
+                                  f + 1);
         return;
     }
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     if (t >= tend) return;
-    iface_colour<T, VEL>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
+    iface_colour<T, VEL, GEN>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -1419,8 +1455,8 @@ __global__ void k_gather(const int* __restrict__ node_slot, size_t N, int nfield
                          const double* __restrict__ x, size_t len, double* __restrict__ nodal) {
     for (size_t v = blockIdx.x * (size_t)blockDim.x + threadIdx.x; v < N;
          v += (size_t)gridDim.x * blockDim.x) {
-        const int s = node_slot[v];
-        for (int f = 0; f < nfields; ++f) nodal[f * N + v] = x[f * len + s];
+        const int s = node_slot[v];   // -1: a lattice point in no macro (hole)
+        for (int f = 0; f < nfields; ++f) nodal[f * N + v] = s >= 0 ? x[f * len + s] : 0.0;
     }
 }
 template <typename T>

@@ -148,3 +148,51 @@ def test_kernel_index_arithmetic_on_host(cid, R, order):
     cfg = W.WORKLOADS[cid].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
     P.Solver(xyz, tet, nu, tags, R, host_only=True, block_order=order).check_layout()
+
+
+def _shell(R=3):
+    cfg = W.WORKLOADS[8].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    return cfg, xyz, tet, nu, tags, cfg.physical()
+
+
+def test_shell_hierarchy_matches_oracle_mesh():
+    """General macro geometry with a hole (the spherical shell): the library's
+    vertices are the oracle's (lattice points of the removed cell are not
+    vertices: mass weight 0, no Dirichlet flag), with equal DoF counts,
+    Dirichlet sets and lumped masses of the physical elements on every level."""
+    R = 4
+    cfg, xyz, tet, nu, tags, phys = _shell(R)
+    s = P.Solver(xyz, tet, nu, tags, R, host_only=True, phys=phys, coarse_solver=1)
+    H = build_hierarchy(xyz, tet, nu, tags, R, phys=phys)
+    for l, lv in enumerate(H.levels):
+        m = s.mass_weights(l)
+        ijk, d = s.node_info(l)
+        present = np.nonzero(m > 0)[0]
+        assert np.array_equal(present, lv.lat)
+        assert s.num_nodes(l) == np.prod(lv.shape) > lv.N
+        assert s.num_dofs(l) == lv.ndofs()
+        assert np.array_equal(ijk[lv.lat], lv.X)
+        assert np.array_equal(d[lv.lat], lv.dirichlet)
+        assert not np.any(d[m == 0])
+        assert np.allclose(m[lv.lat], lv.mass, rtol=1e-13, atol=0)
+    s.check_layout()
+
+
+def test_plan_rejects_bad_physical_coordinates():
+    """Physical coordinates must be finite and keep every macro's orientation;
+    a mesh with a hole needs them (without them the macros must tile their
+    bounding box); the shell's level-0 system fits the MINRES coarse solver."""
+    cfg, xyz, tet, nu, tags, phys = _shell()
+    assert P.plan(xyz, tet, nu, tags, 3, phys=phys, coarse_solver=1) > 0
+    assert "tile" in _expect_einval(xyz, tet, nu, tags)
+    bad = phys.copy()
+    bad[5, 1] = np.inf
+    assert "finite" in _expect_einval(xyz, tet, nu, tags, phys=bad, coarse_solver=1)
+    bad = phys.copy()
+    bad[tet[0, 1]] = 2.0 * phys[tet[0, 0]] - phys[tet[0, 1]]   # turns macro 0 inside out
+    assert "inverted" in _expect_einval(xyz, tet, nu, tags, phys=bad, coarse_solver=1)
+    bxyz, btet, bnu, btags = _mesh()
+    flat = bxyz.copy()
+    flat[:, 2] = 0.0                                      # every macro degenerate
+    _expect_einval(bxyz, btet, bnu, btags, phys=flat)

@@ -1,0 +1,322 @@
+"""GPU parity on a general macro mesh: the spherical shell 0.55 < |x| < 1
+(Section 4.4), 156 affinely mapped macros around a hole.  Its a_1 and c_l
+stencils couple all 14 neighbours, so the general-stencil kernels run (15-tap
+colour sweeps, point-block full passes, B u - g and its pressure sweep in
+separate launches) and the level-0 system is solved by MINRES.
+
+The library's nodal arrays live on the lattice of the bounding box; the
+oracle numbers only the vertices (its lattice indices lv.lat), so every
+comparison maps between the two.  Small levels are compared with the oracle
+on every vertex; the full-size workload (5 refinements) on sampled rows of
+the oracle's row evaluator and on properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import UMG, build_hierarchy
+from oracle.rows import stokes_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+COARSE = {"coarse_solver": 1, "coarse_maxit": 4000}
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+class Shell:
+    """Library solver and oracle hierarchy of the shell, with the maps between
+    the library's lattice arrays and the oracle's vertex arrays."""
+
+    def __init__(self, cid, R, oracle=True, **opts):
+        import paper_1511_02134_amd as P
+        self.cfg = W.WORKLOADS[cid].with_R(R)
+        xyz, tet, nu, tags = self.cfg.mesh()
+        self.mesh = (xyz, tet, nu, tags)
+        self.phys = self.cfg.physical()
+        o = dict(COARSE)
+        o.update(opts)
+        _announce(f"shell config {cid} R={R} opts={o}")
+        self.s = P.Solver(xyz, tet, nu, tags, R, phys=self.phys, **o)
+        if oracle:
+            H = build_hierarchy(xyz, tet, nu, tags, R, phys=self.phys)
+            self.umg = UMG(H, nu1=self.s.opts.nu1, nu2=self.s.opts.nu2,
+                           variable=bool(self.s.opts.cycle))
+
+    def to_lat(self, x, l, fill=0.0):
+        lv = self.umg.H.levels[l]
+        out = np.full((x.shape[0], self.s.num_nodes(l)), fill)
+        out[:, lv.lat] = x
+        return out
+
+    def put(self, x, l=None):
+        """Oracle vertex array -> library vector (hole points NaN: scatter
+        must ignore them)."""
+        l = self.umg.L if l is None else l
+        return self.s.scatter(_dev(self.to_lat(x, l, np.nan)), l)
+
+    def get(self, xd, l=None):
+        l = self.umg.L if l is None else l
+        return _host(self.s.gather(xd, l))[:, self.umg.H.levels[l].lat]
+
+
+def _rand_state(lv, seed, dirichlet=None):
+    x = np.random.default_rng(seed).normal(size=(4, lv.N))
+    x[:3, lv.dirichlet] = 0.0 if dirichlet is None else dirichlet[:, lv.dirichlet]
+    return x
+
+
+@pytest.fixture(scope="module")
+def shell4():
+    return Shell(8, 4)
+
+
+def test_shell_layout_scatter_gather(shell4):
+    sh = shell4
+    for l, lv in enumerate(sh.umg.H.levels):
+        x = _rand_state(lv, 10 + l)
+        xi = sh.put(x, l)
+        g = _host(sh.s.gather(xi, l))
+        assert np.array_equal(g[:, lv.lat], x)
+        hole = np.ones(g.shape[1], dtype=bool)
+        hole[lv.lat] = False
+        assert hole.any() and np.all(g[:, hole] == 0.0)
+        assert not torch.isnan(xi).any()
+        y = xi.clone()
+        sh.s.exchange(y, l)
+        assert torch.equal(y, xi)
+
+
+def test_shell_apply_matches_oracle(shell4):
+    sh = shell4
+    for l, lv in enumerate(sh.umg.H.levels):
+        x = np.random.default_rng(20 + l).normal(size=(4, lv.N))
+        y = sh.get(sh.s.apply(sh.put(x, l), l), l)
+        err = _relerr(y, sh.umg.apply(l, x))
+        _announce(f"K x level {l}: max rel. difference {err:.2e}")
+        assert err < 1e-13, l
+
+
+def test_shell_rhs_and_residual_match_oracle(shell4):
+    sh = shell4
+    umg = sh.umg
+    lv = umg.H.finest
+    f = np.random.default_rng(4).normal(size=(3, lv.N))
+    b = sh.get(sh.s.rhs(sh.put(f)))
+    bo = umg.rhs(f)
+    assert _relerr(b, bo) < 1e-13
+    x = _rand_state(lv, 5, np.random.default_rng(6).normal(size=(3, lv.N)))
+    r, nrm = sh.s.residual(sh.put(x), sh.put(bo))
+    ro = umg.residual(umg.L, x, bo)
+    assert _relerr(sh.get(r), ro) < 1e-13
+    assert nrm == pytest.approx(umg.norm(umg.L, ro), rel=1e-13)
+
+
+def test_shell_transfers_match_oracle(shell4):
+    sh = shell4
+    umg = sh.umg
+    for l in range(1, umg.L + 1):
+        lf, lc = umg.H.levels[l], umg.H.levels[l - 1]
+        r = _rand_state(lf, 30 + l)
+        bc = sh.get(sh.s.restrict(sh.put(r, l), l), l - 1)
+        assert _relerr(bc, umg.restrict(l, r)) < 1e-14
+        e = _rand_state(lc, 40 + l)
+        x = _rand_state(lf, 50 + l)
+        xd = sh.put(x, l)
+        sh.s.prolong_add(sh.put(e, l - 1), xd, l)
+        assert _relerr(sh.get(xd, l), x + umg.prolong(l, e)) < 1e-14
+
+
+def test_shell_uzawa_steps_match_oracle(shell4):
+    sh = shell4
+    umg = sh.umg
+    for l in (0, 1, umg.L):
+        lv = umg.H.levels[l]
+        x = _rand_state(lv, 60 + l, np.random.default_rng(7).normal(size=(3, lv.N)))
+        b = _rand_state(lv, 70 + l)
+        xd, bd = sh.put(x, l), sh.put(b, l)
+        sh.s.smooth(xd, bd, 2, l)
+        xo = x.copy()
+        for _ in range(2):
+            umg.uzawa(l, xo, b)
+        err = _relerr(sh.get(xd, l), xo)
+        _announce(f"Uzawa steps level {l}: max rel. difference {err:.2e}")
+        assert err < 1e-12, l
+
+
+def test_shell_coarse_minres_matches_oracle(shell4):
+    """MINRES with the lumped-mass pressure preconditioner on the 5788
+    unknowns of the shell's level 0 reaches the oracle's direct solution."""
+    sh = shell4
+    umg = sh.umg
+    lv = umg.H.levels[0]
+    x = _rand_state(lv, 80)
+    b = umg.apply(0, x)
+    xg, it, rel = sh.s.coarse_solve(sh.put(b, 0))
+    _announce(f"coarse MINRES on the shell: {it} iterations, preconditioned residual {rel:.1e}")
+    assert rel < 1e-13 and it < COARSE["coarse_maxit"]
+    assert _relerr(sh.get(xg, 0), umg.coarse_solve(b)) < 1e-10
+
+
+@pytest.mark.parametrize("cycle", [0, 1])
+def test_shell_cycles_match_oracle(cycle):
+    """V(3,3) and the variable V-cycle iterate by iterate from the paper's
+    setting (random start, f = 0, homogeneous Dirichlet data) at 3 levels."""
+    sh = Shell(7, 4, cycle=cycle)
+    umg = sh.umg
+    lv = umg.H.finest
+    x0 = _rand_state(lv, 90)
+    bo = np.zeros((4, lv.N))
+    xd, bd = sh.put(x0), sh.put(bo)
+    xo = x0.copy()
+    r0 = umg.norm(umg.L, umg.residual(umg.L, x0, bo))
+    for k in range(3):
+        sh.s.vcycle(xd, bd)
+        xo = umg.cycle(xo, bo)
+        xg = sh.get(xd)
+        d = xg - xo
+        d[:3, lv.dirichlet] = 0.0
+        rel = umg.norm(umg.L, umg.apply(umg.L, d)) / r0
+        _announce(f"cycle {k}: ||K (x_gpu - x_oracle)|| / ||r0|| = {rel:.2e}")
+        assert rel <= 1e-9, k
+        assert _relerr(xg, xo) < 1e-8, k
+
+
+def test_shell_solve_matches_oracle_at_three_refinements():
+    sh = Shell(8, 3, cycle=1)
+    umg = sh.umg
+    lv = umg.H.finest
+    bo = umg.rhs(sh.cfg.forcing_field()[:, lv.lat])
+    x0 = np.zeros((4, lv.N))
+    x0[:3] = sh.cfg.dirichlet_field()[:, lv.lat]
+    x0[:3, lv.free] = 0.0
+    xd = sh.put(x0)
+    info = sh.s.solve(xd, sh.put(bo), rtol=1e-8, max_cycles=80)
+    xo, hist = umg.solve(x0.copy(), bo, rtol=1e-8, max_cycles=80)
+    _announce(f"shell R=3: {info['cycles']} cycles (oracle {len(hist) - 1}), "
+              f"rho_mean {info['rho_mean']:.3f}")
+    assert info["status"] == 0
+    assert abs(info["cycles"] - (len(hist) - 1)) <= 1
+    n = min(len(hist), len(info["res_hist"]))
+    assert np.abs(np.array(info["res_hist"][:n]) - np.array(hist[:n])).max() <= 1e-9 * hist[0]
+    d = sh.get(xd) - xo
+    d[:3, lv.dirichlet] = 0.0
+    assert umg.norm(umg.L, umg.apply(umg.L, d)) <= 1e-8 * hist[0]
+
+
+def _quadratic(x):
+    """A Stokes pair with div u = 0: u = (y^2, z^2, x^2), p = x + y + z, so
+    -Lap u + grad p = (-1, -1, -1)."""
+    return (np.stack([x[:, 1] ** 2, x[:, 2] ** 2, x[:, 0] ** 2]), x.sum(axis=1),
+            np.full((3, x.shape[0]), -1.0))
+
+
+def test_shell_discretisation_error_is_second_order():
+    """Solves to 1e-10 at 3, 4 and 5 refinements with the exact Dirichlet
+    data of a quadratic Stokes pair: the nodal velocity error falls like h^2
+    (the polyhedral domain is the same on every level) and the pressure error
+    at least like h."""
+    import paper_1511_02134_amd as P
+    cfg = W.WORKLOADS[8]
+    xyz, tet, nu, tags = cfg.mesh()
+    phys = cfg.physical()
+    eu, ep = [], []
+    for R in (3, 4, 5):
+        s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1, **COARSE)
+        X = W.refined_points(xyz, tet, phys, R)
+        present = ~np.isnan(X[:, 0])
+        Xs = np.where(present[:, None], X, 0.0)
+        u, p, f = _quadratic(Xs)
+        _announce(f"quadratic pair, R={R}")
+        b = s.rhs(s.scatter(_dev(f)))
+        _, d = s.node_info()
+        x0 = np.zeros((4, X.shape[0]))
+        x0[:3, d.astype(bool)] = u[:, d.astype(bool)]
+        xd = s.scatter(_dev(x0))
+        info = s.solve(xd, b, rtol=1e-10, max_cycles=120)
+        assert info["status"] == 0
+        xg = _host(s.gather(xd))
+        m = s.mass_weights()
+        eu.append(np.abs(xg[:3, present] - u[:, present]).max())
+        pe = xg[3, present] - p[present]
+        pe -= (m[present] @ pe) / m[present].sum()
+        ep.append(np.sqrt(m[present] @ pe ** 2))
+        _announce(f"R={R}: {info['cycles']} cycles, rho_mean {info['rho_mean']:.3f}, "
+                  f"max velocity error {eu[-1]:.3e}, pressure L2 error {ep[-1]:.3e}")
+    assert eu[0] / eu[1] > 3.3 and eu[1] / eu[2] > 3.5, eu
+    assert ep[0] / ep[1] > 2.0 and ep[1] / ep[2] > 2.0, ep
+
+
+def _sample(lv_shape, present, rng, m=300):
+    idx = np.nonzero(present)[0]
+    sel = rng.choice(idx, size=m, replace=False)
+    nx, ny = lv_shape[0], lv_shape[1]
+    return np.stack([sel % nx, (sel // nx) % ny, sel // (nx * ny)], axis=1), sel
+
+
+def test_shell_full_size_rows_and_solve():
+    """Five refinements (the shell workload itself, 3.9 million unknowns):
+    K x at sampled vertices of every class against the oracle's rows, then
+    the paper's setting (f = 0, random start) solved to a relative residual of
+    1e-8, and the final residual checked against the oracle's rows."""
+    import paper_1511_02134_amd as P
+    cfg = W.WORKLOADS[7]
+    xyz, tet, nu, tags = cfg.mesh()
+    phys = cfg.physical()
+    R = cfg.R
+    s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1, coarse_solver=1)
+    _announce(f"shell full size R={R}: {s.num_dofs()} unknowns")
+    m = s.mass_weights()
+    present = m > 0
+    ijk, d = s.node_info()
+    shape = (ijk[:, 0].max() + 1, ijk[:, 1].max() + 1, ijk[:, 2].max() + 1)
+    rng = np.random.default_rng(71)
+    verts, sel = _sample(shape, present, rng)
+    # add vertices on both boundaries and on macro faces (interface vertices)
+    bnd = np.nonzero(present & (d == 1))[0]
+    extra = rng.choice(bnd, size=100, replace=False)
+    verts = np.concatenate([verts, ijk[extra]])
+    sel = np.concatenate([sel, extra])
+    x = rng.normal(size=(4, s.num_nodes()))
+    x[:, ~present] = 0.0
+    x[:3, d == 1] = 0.0
+    y = _host(s.gather(s.apply(s.scatter(_dev(x)))))
+    _, kx, dirich, scale = stokes_rows(xyz, tet, nu, tags, R, verts, x,
+                                       np.zeros((3, x.shape[1])), phys=phys)
+    assert np.array_equal(dirich, d[sel] == 1)
+    err = np.abs(y[:, sel] - kx).max() / scale.max()
+    _announce(f"K x rows: max difference / row scale {err:.2e}")
+    assert np.all(np.abs(y[:, sel] - kx) <= 1e-13 * scale + 1e-300)
+    # the paper's setting
+    x0 = rng.normal(size=(4, s.num_nodes()))
+    x0[:3, d == 1] = 0.0
+    xd = s.scatter(_dev(x0))
+    bd = s.scatter(_dev(np.zeros((4, s.num_nodes()))))
+    info = s.solve(xd, bd, rtol=1e-8, max_cycles=100)
+    _announce(f"solve: {info['cycles']} cycles, rho_mean {info['rho_mean']:.3f}, "
+              f"{info['t_solve_ms']:.1f} ms")
+    assert info["status"] == 0 and info["rel_res"] <= 1e-8
+    xs = _host(s.gather(xd))
+    _, kx, _, scale = stokes_rows(xyz, tet, nu, tags, R, verts, xs,
+                                  np.zeros((3, x.shape[1])), phys=phys)
+    r, nrm = s.residual(xd, bd)
+    rg = _host(s.gather(r))
+    assert np.all(np.abs(rg[:, sel] + kx) <= 1e-13 * scale + 1e-300)
+    assert nrm <= 1e-8 * info["r0"] * (1 + 1e-12)

@@ -26,6 +26,15 @@ tetrahedra, Section 4 and Table "iteration numbers and time-to-solution"):
      observation viscosity seed 52, mixed precision forward + adjoint
   6  unit cube, 6 macros, R=7, the analytic solution of the efficiency study
      (Section 5) with its forcing and Dirichlet data, fp64 full multigrid
+  7  spherical shell 0.55 < |x| < 1 (Section 4.4), 156 macros (the hollow cube
+     [0,3]^3 minus its central cell, mapped radially), R=5, f=0, homogeneous
+     Dirichlet data on both spheres, random start (the paper's setting), fp64
+  8  the same shell, R=4, the analytic solution of the efficiency study as
+     forcing and Dirichlet data (a manufactured solution on the shell)
+
+For the shell the nodal arrays live on the lattice of the bounding box of the
+hollow cube; lattice points in the removed central cell are not vertices
+(NaN coordinates; their values are ignored).
 """
 from __future__ import annotations
 
@@ -84,6 +93,96 @@ def face_tags(xyz, tet, a: int, natural_x: float | None = None):
                     else:
                         tags[t, f] = FACE_DIRICHLET
     return tags
+
+
+def hollow_cube_mesh(m: int = 3):
+    """Macro mesh of the hollow cube [0,m]^3 minus its central unit cell (m odd):
+    every other unit cell is split into the 6 Kuhn tetrahedra of box_mesh, in
+    the same path order.  These are the lattice (topological) coordinates of
+    the spherical shell; shell_coordinates gives the physical ones.
+
+    Returns (xyz [nv,3] float64 integer-valued, tet [nt,4] int32)."""
+    c0 = m // 2
+    nx = m + 1
+    pts = np.array([(x, y, z) for z in range(nx) for y in range(nx) for x in range(nx)],
+                   dtype=np.float64)
+
+    def vid(x, y, z):
+        return x + nx * (y + nx * z)
+
+    tets = []
+    for cz in range(m):
+        for cy in range(m):
+            for cx in range(m):
+                if (cx, cy, cz) == (c0, c0, c0):
+                    continue
+                for perm in itertools.permutations((0, 1, 2)):
+                    v = np.array([cx, cy, cz])
+                    path = [vid(*v)]
+                    for ax in perm:
+                        v = v.copy()
+                        v[ax] += 1
+                        path.append(vid(*v))
+                    tets.append(path)
+    tet = np.asarray(tets, dtype=np.int32)
+    used = np.unique(tet)
+    remap = -np.ones(pts.shape[0], dtype=np.int64)
+    remap[used] = np.arange(used.shape[0])
+    return pts[used], remap[tet].astype(np.int32)
+
+
+def shell_coordinates(xyz, m: int = 3, r_in: float = 0.55, r_out: float = 1.0):
+    """Physical coordinates of the hollow-cube macro vertices on the spherical
+    shell r_in < |x| < r_out (Section 4.4 uses 0.55 < |x| < 1): a vertex on the
+    surface of the removed central cell goes radially to |x| = r_in, a vertex
+    on the outer surface to |x| = r_out (every macro vertex lies on one of the
+    two, for m = 3)."""
+    c = xyz - m / 2.0
+    mx = np.abs(c).max(axis=1)
+    r = np.where(np.isclose(mx, 0.5), r_in, r_out)
+    if not np.all(np.isclose(mx, 0.5) | np.isclose(mx, m / 2.0)):
+        raise ValueError("every macro vertex must lie on the inner or the outer surface")
+    return c / np.linalg.norm(c, axis=1, keepdims=True) * r[:, None]
+
+
+def boundary_face_tags(tet):
+    """Tag 1 (Dirichlet) on every face that belongs to one tetrahedron only, 0
+    on faces shared by two."""
+    nt = tet.shape[0]
+    count = {}
+    for t in range(nt):
+        for f in range(4):
+            key = tuple(sorted(np.delete(tet[t], f).tolist()))
+            count[key] = count.get(key, 0) + 1
+    tags = np.zeros((nt, 4), dtype=np.int8)
+    for t in range(nt):
+        for f in range(4):
+            key = tuple(sorted(np.delete(tet[t], f).tolist()))
+            if count[key] == 1:
+                tags[t, f] = FACE_DIRICHLET
+    return tags
+
+
+def refined_points(xyz, tet, phys, R: int):
+    """Physical coordinates [N,3] of the vertices of the R times uniformly
+    refined macro mesh, on the lattice of the bounding box of xyz (index X +
+    nx (Y + ny Z) at spacing 2^-R); lattice points outside every macro are NaN.
+    Each macro carries its vertices affinely: a refined vertex with barycentric
+    coordinates l in macro t sits at sum_q l_q phys[tet[t, q]]."""
+    n = 1 << R
+    lo = xyz.min(axis=0)
+    ext = ((xyz.max(axis=0) - lo) * n + 1).astype(np.int64)
+    out = np.full((int(ext[0] * ext[1] * ext[2]), 3), np.nan)
+    # barycentric coordinates of the refined vertices of one macro, (i, j, k, l)/n
+    ijk = np.array([(a, b, c) for a in range(n + 1) for b in range(n + 1 - a)
+                    for c in range(n + 1 - a - b)], dtype=np.int64)
+    lam = np.concatenate([n - ijk.sum(axis=1, keepdims=True), ijk], axis=1) / n    # [nv,4]
+    for t in range(tet.shape[0]):
+        L = xyz[tet[t]]                                    # [4,3]
+        X = np.rint((lam @ L - lo) * n).astype(np.int64)   # lattice coordinates
+        idx = X[:, 0] + ext[0] * (X[:, 1] + ext[1] * X[:, 2])
+        out[idx] = lam @ phys[tet[t]]
+    return out
 
 
 def lattice_shape(a: int, R: int):
@@ -238,10 +337,14 @@ class Workload:
     noise_sigma: float = 0.0
     inflow: bool = False
     solution: str | None = None     # "tme": the analytic solution of the efficiency study
+    kind: str = "box"               # "box" | "shell" (the spherical shell of Section 4.4)
     extra: dict = field(default_factory=dict)
 
     # -- inputs ----------------------------------------------------------
     def mesh(self):
+        if self.kind == "shell":
+            xyz, tet = hollow_cube_mesh(3)
+            return xyz, tet, np.ones(tet.shape[0]), boundary_face_tags(tet)
         xyz, tet = box_mesh(self.a)
         tags = face_tags(xyz, tet, self.a, self.natural_x)
         if self.nu_range is None:
@@ -256,7 +359,17 @@ class Workload:
         d["R"] = R
         return Workload(**d)
 
+    def physical(self):
+        """Physical coordinates of the macro vertices (None: the lattice ones)."""
+        if self.kind == "shell":
+            xyz, _ = hollow_cube_mesh(3)
+            return shell_coordinates(xyz, 3)
+        return None
+
     def points(self):
+        if self.kind == "shell":
+            xyz, tet, _, _ = self.mesh()
+            return refined_points(xyz, tet, self.physical(), self.R)
         return lattice_points(self.a, self.R)
 
     def forcing_field(self):
@@ -271,7 +384,7 @@ class Workload:
         if self.forcing == "zero":
             return np.zeros((3, x.shape[0]))
         if self.forcing == "tme":
-            return tme_forcing(x)
+            return np.nan_to_num(tme_forcing(x))
         raise ValueError(self.forcing)
 
     def dirichlet_field(self):
@@ -281,7 +394,7 @@ class Workload:
         if self.inflow:
             return inflow_profile(x)
         if self.solution == "tme":
-            return tme_velocity(x)
+            return np.nan_to_num(tme_velocity(x))
         return np.zeros((3, x.shape[0]))
 
     def exact_solution(self):
@@ -306,4 +419,7 @@ WORKLOADS = {
     5: Workload("channel4-R7-adjoint-mixed", a=4, R=7, precision="mixed", natural_x=4.0,
                 nu_range=(0.5, 2.0), nu_seed=5, nu_obs_seed=52, forcing="zero", inflow=True),
     6: Workload("unit-cube-tme-R7-fp64", a=1, R=7, precision="fp64", forcing="tme", solution="tme"),
+    7: Workload("shell-R5-fp64", a=3, R=5, precision="fp64", forcing="zero", kind="shell"),
+    8: Workload("shell-tme-R4-fp64", a=3, R=4, precision="fp64", forcing="tme", solution="tme",
+                kind="shell"),
 }
