@@ -114,6 +114,8 @@ struct hhg_ctx {
     double* kpart = nullptr;       // partial sums of the vector kernels
     double* kscal = nullptr;       // device scalars of the Krylov solvers
     double* gpart = nullptr;       // gradient partials
+    double* gj_col = nullptr;      // set-up of the direct coarse solver: elimination factors
+    GJState* gj_state = nullptr;   // and pivot state
     std::vector<double> inv_mass;  // 1 / sum_i m_i per level
     // operator evaluations per level (A, B, C, M) since the last reset; a
     // colour sweep counts a quarter of its operator (Section 4.2)
@@ -334,7 +336,13 @@ size_t layout(hhg_ctx* c, char* ws) {
     d.node_cptr = cv.take<int32_t>(C.node_cptr.size());
     d.node_copy = cv.take<int32_t>(C.node_copy.size());
     d.gscratch = cv.take<double>((size_t)8 * C.nd);
-    d.zinv = cv.take<double>(std::max<size_t>(1, C.zinv.size()));
+    // direct solver: the bordered matrix, inverted in place at set-up, its
+    // column permutation, the elimination factors and the pivot state
+    d.nb = C.nb;
+    d.zinv = cv.take<double>(std::max<size_t>(1, C.kb.size()));
+    d.zperm = cv.take<int32_t>(std::max(1, C.nb));
+    c->gj_col = cv.take<double>(std::max(1, C.nb));
+    c->gj_state = cv.take<GJState>(1);
     d.a2inv = cv.take<double>(std::max<size_t>(1, C.a2inv.size()));
     d.coupled = C.a2inv.empty() ? 0 : 1;
     return cv.off + 256;
@@ -380,6 +388,40 @@ hhg_status upload(hhg_ctx* c, T* dst, const void* src, size_t count) {
     return HHG_OK;
 }
 
+// Direct level-0 solver: uploads the bordered matrix and inverts it in place
+// on the device (Gauss-Jordan with partial pivoting, three launches per
+// column); fails when a pivot vanishes relative to the largest entry.
+hhg_status coarse_direct_setup(hhg_ctx* c) {
+    CoarseHost& C = c->CH;
+    const int nb = C.nb;
+    if (nb == 0) return HHG_OK;
+    hhg_status s;
+    if ((s = upload<double>(c, c->cd.zinv, C.kb.data(), C.kb.size())) != HHG_OK) return s;
+    std::vector<int32_t> perm(nb);
+    for (int i = 0; i < nb; ++i) perm[i] = i;
+    if ((s = upload<int32_t>(c, (int32_t*)c->cd.zperm, perm.data(), perm.size())) != HHG_OK) return s;
+    double scale = 0.0;
+    for (double v : C.kb) scale = std::max(scale, std::fabs(v));
+    GJState st0{0, 0, 1.0, 0.0, 1e-13 * scale};
+    if ((s = upload<GJState>(c, c->gj_state, &st0, 1)) != HHG_OK) return s;
+    const hipStream_t st = nullptr;
+    double* M = c->cd.zinv;
+    const dim3 ugrid((nb + TPB - 1) / TPB, nb);
+    for (int col = 0; col < nb; ++col) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, st, M, nb, col,
+                           (int*)c->cd.zperm, c->gj_state);
+        hipLaunchKernelGGL(k_gj_swap, dim3((nb + TPB - 1) / TPB), dim3(TPB), 0, st, M, nb, col,
+                           c->gj_state, c->gj_col);
+        hipLaunchKernelGGL(k_gj_update, ugrid, dim3(TPB), 0, st, M, nb, col, c->gj_col);
+    }
+    HIPCHECK(c, hipGetLastError());
+    GJState st1;
+    HIPCHECK(c, hipMemcpy(&st1, c->gj_state, sizeof(GJState), hipMemcpyDeviceToHost));
+    if (st1.bad) return fail(c, HHG_EINVAL, "level-0 system is singular");
+    std::vector<double>().swap(C.kb);   // the device holds the inverse
+    return HHG_OK;
+}
+
 hhg_status upload_stencils(hhg_ctx* c) {
     for (int l = 0; l <= c->L; ++l) {
         HostLevel& h = c->H[l];
@@ -420,8 +462,7 @@ hhg_status upload_stencils(hhg_ctx* c) {
         return s;
     if ((s = upload<double>(c, (double*)c->cd.sinv, C.sinv.data(), C.sinv.size())) != HHG_OK)
         return s;
-    if ((s = upload<double>(c, (double*)c->cd.zinv, C.zinv.data(), C.zinv.size())) != HHG_OK)
-        return s;
+    if ((s = coarse_direct_setup(c)) != HHG_OK) return s;
     if (!C.a2inv.empty() &&
         (s = upload<double>(c, (double*)c->cd.a2inv, C.a2inv.data(), C.a2inv.size())) != HHG_OK)
         return s;
@@ -534,6 +575,13 @@ hhg_status upload_all(hhg_ctx* c) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)used) != hipSuccess)
                 return fail(c, HHG_EDEVICE, "cannot raise the LDS limit of the coarse kernel");
         }
+        const size_t dl = (size_t)C.nb * sizeof(double);   // k_coarse_direct's staged b0
+        if (dl > 65536 &&
+            (hipFuncSetAttribute((const void*)k_coarse_direct<double>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl) != hipSuccess ||
+             hipFuncSetAttribute((const void*)k_coarse_direct<float>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)dl) != hipSuccess))
+            return fail(c, HHG_EDEVICE, "cannot raise the LDS limit of the direct coarse kernel");
     }
     if ((s = upload_stencils(c)) != HHG_OK) return s;
     {
@@ -1028,7 +1076,7 @@ void coarse_solve(hhg_ctx* c, const T* b, T* x, hipStream_t s) {
     if (c->opts.coarse_solver == 0) {
         const int rows = (c->cd.nd + TPB / 64 - 1) / (TPB / 64);
         const int grid = std::max(rows, (c->cd.N + TPB - 1) / TPB);
-        hipLaunchKernelGGL(k_coarse_direct<T>, dim3(grid), dim3(TPB), c->cd.nd * sizeof(double), s,
+        hipLaunchKernelGGL(k_coarse_direct<T>, dim3(grid), dim3(TPB), c->cd.nb * sizeof(double), s,
                            c->cd, b, len, x, len, c->scal + 8);
         return;
     }

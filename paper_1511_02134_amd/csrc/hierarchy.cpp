@@ -1058,15 +1058,18 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
         }
         C.a2inv.swap(K);
     }
-    // direct solver: the inverse of K_0 bordered by the constraint
-    // sum_i m_i p_i = 0 (only when the pressure has a null space); its leading
-    // nd x nd block maps any right-hand side to the mean-zero solution of the
-    // consistent part of it
-    C.zinv.clear();
+    // direct solver: K_0 bordered by the constraint sum_i m_i p_i = 0 (only
+    // when the pressure has a null space); the leading nd x nd block of its
+    // inverse maps any right-hand side to the mean-zero solution of the
+    // consistent part of it.  The device inverts it (set-up).
+    C.kb.clear();
+    C.nb = 0;
     if (direct) {
         const int nd = C.nd;
         const int nb = nd + (mi.project ? 1 : 0);
-        std::vector<double> K((size_t)nb * nb, 0.0);
+        C.nb = nb;
+        C.kb.assign((size_t)nb * nb, 0.0);
+        std::vector<double>& K = C.kb;
         for (int r = 0; r < nd; ++r)
             for (int e = C.rowptr[r]; e < C.rowptr[r + 1]; ++e) K[(size_t)r * nb + C.col[e]] += C.val[e];
         if (mi.project)
@@ -1075,13 +1078,6 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
                 K[(size_t)(3 * nfv + v) * nb + nd] = m;
                 K[(size_t)nd * nb + 3 * nfv + v] = m;
             }
-        if (!invert_dense(K, nb)) {
-            *err = "level-0 system is singular";
-            return false;
-        }
-        C.zinv.resize((size_t)nd * nd);
-        for (int r = 0; r < nd; ++r)
-            for (int q = 0; q < nd; ++q) C.zinv[(size_t)r * nd + q] = K[(size_t)r * nb + q];
     }
     C.pdinv.resize(N);
     C.mass.resize(N);

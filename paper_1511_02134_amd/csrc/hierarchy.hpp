@@ -120,8 +120,11 @@ struct CoarseHost {
     std::vector<double> sinv;       // [N][N] inverse of the Schur complement
                                     // B A^-1 B^T + C (+ a rank-one term on the
                                     // pressure null space), symmetric
-    std::vector<double> zinv;       // [nd][nd] solution operator of the level-0
-                                    // system with the mean constraint (direct solver)
+    // direct solver: the level-0 matrix bordered by the mean constraint
+    // sum_i m_i p_i = 0 when the pressure has a null space, [nb][nb] row
+    // major, nb = nd (+ 1); the device inverts it at set-up
+    int32_t nb = 0;
+    std::vector<double> kb;
     std::vector<double> a2inv;      // D form: [3 nfv][3 nfv] inverse of the coupled
                                     // free velocity block
     std::vector<double> mass;       // [N] int phi_i
@@ -129,8 +132,8 @@ struct CoarseHost {
     std::vector<int32_t> node_slot; // [N]
     std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
 };
-constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns of the direct solver
-// direct: the solution operator (zinv); schur: the dense Schur complement
+constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns
+// direct: the bordered matrix (kb); schur: the dense Schur complement
 // inverse (sinv) of the MINRES preconditioner; dform: coupled velocity rows
 bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, bool schur, bool dform,
                   CoarseHost* out, std::string* err);

@@ -1496,7 +1496,10 @@ struct CoarseDev {
     const int* node_cptr;   // [N+1]
     const int* node_copy;
     double* gscratch;       // 8 * nd doubles when the vectors do not fit in LDS
-    const double* zinv;     // [nd][nd] solution operator (direct solver)
+    double* zinv;           // [nb][nb] inverse of the bordered level-0 matrix up to
+                            // the column permutation zperm (direct solver)
+    const int* zperm;       // [nb]
+    int nb;
     const double* a2inv;    // D form: [3 nfv][3 nfv] inverse of the coupled velocity block
     int coupled;            // 1: the velocity block couples the components (D form)
     // what lives in the dynamic LDS (in this order): vectors, CSR (val, then
@@ -1733,31 +1736,124 @@ __global__ void __launch_bounds__(CTPB) k_coarse(CoarseDev cd, const T* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Set-up of the direct level-0 solver: in-place Gauss-Jordan inversion of the
+// bordered level-0 matrix M [nb][nb] with partial pivoting, one pivot column
+// per three launches.  Step c swaps the pivot row into row c, scales it by
+// the pivot and eliminates column c from every other row; the row swaps
+// leave the inverse with its columns permuted (perm), which the solve undoes
+// by reading the right-hand side through perm.
+// ---------------------------------------------------------------------------
+struct GJState {
+    int piv, bad;
+    double p;     // pivot value
+    double acc;   // M[c][c] before the swap
+    double tiny;  // pivots at or below this magnitude make the matrix singular
+};
+
+// pivot search over rows c..nb-1 of column c (one workgroup)
+__global__ void __launch_bounds__(1024) k_gj_pivot(const double* __restrict__ M, int nb, int c,
+                                                   int* __restrict__ perm, GJState* st) {
+    __shared__ double sv[16];
+    __shared__ int si[16];
+    double best = -1.0;
+    int bi = c;
+    for (int r = c + (int)threadIdx.x; r < nb; r += blockDim.x) {
+        const double v = fabs(M[(size_t)r * nb + c]);
+        if (v > best) {
+            best = v;
+            bi = r;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > best || (ov == best && oi < bi)) {
+            best = ov;
+            bi = oi;
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sv[threadIdx.x >> 6] = best;
+        si[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (sv[w] > best || (sv[w] == best && si[w] < bi)) {
+                best = sv[w];
+                bi = si[w];
+            }
+        st->piv = bi;
+        st->acc = M[(size_t)c * nb + c];
+        double p = M[(size_t)bi * nb + c];
+        if (!(fabs(p) > st->tiny)) {
+            st->bad = 1;
+            p = 1.0;   // keeps the remaining steps finite; the result is discarded
+        }
+        st->p = p;
+        const int t = perm[c];
+        perm[c] = perm[bi];
+        perm[bi] = t;
+    }
+}
+
+// row swap and scaling of the pivot row; col receives column c of the other
+// rows after the swap (the elimination factors)
+__global__ void k_gj_swap(double* __restrict__ M, int nb, int c, const GJState* __restrict__ st,
+                          double* __restrict__ col) {
+    const int i = (int)blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (i >= nb) return;
+    const int piv = st->piv;
+    const double p = st->p;
+    const double a = M[(size_t)c * nb + i], bv = M[(size_t)piv * nb + i];
+    M[(size_t)c * nb + i] = (i == c ? 1.0 : bv) / p;
+    if (piv != c) M[(size_t)piv * nb + i] = a;
+    // rows other than c and piv are not written by this launch
+    col[i] = i == c ? 0.0 : i == piv ? st->acc : M[(size_t)i * nb + c];
+}
+
+// elimination of column c from every row r != c (rows with a zero factor are
+// unchanged)
+__global__ void k_gj_update(double* __restrict__ M, int nb, int c, const double* __restrict__ col) {
+    const int r = (int)blockIdx.y;
+    const int q = (int)blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (r == c || q >= nb) return;
+    const double f = col[r];
+    if (f == 0.0) return;
+    double* mr = M + (size_t)r * nb;
+    mr[q] = (q == c ? 0.0 : mr[q]) - f * M[(size_t)c * nb + q];
+}
+
+// ---------------------------------------------------------------------------
 // Direct level-0 solve x0 = Z b0 with Z the leading block of the inverse of
 // the level-0 system bordered by the mean constraint: one wave per row of Z
-// (rows are contiguous), the gathered b0 staged in LDS by every workgroup.
+// (rows are contiguous), the gathered b0 (and the border's zero) staged in
+// LDS by every workgroup and read through the column permutation.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_coarse_direct(CoarseDev cd, const T* __restrict__ b,
                                                        size_t blen, T* __restrict__ x, size_t xlen,
                                                        double* __restrict__ stats) {
     extern __shared__ double bl[];
-    const int nd = cd.nd, nfv = cd.nfv, N = cd.N;
-    for (int i = threadIdx.x; i < nd; i += TPB) {
+    const int nd = cd.nd, nfv = cd.nfv, N = cd.N, nb = cd.nb;
+    for (int i = threadIdx.x; i < nb; i += TPB) {
         if (i < 3 * nfv) {
             const int c = i / nfv;
             bl[i] = (double)b[c * blen + cd.node_slot[cd.vel_node[i - c * nfv]]];
-        } else {
+        } else if (i < nd) {
             bl[i] = (double)b[3 * blen + cd.node_slot[i - 3 * nfv]];
+        } else {
+            bl[i] = 0.0;
         }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int row = (int)blockIdx.x * (TPB / 64) + ((int)threadIdx.x >> 6);
     if (row < nd) {
-        const double* z = cd.zinv + (size_t)row * nd;
+        const double* z = cd.zinv + (size_t)row * nb;
+        const int* __restrict__ perm = cd.zperm;
         double acc = 0.0;
-        for (int q = lane; q < nd; q += 64) acc += z[q] * bl[q];
+        for (int q = lane; q < nb; q += 64) acc += z[q] * bl[perm[q]];
         acc = wave_sum(acc);
         if (lane == 0) {
             int comp, vtx;

@@ -2,7 +2,8 @@
 (Section 4.4), 156 affinely mapped macros around a hole.  Its a_1 and c_l
 stencils couple all 14 neighbours, so the general-stencil kernels run (15-tap
 colour sweeps, point-block full passes, B u - g and its pressure sweep in
-separate launches) and the level-0 system is solved by MINRES.
+separate launches).  Its level-0 system (5788 unknowns) is solved directly
+(inverted on the device at set-up) or by MINRES.
 
 The library's nodal arrays live on the lattice of the bounding box; the
 oracle numbers only the vertices (its lattice indices lv.lat), so every
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-COARSE = {"coarse_solver": 1, "coarse_maxit": 4000}
+MINRES = {"coarse_solver": 1, "coarse_maxit": 4000}
 
 
 def _announce(msg):
@@ -51,10 +52,8 @@ class Shell:
         xyz, tet, nu, tags = self.cfg.mesh()
         self.mesh = (xyz, tet, nu, tags)
         self.phys = self.cfg.physical()
-        o = dict(COARSE)
-        o.update(opts)
-        _announce(f"shell config {cid} R={R} opts={o}")
-        self.s = P.Solver(xyz, tet, nu, tags, R, phys=self.phys, **o)
+        _announce(f"shell config {cid} R={R} opts={opts}")
+        self.s = P.Solver(xyz, tet, nu, tags, R, phys=self.phys, **opts)
         if oracle:
             H = build_hierarchy(xyz, tet, nu, tags, R, phys=self.phys)
             self.umg = UMG(H, nu1=self.s.opts.nu1, nu2=self.s.opts.nu2,
@@ -161,25 +160,40 @@ def test_shell_uzawa_steps_match_oracle(shell4):
         assert err < 1e-12, l
 
 
-def test_shell_coarse_minres_matches_oracle(shell4):
-    """MINRES with the lumped-mass pressure preconditioner on the 5788
-    unknowns of the shell's level 0 reaches the oracle's direct solution."""
+def test_shell_coarse_solvers_match_oracle(shell4):
+    """The level-0 system of the shell (5788 unknowns, bordered by the mean
+    constraint): the inverse formed on the device at set-up, and MINRES with
+    the lumped-mass pressure preconditioner, reach the oracle's direct
+    solution; an inconsistent right-hand side (a constant pressure part) has
+    that part removed."""
+    import paper_1511_02134_amd as P
     sh = shell4
     umg = sh.umg
     lv = umg.H.levels[0]
     x = _rand_state(lv, 80)
     b = umg.apply(0, x)
-    xg, it, rel = sh.s.coarse_solve(sh.put(b, 0))
-    _announce(f"coarse MINRES on the shell: {it} iterations, preconditioned residual {rel:.1e}")
-    assert rel < 1e-13 and it < COARSE["coarse_maxit"]
-    assert _relerr(sh.get(xg, 0), umg.coarse_solve(b)) < 1e-10
+    bi = b + np.concatenate([np.zeros((3, lv.N)), np.full((1, lv.N), 0.1)])
+    xyz, tet, nu, tags = sh.mesh
+    sm = P.Solver(xyz, tet, nu, tags, 4, phys=sh.phys, **MINRES)
+    for bb in (b, bi):
+        xo = umg.coarse_solve(bb)
+        xg, it, rel = sh.s.coarse_solve(sh.put(bb, 0))
+        assert it == 1 and rel == 0.0
+        err = _relerr(sh.get(xg, 0), xo)
+        _announce(f"coarse direct on the shell: max rel. difference {err:.2e}")
+        assert err < 1e-11
+        xg, it, rel = sm.coarse_solve(sm.scatter(_dev(sh.to_lat(bb, 0)), 0))
+        _announce(f"coarse MINRES on the shell: {it} iterations, preconditioned residual {rel:.1e}")
+        assert rel < 1e-13 and it < MINRES["coarse_maxit"]
+        assert _relerr(_host(sm.gather(xg, 0))[:, lv.lat], xo) < 1e-10
 
 
-@pytest.mark.parametrize("cycle", [0, 1])
-def test_shell_cycles_match_oracle(cycle):
-    """V(3,3) and the variable V-cycle iterate by iterate from the paper's
-    setting (random start, f = 0, homogeneous Dirichlet data) at 3 levels."""
-    sh = Shell(7, 4, cycle=cycle)
+@pytest.mark.parametrize("cycle,coarse", [(0, 0), (1, 0), (1, 1)])
+def test_shell_cycles_match_oracle(cycle, coarse):
+    """V(3,3) and the variable V-cycle, with either coarse solver, iterate by
+    iterate from the paper's setting (random start, f = 0, homogeneous
+    Dirichlet data) at 3 levels."""
+    sh = Shell(7, 4, cycle=cycle, **(MINRES if coarse else {}))
     umg = sh.umg
     lv = umg.H.finest
     x0 = _rand_state(lv, 90)
@@ -239,7 +253,7 @@ def test_shell_discretisation_error_is_second_order():
     phys = cfg.physical()
     eu, ep = [], []
     for R in (3, 4, 5):
-        s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1, **COARSE)
+        s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1)
         X = W.refined_points(xyz, tet, phys, R)
         present = ~np.isnan(X[:, 0])
         Xs = np.where(present[:, None], X, 0.0)
@@ -281,7 +295,7 @@ def test_shell_full_size_rows_and_solve():
     xyz, tet, nu, tags = cfg.mesh()
     phys = cfg.physical()
     R = cfg.R
-    s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1, coarse_solver=1)
+    s = P.Solver(xyz, tet, nu, tags, R, phys=phys, cycle=1)
     _announce(f"shell full size R={R}: {s.num_dofs()} unknowns")
     m = s.mass_weights()
     present = m > 0
