@@ -75,7 +75,8 @@ typedef enum {
  *   nu  [nt]      per-macro viscosity > 0 (NULL: all 1);
  *   face_bc [nt][4] tag of the face opposite vertex f: 0 interior (shared by
  *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing);
- *   phys [nv][3]  physical coordinates of the vertices (NULL: xyz).  Every
+ *   phys [nv][3]  physical coordinates of the vertices (NULL: xyz; the
+ *                 field was appended to the struct, callers must set it).  Every
  *                 macro carries its refinement affinely (Section 2.1: uniform
  *                 refinement splits a tetrahedron into 8 by its edge
  *                 midpoints), so its stencils are those of its own affine
@@ -110,9 +111,11 @@ typedef struct {
                              weighted by 1/nu (the paper's choice, default) */
     int32_t coarse_solver; /* 0: exact, x0 = Z b0 with Z the inverse of the level-0
                               system bordered by the mass-weighted mean constraint
-                              (computed once at set-up; one matrix-vector product
-                              per solve; default, at most 8192 level-0 unknowns);
-                              1: the block-diagonal preconditioned MINRES above */
+                              (formed on the device by hhg_create and
+                              hhg_set_viscosity, Gauss-Jordan elimination; one
+                              matrix-vector product per solve; default);
+                              1: the block-diagonal preconditioned MINRES above.
+                              Either way at most 8192 level-0 unknowns */
     int32_t krylov;       /* 1: reserve the ten finest-level vectors (4 fields each) of
                              hhg_pminres and hhg_scg; 0 (default): those calls return
                              HHG_EINVAL */
@@ -184,14 +187,17 @@ const char* hhg_global_error(void);
 int32_t hhg_num_levels(const hhg_ctx* ctx);               /* L + 1 */
 int64_t hhg_vec_len(const hhg_ctx* ctx, int32_t level);   /* values per field */
 int64_t hhg_num_nodes(const hhg_ctx* ctx, int32_t level); /* lattice nodes */
-int64_t hhg_num_dofs(const hhg_ctx* ctx, int32_t level);  /* 3*free velocity nodes + nodes */
+int64_t hhg_num_dofs(const hhg_ctx* ctx, int32_t level);  /* 3*free velocity nodes + nodes
+                                                             (vertices only, no hole points) */
 int64_t hhg_num_interface(const hhg_ctx* ctx, int32_t level); /* vertices on macro faces */
 /* Integer lattice coordinates [N][3] and velocity Dirichlet flags [N] (either
- * may be NULL) of the level's nodes in lattice order, into host arrays. */
+ * may be NULL) of the level's lattice points in lattice order, into host
+ * arrays (N = hhg_num_nodes; a lattice point of a hole has flag 0). */
 hhg_status hhg_node_info(const hhg_ctx* ctx, int32_t level, int32_t* ijk, int8_t* dirichlet);
 
 /* Lumped mass m_i = int phi_i of every node (lattice order) into a host
- * array [N]: the weights of the mean-zero pressure projection. */
+ * array [N]: the weights of the mean-zero pressure projection (0 at the
+ * lattice points of a hole, which are not vertices). */
 hhg_status hhg_mass_weights(const hhg_ctx* ctx, int32_t level, double* m);
 
 /* Host-only self-check of the index tables: runs the kernels' index

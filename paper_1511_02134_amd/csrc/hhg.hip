@@ -955,7 +955,17 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
     if (MODE == MODE_RU) ops(c, l, 0.25, 1, 0, 0);
     else ops(c, l, 0, 1, 0.25, 0);
-    if (v.n >= WIN_MIN_N) {
+    if (c->mi.general) {
+        // 15-tap fused updates
+        if (v.n >= WIN_MIN_N)
+            hipLaunchKernelGGL((k_full<T, MODE, true, true, true, 0, false, true>),
+                               dim3(ib + v.n_vtiles), dim3(TPB), 0, s, v, (const T*)x, b, t,
+                               c->partials, ib, x, col, (T)c->opts.omega);
+        else
+            hipLaunchKernelGGL((k_full<T, MODE, true, true, false, 0, false, true>),
+                               dim3(ib + full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, (const T*)x, b,
+                               t, c->partials, ib, x, col, (T)c->opts.omega);
+    } else if (v.n >= WIN_MIN_N) {
         hipLaunchKernelGGL((k_full<T, MODE, true, true, true>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s,
                            v, (const T*)x, b, t, c->partials, ib, x, col, (T)c->opts.omega);
     } else {
@@ -1005,24 +1015,18 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     // first sweep runs inside the pass that forms f - B^T p, except for the D
     // form, whose point-block sweeps run on their own
     static const int vorder[6] = {1, 2, 3, 2, 1, 0};
-    if (dpath(c)) {
+    if (c->opts.op == 1) {
         full_pass<T, MODE_RU>(c, l, x, b, t, s);
     } else {
         full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
     }
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
-        if (dpath(c)) colour_pass<T>(c, l, 0, true, x, t, s);
+        if (c->opts.op == 1) colour_pass<T>(c, l, 0, true, x, t, s);
         for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
     }
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
-    // (on general meshes, whose c_l stencils couple all 14 neighbours, on its own)
-    if (c->mi.general) {
-        full_pass<T, MODE_BP>(c, l, x, b, t, s);
-        colour_pass<T>(c, l, 0, false, x, t, s);
-    } else {
-        full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
-    }
+    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
     for (int col = 1; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
     if (c->opts.p_sweep == 1)
         for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, false, x, t, s);

@@ -648,13 +648,43 @@ __device__ __forceinline__ void mode_fields(int& f0, int& f1) {
 // sit at record positions 1, 2, 3, 4, 7, 8 in the local order of volume
 // records and 1..6 in the global direction order of interface records.
 // Volume vertices write their slot, interface vertices every copy; both
-// write mirror entry cm when there is one.
-template <typename T, int MODE, bool IFACE>
+// write mirror entry cm when there is one.  GEN (general meshes): tp holds all
+// 15 taps in the record's order and a_1, c_l couple every one of them.
+template <typename T, int MODE, bool IFACE, bool GEN = false>
 __device__ __forceinline__ void fused_update(const T* __restrict__ st, const int* tp, const T* xr,
                                              size_t rs, T* xw, size_t len, const T out[4], T omega,
                                              int ncopy, const int* copies, T* cx, size_t cs, int cm,
                                              int fa = 0, int fb = 3) {
     constexpr int q5 = IFACE ? 5 : 7, q6 = IFACE ? 6 : 8;
+    if (GEN) {
+        if (MODE == MODE_RU) {
+            for (int f = fa; f < fb; ++f) {
+                const T* u = xr + f * rs;
+                T v = out[f];
+#pragma unroll
+                for (int g = 1; g < 15; ++g) v -= st[ST_A + g] * u[tp[g]];
+                const T un = v * st[ST_INVA];
+                if (IFACE)
+                    for (int q = 0; q < ncopy; ++q) xw[f * len + copies[q]] = un;
+                else
+                    xw[f * len + tp[0]] = un;
+                if (cm >= 0) cx[f * cs + cm] = un;
+            }
+        } else {
+            const T* p = xr + 3 * rs;
+            const T p0 = IFACE ? cx[3 * cs + cm] : xw[3 * len + tp[0]];
+            T cp = st[ST_C] * p0;
+#pragma unroll
+            for (int g = 1; g < 15; ++g) cp += st[ST_C + g] * p[tp[g]];
+            const T pn = p0 + omega * (out[3] - cp) * st[ST_INVC];
+            if (IFACE)
+                for (int q = 0; q < ncopy; ++q) xw[3 * len + copies[q]] = pn;
+            else
+                xw[3 * len + tp[0]] = pn;
+            if (cm >= 0) cx[3 * cs + cm] = pn;
+        }
+        return;
+    }
     if (MODE == MODE_RU) {
         // components fa .. fb-1
         for (int f = fa; f < fb; ++f) {
@@ -788,7 +818,7 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
 // Interface vertex t of a full pass with the stencil record st.  With MIRROR
 // its taps of x come from the mirror; with FUSE (which needs the mirror) the
 // colour-fc vertices (velocity: those without Dirichlet data) are updated too.
-template <typename T, int MODE, bool FUSE, bool MIRROR, bool DOP = false>
+template <typename T, int MODE, bool FUSE, bool MIRROR, bool DOP = false, bool GEN = false>
 __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                            const T* __restrict__ x, const T* __restrict__ b, T* xw,
                                            int fcol, T omega, T out[4], int fa = 0, int fb = 3) {
@@ -807,7 +837,7 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     if (FUSE && t >= L.col_start[fcol] &&
         t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
         const int c0 = L.if_cptr[t];
-        fused_update<T, MODE, true>(st, s, L.cx, cs, xw, len, out, omega, L.if_cptr[t + 1] - c0,
+        fused_update<T, MODE, true, GEN>(st, s, L.cx, cs, xw, len, out, omega, L.if_cptr[t + 1] - c0,
                                     L.if_copy + c0, L.cx, cs, t, fa, fb);
     }
 }
@@ -816,8 +846,10 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
 // PART 1 / 2: a launch of the volume blocks only (ib = 0) or of the interface
 // blocks only (grid = ib); each then gets the registers of its own branch.
 // DOP (K x and the residual only): the D form a_2, every row from eval_node.
+// GEN (fused passes only): the fused colour update of a general mesh, whose
+// a_1 and c_l couple all 14 neighbours.
 template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false, int PART = 0,
-          bool DOP = false>
+          bool DOP = false, bool GEN = false>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
@@ -862,11 +894,14 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
 #pragma unroll
                         for (int f = 0; f < 4; ++f)
                             o[f] = rc == 0 ? out[0][f] : rc == 1 ? out[1][f] : rc == 2 ? out[2][f] : out[3][f];
-                        int s7[7];
-                        axis_slots(R, i, s7);
+                        int s7[GEN ? 15 : 7];
+                        if (GEN)
+                            nbr_slots(R, i, s7);
+                        else
+                            axis_slots(R, i, s7);
                         const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s7[0]] : -1;
-                        fused_update<T, MODE, false>(st, s7, x, len, xw, len, o, omega, 0, nullptr,
-                                                     L.cx, (size_t)L.cstride, cm);
+                        fused_update<T, MODE, false, GEN>(st, s7, x, len, xw, len, o, omega, 0,
+                                                          nullptr, L.cx, (size_t)L.cstride, cm);
                     }
                 }
             }
@@ -938,8 +973,9 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     if (FUSE && ((i + 2 * j + 3 * k) & 3) == fcol) {
                         const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
                         const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
-                        fused_update<T, MODE, false>(st, tp, x, len, xw, len, out, omega, 0, nullptr,
-                                                     L.cx, (size_t)L.cstride, cm);
+                        fused_update<T, MODE, false, GEN>(st, GEN ? s : tp, x, len, xw, len, out,
+                                                          omega, 0, nullptr, L.cx,
+                                                          (size_t)L.cstride, cm);
                     }
                 }
             }
@@ -953,7 +989,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
             T out[4];
-            iface_full<T, MODE, FUSE, MIRROR, DOP>(L, st, t, x, b, xw, fcol, omega, out, f, f + 1);
+            iface_full<T, MODE, FUSE, MIRROR, DOP, GEN>(L, st, t, x, b, xw, fcol, omega, out, f,
+                                                        f + 1);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int q2 = c0; q2 < c1; ++q2) y[f * len + L.if_copy[q2]] = out[f];
         }
@@ -989,7 +1026,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int qq = c0; qq < c1; ++qq) y[3 * len + L.if_copy[qq]] = out[3];
             if (t >= L.col_start[fcol] && t < L.col_start[fcol + 1])
-                fused_update<T, MODE, true>(st, sl, L.cx, cs, xw, len, out, omega, c1 - c0,
+                fused_update<T, MODE, true, GEN>(st, sl, L.cx, cs, xw, len, out, omega, c1 - c0,
                                             L.if_copy + c0, L.cx, cs, t);
         }
     } else {
@@ -999,7 +1036,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
             T out[4];
-            iface_full<T, MODE, FUSE, MIRROR, DOP>(L, st, t, x, b, xw, fcol, omega, out);
+            iface_full<T, MODE, FUSE, MIRROR, DOP, GEN>(L, st, t, x, b, xw, fcol, omega, out);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int f = f0; f < f1; ++f) {
                 for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
