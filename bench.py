@@ -267,7 +267,7 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     print(json.dumps(line), flush=True)
 
 
-def run_shell(R: int, steps: int, warmup: int):
+def run_shell(R: int, steps: int, warmup: int, ordering: int = 0):
     """The spherical shell 0.55 < |x| < 1 (Section 4.4) as 156 affinely mapped
     macros: f = 0, homogeneous Dirichlet data on both spheres, a seeded random
     start (the paper's setting), variable V(3,3) to a 1e-8 relative residual
@@ -281,7 +281,7 @@ def run_shell(R: int, steps: int, warmup: int):
     cfg = W.WORKLOADS[7].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
     t0 = time.perf_counter()
-    s = P.Solver(xyz, tet, nu, tags, R, phys=cfg.physical(), cycle=1)
+    s = P.Solver(xyz, tet, nu, tags, R, phys=cfg.physical(), cycle=1, ordering=ordering)
     t_setup = time.perf_counter() - t0
     dev = torch.device("cuda")
     dofs, N = s.num_dofs(), s.num_nodes()
@@ -315,6 +315,7 @@ def run_shell(R: int, steps: int, warmup: int):
                        "156 affinely mapped macros (hollow cube [0,3]^3 minus its centre cell)",
                        "refinements": R, "dofs": dofs, "vertices": nvert,
                        "cycle": "Vvar(3,3)",
+                       "ordering": "hybrid" if ordering else "colour",
                        "coarse": "exact (inverse of the bordered level-0 system, 5788 unknowns)",
                        "cycles": info["cycles"], "rho_mean": info["rho_mean"],
                        "status": info["status"]},
@@ -380,6 +381,9 @@ def main():
                          "refinements and the channel, V otherwise)")
     ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
                     help="velocity form: Laplace (a_1, default) or D (a_2 = 2<nu D(u), D(v)>)")
+    ap.add_argument("--ordering", choices=("colour", "hybrid"), default="colour",
+                    help="Gauss-Seidel order of the smoother: the global 4-colouring (default) "
+                         "or the hybrid primitive-class order of HHG (Section 3.4)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision solve reported beside the FP64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -405,8 +409,9 @@ def main():
         run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1),
                     args.op == "D")
         return
+    ordering = 1 if args.ordering == "hybrid" else 0
     if args.shell:
-        run_shell(args.shell, args.steps, args.warmup)
+        run_shell(args.shell, args.steps, args.warmup, ordering)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -431,7 +436,7 @@ def main():
         cycle = 1 if args.cycle == "Vvar" else 0
     dform = args.op == "D"
     s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0,
-                 cycle=cycle)
+                 cycle=cycle, ordering=ordering)
     dofs = s.num_dofs()
     nvert = s.num_nodes()
     name = cfg.name.rsplit("-", 1)[0] + ("-fp64" if precision == 0 else "-mixed")
@@ -535,6 +540,7 @@ def main():
             "vertices": nvert,
             "cycle": "Vvar(3,3)" if cycle else "V(3,3)",
             "form": "D (a_2)" if dform else "Laplace (a_1)",
+            "ordering": args.ordering,
             "rtol": 1e-8,
             "cycles": info["cycles"],
             "coarse": ("exact (inverse of the bordered level-0 system)" if s.opts.coarse_solver == 0
@@ -569,7 +575,8 @@ def main():
         },
     }
     if precision == 0 and not args.no_mixed:
-        sm = P.Solver(xyz, tet, nu, tags, cfg.R, precision=1, op=1 if dform else 0, cycle=cycle)
+        sm = P.Solver(xyz, tet, nu, tags, cfg.R, precision=1, op=1 if dform else 0, cycle=cycle,
+                      ordering=ordering)
         xm = torch.empty_like(x0)
         ms_m, info_m, _ = timed_solves(sm, f_int, x0, xm, args.steps, args.warmup)
         line["mixed_precision"] = {

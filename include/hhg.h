@@ -132,6 +132,15 @@ typedef struct {
                              in the velocity multigrid of hhg_vel_cycle, hhg_pminres and
                              hhg_scg, and the viscosity gradient of hhg_grad takes the
                              coupled form.  The D form needs coarse_solver = 0 */
+    int32_t ordering;     /* Gauss-Seidel order of the Uzawa smoother (Section 3.4):
+                             0 (default) the global 4-colouring, colour (X+Y+Z) mod 4;
+                             1 the hybrid order of HHG: primitive classes in the order
+                             macro vertices, edges, faces, volumes; primitives of one
+                             class decoupled (block Jacobi: a vertex reads the vertices
+                             of other primitives of its class as they were when the
+                             class started); inside a primitive the colours 0..3
+                             (backward sweep 3..0, class order kept).  Laplace form,
+                             without the Krylov vectors */
 } hhg_opts;
 
 /* Result of hhg_solve. */
@@ -194,6 +203,12 @@ int64_t hhg_num_interface(const hhg_ctx* ctx, int32_t level); /* vertices on mac
  * may be NULL) of the level's lattice points in lattice order, into host
  * arrays (N = hhg_num_nodes; a lattice point of a hole has flag 0). */
 hhg_status hhg_node_info(const hhg_ctx* ctx, int32_t level, int32_t* ijk, int8_t* dirichlet);
+
+/* HHG primitive class (Section 3.4) of every lattice point of the level into
+ * a host array [N] (lattice order): 0 on a macro vertex, 1 inside a macro
+ * edge, 2 inside a macro face, 3 inside a macro, -1 at a point of a hole.
+ * The hybrid ordering (opts.ordering = 1) sweeps the classes in this order. */
+hhg_status hhg_primitive_classes(const hhg_ctx* ctx, int32_t level, int8_t* cls);
 
 /* Lumped mass m_i = int phi_i of every node (lattice order) into a host
  * array [N]: the weights of the mean-zero pressure projection (0 at the

@@ -284,6 +284,8 @@ class Hierarchy:
     nu: np.ndarray
     project: bool              # pressure determined up to a constant (no natural face)
     op: str = "laplace"        # velocity form: "laplace" (a_1) or "D" (a_2)
+    macro_int: np.ndarray = None   # [nv,3] integer lattice coordinates of the macro vertices
+    tet: np.ndarray = None         # [nt,4] macro tetrahedra
 
     @property
     def finest(self):
@@ -319,4 +321,30 @@ def build_hierarchy(xyz, tet, nu, face_bc, R, R0=2, op="laplace", phys=None):
         prol.append(_prolongation(levels[-1], None, lv))
         levels.append(lv)
     project = not np.any(face_bc == 2)
-    return Hierarchy(levels=levels, P=prol, nu=nu, project=project, op=op)
+    return Hierarchy(levels=levels, P=prol, nu=nu, project=project, op=op, macro_int=macro_int,
+                     tet=np.asarray(tet))
+
+
+def primitives(lv, macro_int, tet):
+    """HHG primitive of every node (Section 3.4): the macro vertex, edge, face or
+    volume whose relative interior holds it, i.e. the sub-simplex spanned by
+    the macro vertices with positive barycentric coordinate.  Returns
+    (cls [N], prim [N]): cls 0 vertex, 1 edge, 2 face, 3 volume; prim numbers
+    the primitives (equal for nodes of one primitive)."""
+    n = lv.n
+    N = lv.N
+    key = np.full((N, 4), -1, dtype=np.int64)
+    for t in range(tet.shape[0]):
+        L = macro_int[tet[t]].astype(np.int64)
+        E = (L[1:] - L[0]).T                          # columns: edge vectors
+        Einv = np.rint(np.linalg.inv(E)).astype(np.int64)   # unimodular (Kuhn macros)
+        mu = (lv.X - n * L[0]) @ Einv.T               # n * (lambda_1..3)
+        lam = np.concatenate([n - mu.sum(axis=1, keepdims=True), mu], axis=1)
+        inside = np.all(lam >= 0, axis=1)
+        ids = np.where(lam[inside] > 0, tet[t][None, :], -1)
+        key[inside] = np.sort(ids, axis=1)
+    if np.any(key[:, 3] < 0):
+        raise ValueError("a node lies in no macro")
+    cls = (key >= 0).sum(axis=1) - 1
+    _, prim = np.unique(key, axis=0, return_inverse=True)
+    return cls.astype(np.int64), prim.ravel().astype(np.int64)

@@ -30,6 +30,17 @@ Readings taken (listed again in the design notes):
     null space.
   * stopping criterion (Section 3.6): ||K x_k - f~||_2 <= eps ||K x_0 - f~||_2,
     Euclidean over free velocity rows and all pressure rows.
+  * ordering="hybrid": the hybrid Gauss-Seidel of HHG (Section 3.4).  The
+    nodes are grouped by primitive (macro vertex, edge, face, volume: the
+    sub-simplex whose relative interior holds the node) and updated class by
+    class, vertices -> edges -> faces -> volumes.  Primitives of one class are
+    decoupled (block Jacobi): a node reads the nodes of other primitives of
+    its own class as they were when the class started.  Inside a primitive
+    the Gauss-Seidel order is the 4-colouring (colours 0..3 forward); the
+    backward sweep reverses only the order inside the primitives (colours
+    3..0), not the class order, so forward + backward (SHGS) is not
+    symmetric.  The paper uses a row-wise red-black order inside a
+    primitive; the 4-colouring is the order the device can run in parallel.
   * D form (a_2, Section 2.1): the velocity block couples the three
     components, so the velocity sweep is a point-block Gauss-Seidel: at each
     vertex of the colour the 3x3 diagonal block is solved exactly.  The
@@ -41,13 +52,17 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from .fem import Hierarchy
 
 
 class UMG:
     def __init__(self, H: Hierarchy, nu1=3, nu2=3, omega=0.3, variable=False,
-                 p_sweep="forward"):
+                 p_sweep="forward", ordering="colour"):
+        if ordering not in ("colour", "hybrid"):
+            raise ValueError(ordering)
+        self.ordering = ordering
         self.H = H
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         self.variable = variable
@@ -72,7 +87,44 @@ class UMG:
                     g["v"].append((iv, lv.A[iv], dA[iv]))
                 g["p"].append((ip, lv.C[ip], dC[ip]))
             self._gs.append(g)
+        if ordering == "hybrid":
+            if self.dform:
+                raise ValueError("hybrid ordering: Laplace form only")
+            self._hyb = [self._hybrid_groups(lv) for lv in H.levels]
         self._coarse = self._factor_coarse(H.levels[0])
+
+    def _hybrid_groups(self, lv):
+        """Per (class, colour): the rows updated together, their rows of A or
+        C, the diagonal, and the entries towards nodes of other primitives of
+        the same class (read from the class's starting values)."""
+        from .fem import primitives
+        cls, prim = primitives(lv, self.H.macro_int, self.H.tet)
+        out = {"v": {}, "p": {}}
+        for key, M, rowmask in (("v", lv.A, lv.free), ("p", lv.C, np.ones(lv.N, dtype=bool))):
+            diag = M.diagonal()
+            for k in range(4):
+                for c in range(4):
+                    idx = np.nonzero(rowmask & (cls == k) & (lv.colour == c))[0]
+                    rows = M[idx].tocoo()
+                    jac = (cls[rows.col] == k) & (prim[rows.col] != prim[idx[rows.row]])
+                    J = sp.csr_matrix((rows.data[jac], (rows.row[jac], rows.col[jac])),
+                                      shape=(idx.shape[0], lv.N))
+                    out[key][(k, c)] = (idx, M[idx], J, diag[idx])
+        return out
+
+    def _hybrid_pass(self, l, kind, r, d, colours, omega=1.0):
+        """One hybrid pass (classes 0..3, the given colour order inside each)
+        on M d = r in place, kind "v" (A) or "p" (C, relaxed by omega)."""
+        g = self._hyb[l][kind]
+        for k in range(4):
+            snap = d.copy()
+            for c in colours:
+                idx, rows, J, diag = g[(k, c)]
+                if idx.shape[0] == 0:
+                    continue
+                s = rows @ d - J @ (d - snap)
+                d[idx] += omega * (r[idx] - s) / diag
+        return d
 
     # -- operators -------------------------------------------------------
     def rhs(self, f_nodal, l=None):
@@ -104,6 +156,9 @@ class UMG:
         and every vertex solves its 3x3 diagonal block)."""
         d = np.zeros_like(r)
         order = list(range(4)) + list(range(3, -1, -1))
+        if self.ordering == "hybrid":
+            self._hybrid_pass(l, "v", r, d, range(4))
+            return self._hybrid_pass(l, "v", r, d, range(3, -1, -1))
         if self.dform:
             N = r.shape[-1]
             rf, df = r.ravel(), d.ravel()
@@ -122,6 +177,11 @@ class UMG:
         version (forward then backward) when p_sweep == 'symmetric'."""
         d = np.zeros_like(s)
         order = list(range(4))
+        if self.ordering == "hybrid":
+            self._hybrid_pass(l, "p", s, d, range(4), self.omega)
+            if self.p_sweep == "symmetric":
+                self._hybrid_pass(l, "p", s, d, range(3, -1, -1), self.omega)
+            return d
         if self.p_sweep == "symmetric":
             order += list(range(3, -1, -1))
         for c in order:

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("coarse_rtol", ctypes.c_double),
                 ("coarse_maxit", ctypes.c_int32), ("block_order", ctypes.c_int32),
                 ("coarse_prec", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
-                ("krylov", ctypes.c_int32), ("graphs", ctypes.c_int32), ("op", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("graphs", ctypes.c_int32), ("op", ctypes.c_int32),
+                ("ordering", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -83,6 +84,7 @@ def _load():
         "hhg_node_info": (S, [P, I32, P, P]),
         "hhg_check_layout": (S, [P]),
         "hhg_mass_weights": (S, [P, I32, P]),
+        "hhg_primitive_classes": (S, [P, I32, P]),
         "hhg_scatter": (S, [P, I32, P, I32, P, P]),
         "hhg_gather": (S, [P, I32, P, I32, P, P]),
         "hhg_exchange": (S, [P, I32, P, I32, P]),
@@ -122,7 +124,8 @@ lib = _load()
 # exported symbols declared in include/hhg.h (checked by the CPU tests)
 ABI_FUNCTIONS = ("hhg_default_opts", "hhg_plan", "hhg_create", "hhg_destroy", "hhg_last_error",
                  "hhg_global_error", "hhg_num_levels", "hhg_vec_len", "hhg_num_nodes",
-                 "hhg_num_dofs", "hhg_num_interface", "hhg_node_info", "hhg_mass_weights", "hhg_check_layout", "hhg_scatter",
+                 "hhg_num_dofs", "hhg_num_interface", "hhg_node_info", "hhg_mass_weights",
+                 "hhg_primitive_classes", "hhg_check_layout", "hhg_scatter",
                  "hhg_gather", "hhg_exchange", "hhg_rhs", "hhg_rhs_level", "hhg_fmg",
                  "hhg_apply", "hhg_residual", "hhg_residual_noalloc",
                  "hhg_smooth", "hhg_restrict", "hhg_prolong_add", "hhg_coarse_solve",
@@ -248,6 +251,15 @@ class Solver:
         m = np.zeros(self.num_nodes(level))
         _check(lib.hhg_mass_weights(self.ctx, level, m.ctypes.data_as(ctypes.c_void_p)), self.ctx)
         return m
+
+    def primitive_classes(self, level=None):
+        """HHG primitive class of every lattice point (0 macro vertex, 1 edge,
+        2 face, 3 volume, -1 hole)."""
+        level = self.L if level is None else level
+        cls = np.zeros(self.num_nodes(level), dtype=np.int8)
+        _check(lib.hhg_primitive_classes(self.ctx, level, cls.ctypes.data_as(ctypes.c_void_p)),
+               self.ctx)
+        return cls
 
     def check_layout(self):
         """Host-side verification of every index the kernels compute."""

@@ -82,6 +82,11 @@ struct DevLevelArrays {
     // once) and 1 / (lumped pressure mass weighted by 1/nu) on every copy
     uint8_t* owned;
     double* pinv;
+    // hybrid ordering: grouped interface lists, cross-primitive tap masks and
+    // the class's starting values of the interface vertices (4 fields x nif)
+    int32_t *hyb_list, *hyb_mask;
+    double* snap64;
+    float* snap32;
 };
 
 constexpr int KV_N = 10;   // finest-level vectors of the Krylov solvers
@@ -195,6 +200,14 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
         *err = "the D form needs the exact coarse solver (coarse_solver = 0)";
         return false;
     }
+    if (o->ordering < 0 || o->ordering > 1) {
+        *err = "ordering must be 0 (colours) or 1 (hybrid primitive classes)";
+        return false;
+    }
+    if (o->ordering == 1 && (o->op != 0 || o->krylov != 0)) {
+        *err = "the hybrid ordering runs the Laplace form without the Krylov solvers";
+        return false;
+    }
     return true;
 }
 
@@ -299,6 +312,11 @@ size_t layout(hhg_ctx* c, char* ws) {
             a.r32 = cv.take<float>(v4);
             a.t32 = cv.take<float>(v4);
         }
+        a.hyb_list = cv.take<int32_t>(std::max<size_t>(1, h.hyb_list.size()));
+        a.hyb_mask = cv.take<int32_t>(std::max<size_t>(1, h.hyb_mask.size()));
+        a.snap64 = c->opts.ordering == 1 ? cv.take<double>((size_t)4 * std::max(1, h.nif)) : nullptr;
+        a.snap32 = c->opts.ordering == 1 && mixed ? cv.take<float>((size_t)4 * std::max(1, h.nif))
+                                                  : nullptr;
         a.owned = nullptr;
         a.pinv = nullptr;
         if (l == c->L) {
@@ -515,6 +533,8 @@ hhg_status upload_all(hhg_ctx* c) {
         UP(int32_t, a.if_tap, h.if_tap);
         UP(int32_t, a.halo_slot, h.halo_slot);
         UP(int32_t, a.comp_of_slot, h.comp_of_slot);
+        UP(int32_t, a.hyb_list, h.hyb_list);
+        UP(int32_t, a.hyb_mask, h.hyb_mask);
         {
             std::vector<int32_t> m0(h.nm + 1, 0);
             for (const Tile& t : h.ctiles)
@@ -1007,9 +1027,94 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
     }
 }
 
+template <typename T>
+T* snap_of(DevLevelArrays& a);
+template <>
+double* snap_of<double>(DevLevelArrays& a) { return a.snap64; }
+template <>
+float* snap_of<float>(DevLevelArrays& a) { return a.snap32; }
+
+// One pass of the hybrid ordering (Section 3.4) on the velocity (vel) or the
+// pressure: for each primitive class (macro vertices, edges, faces) the
+// class's starting values are saved, then its colours run in the given
+// order; the volume class follows as volume-only colour launches (volume
+// primitives, the macro interiors, never couple to each other).
+template <typename T>
+void hybrid_pass(hhg_ctx* c, int l, bool vel, bool backward, T* x, const T* rhs, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    DevLevelArrays& a = c->A[l];
+    const HostLevel& h = c->H[l];
+    T* snap = snap_of<T>(a);
+    const int kind = vel ? 0 : 1;
+    const T omega = vel ? T(0) : (T)c->opts.omega;
+    for (int k = 0; k < 3; ++k) {
+        // starting values of every vertex of the class (the pressure groups
+        // list all of them: a masked tap may reach a velocity Dirichlet vertex)
+        const int g0 = h.hyb_off[12 + 4 * k], g1 = h.hyb_off[12 + 4 * k + 4];
+        if (g1 > g0)
+            hipLaunchKernelGGL(k_hyb_snap<T>, dim3((g1 - g0 + TPB - 1) / TPB), dim3(TPB), 0, s, v,
+                               a.hyb_list + g0, g1 - g0, vel ? 0 : 3, vel ? 3 : 4, snap);
+        for (int q = 0; q < 4; ++q) {
+            const int col = backward ? 3 - q : q;
+            const int o0 = h.hyb_off[12 * kind + 4 * k + col], o1 = h.hyb_off[12 * kind + 4 * k + col + 1];
+            const int cnt = o1 - o0;
+            if (cnt == 0) continue;
+            const int lanes = vel ? 3 * cnt : cnt;
+            const dim3 grid((lanes + TPB - 1) / TPB);
+            if (vel && c->mi.general)
+                hipLaunchKernelGGL((k_hyb_iface<T, true, true>), grid, dim3(TPB), 0, s, v,
+                                   a.hyb_list + o0, cnt, x, rhs, omega, (const T*)snap, a.hyb_mask);
+            else if (vel)
+                hipLaunchKernelGGL((k_hyb_iface<T, true, false>), grid, dim3(TPB), 0, s, v,
+                                   a.hyb_list + o0, cnt, x, rhs, omega, (const T*)snap, a.hyb_mask);
+            else if (c->mi.general)
+                hipLaunchKernelGGL((k_hyb_iface<T, false, true>), grid, dim3(TPB), 0, s, v,
+                                   a.hyb_list + o0, cnt, x, rhs, omega, (const T*)snap, a.hyb_mask);
+            else
+                hipLaunchKernelGGL((k_hyb_iface<T, false, false>), grid, dim3(TPB), 0, s, v,
+                                   a.hyb_list + o0, cnt, x, rhs, omega, (const T*)snap, a.hyb_mask);
+        }
+    }
+    // volume primitives: every block a volume tile (no interface blocks)
+    const dim3 grid(v.n_vtiles);
+    for (int q = 0; q < 4; ++q) {
+        const int col = backward ? 3 - q : q;
+        if (vel && c->mi.general)
+            hipLaunchKernelGGL((k_colour<T, true, false, true>), grid, dim3(TPB), 0, s, v, col, x, rhs,
+                               omega, 0);
+        else if (vel)
+            hipLaunchKernelGGL((k_colour<T, true>), grid, dim3(TPB), 0, s, v, col, x, rhs, omega, 0);
+        else if (c->mi.general)
+            hipLaunchKernelGGL((k_colour<T, false, false, true>), grid, dim3(TPB), 0, s, v, col, x,
+                               rhs, omega, 0);
+        else
+            hipLaunchKernelGGL((k_colour<T, false>), grid, dim3(TPB), 0, s, v, col, x, rhs, omega, 0);
+    }
+}
+
+// one inexact Uzawa step in the hybrid ordering: f - B^T p, the forward and
+// the backward hybrid velocity passes (SHGS), B u - g, the forward hybrid
+// pressure pass (and the backward one with p_sweep = 1)
+template <typename T>
+void uzawa_step_hybrid(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
+    // a full sweep of either operator counts as one evaluation of it
+    full_pass<T, MODE_RU>(c, l, x, b, t, s);
+    ops(c, l, 2.0, 0, 0, 0);
+    hybrid_pass<T>(c, l, true, false, x, t, s);
+    hybrid_pass<T>(c, l, true, true, x, t, s);
+    full_pass<T, MODE_BP>(c, l, x, b, t, s);
+    ops(c, l, 0, 0, c->opts.p_sweep == 1 ? 2.0 : 1.0, 0);
+    hybrid_pass<T>(c, l, false, false, x, t, s);
+    if (c->opts.p_sweep == 1) hybrid_pass<T>(c, l, false, true, x, t, s);
+}
+
 // one inexact Uzawa step (eq. Uzawa_smooth) in place
 template <typename T>
 void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
+    if (c->opts.ordering == 1) {
+        uzawa_step_hybrid<T>(c, l, x, b, t, s);
+        return;
+    }
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
     // colour 3 right after the first would recompute identical values); the
     // first sweep runs inside the pass that forms f - B^T p, except for the D
@@ -1284,6 +1389,7 @@ void hhg_default_opts(hhg_opts* o) {
     o->krylov = 0;
     o->graphs = 0;
     o->op = 0;
+    o->ordering = 0;
 }
 
 const char* hhg_global_error(void) { return g_error.c_str(); }
@@ -1363,6 +1469,19 @@ hhg_status hhg_node_info(const hhg_ctx* c, int32_t l, int32_t* ijk, int8_t* dir)
             ijk[3 * v + 2] = (int32_t)(v / ((int64_t)h.lat[0] * h.lat[1]));
         }
         if (dir) dir[v] = h.node_dir[v];
+    }
+    return HHG_OK;
+}
+
+hhg_status hhg_primitive_classes(const hhg_ctx* c, int32_t l, int8_t* cls) {
+    if (!c || l < 0 || l > c->L || !cls)
+        return fail(nullptr, HHG_EINVAL, "bad context, level or array");
+    const HostLevel& h = c->H[l];
+    for (int64_t v = 0; v < h.N; ++v) cls[v] = h.node_slot[v] >= 0 ? 3 : -1;
+    for (int t = 0; t < h.nif; ++t) {
+        const int pat = h.keys[h.if_sid[t] - h.nm][0].second;
+        const int zeros = (pat & 1) + (pat >> 1 & 1) + (pat >> 2 & 1) + (pat >> 3 & 1);
+        cls[h.if_lat[t]] = (int8_t)(3 - zeros);
     }
     return HHG_OK;
 }
@@ -1953,6 +2072,40 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
                     }
         CK(with_entry == (int64_t)h.if_copy.size() + (int64_t)h.halo_slot.size(),
            "mirror entries on padding slots");
+    }
+    // hybrid ordering: every interface vertex in one pressure group and every
+    // velocity-free one in one velocity group, of its own colour; masked taps
+    // reach interface vertices of another primitive in the same group class
+    {
+        const int nif = h.nif;
+        std::vector<int> colour(nif, -1), cls(nif, -1);
+        for (int cc = 0; cc < 4; ++cc)
+            for (int t = h.col_start[cc]; t < h.col_start[cc + 1]; ++t) colour[t] = cc;
+        for (int kind = 0; kind < 2; ++kind) {
+            std::vector<int> seen(nif, 0);
+            for (int k = 0; k < 3; ++k)
+                for (int cc = 0; cc < 4; ++cc)
+                    for (int q = h.hyb_off[12 * kind + 4 * k + cc]; q < h.hyb_off[12 * kind + 4 * k + cc + 1];
+                         ++q) {
+                        const int t = h.hyb_list[q];
+                        CK(t >= 0 && t < nif, "hybrid list entry out of range");
+                        CK(colour[t] == cc, "hybrid group holds a vertex of another colour");
+                        CK(kind == 1 || h.if_flag[t] == 0, "hybrid velocity group holds a Dirichlet vertex");
+                        seen[t]++;
+                        CK(cls[t] < 0 || cls[t] == k, "vertex in two primitive classes");
+                        cls[t] = k;
+                    }
+            for (int t = 0; t < nif; ++t)
+                CK(seen[t] == ((kind == 1 || h.if_flag[t] == 0) ? 1 : 0),
+                   "hybrid groups do not partition the interface");
+        }
+        for (int t = 0; t < nif; ++t)
+            for (int g = 0; g < 14; ++g)
+                if (h.hyb_mask[t] >> g & 1) {
+                    const int e = h.if_tap[(size_t)g * nif + t];
+                    CK(e < nif && cls[e] == cls[t] && h.if_sid[e] != h.if_sid[t],
+                       "hybrid mask flags a tap outside the vertex's class");
+                }
     }
     // full-pass blocks: each real tile once per sub-row, on the tile's XCD,
     // partial slots 4 nat + r distinct and below the reduction count (the

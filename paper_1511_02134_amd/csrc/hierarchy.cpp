@@ -628,6 +628,34 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         L.ncomp = next;
         L.comp_of_slot.swap(comp);
     }
+    // hybrid ordering tables: the primitive of an interface vertex is its key
+    // (all vertices of one macro vertex, edge or face share it); its class
+    // follows from the number of vanishing barycentric coordinates
+    {
+        std::vector<int> cls(nif);
+        for (int t = 0; t < nif; ++t) {
+            const int pat = L.keys[L.if_sid[t] - nm][0].second;
+            const int zeros = (pat & 1) + (pat >> 1 & 1) + (pat >> 2 & 1) + (pat >> 3 & 1);
+            cls[t] = 3 - zeros;
+        }
+        L.hyb_list.clear();
+        for (int kind = 0; kind < 2; ++kind)
+            for (int k = 0; k < 3; ++k)
+                for (int c = 0; c < 4; ++c) {
+                    L.hyb_off[12 * kind + 4 * k + c] = (int32_t)L.hyb_list.size();
+                    for (int t = L.col_start[c]; t < L.col_start[c + 1]; ++t)
+                        if (cls[t] == k && (kind == 1 || L.if_flag[t] == 0)) L.hyb_list.push_back(t);
+                }
+        L.hyb_off[24] = (int32_t)L.hyb_list.size();
+        L.hyb_off[25] = 0;
+        L.hyb_mask.assign(std::max(nif, 1), 0);
+        for (int t = 0; t < nif; ++t)
+            for (int g = 0; g < 14; ++g) {
+                const int32_t e = L.if_tap[(size_t)g * nif + t];
+                if (e < nif && e != t && cls[e] == cls[t] && L.if_sid[e] != L.if_sid[t])
+                    L.hyb_mask[t] |= 1 << g;
+            }
+    }
     L.nfree = 0;
     L.nnodes = 0;
     for (int64_t v = 0; v < L.N; ++v)

@@ -76,6 +76,15 @@ struct HostLevel {
     std::vector<int32_t> if_tap;           // [14][nif] mirror index of each neighbour
     std::vector<int32_t> halo_slot;        // [ncomp - nif] slot of each halo vertex
     std::vector<int32_t> comp_of_slot;     // [len] mirror index of a slot or -1
+    // hybrid ordering (primitive classes, Section 3.4): interface vertices
+    // grouped by class (0 macro vertex, 1 edge, 2 face) and colour, the
+    // velocity-free ones and all of them; hyb_off[12 * kind + 4 * class +
+    // colour] .. [+1] delimit a group in hyb_list (kind 0 velocity, 1
+    // pressure); hyb_mask[t] bit g-1: tap g reaches another primitive of t's
+    // class (read from the class's starting values)
+    std::vector<int32_t> hyb_list;
+    int32_t hyb_off[26] = {0};
+    std::vector<int32_t> hyb_mask;
     int64_t nfree = 0;                     // free velocity vertices
     int64_t nnodes = 0;                    // vertices (N minus the lattice points of a hole)
 };

@@ -377,6 +377,59 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Hybrid ordering (Section 3.4): the interface vertices of one primitive class
+// and colour, listed in `list`.  Taps flagged in mask[t] reach another
+// primitive of the same class and read `snap` (the mirror's values when the
+// class started: block Jacobi between primitives); every other tap reads the
+// current mirror (Gauss-Seidel).  Velocity: a lane per vertex and component;
+// pressure: a lane per vertex, relaxed by omega.  GEN: a_1 and c_l couple all
+// 14 neighbours (general meshes), otherwise the 6 axis neighbours.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_hyb_snap(LevelDev<T> L, const int* __restrict__ list, int cnt, int f0, int f1,
+                           T* __restrict__ snap) {
+    const int q = (int)blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (q >= cnt) return;
+    const int t = list[q];
+    for (int f = f0; f < f1; ++f) snap[(size_t)f * L.nif + t] = L.cx[(size_t)f * L.cstride + t];
+}
+
+template <typename T, bool VEL, bool GEN>
+__global__ void __launch_bounds__(TPB) k_hyb_iface(LevelDev<T> L, const int* __restrict__ list,
+                                                   int cnt, T* __restrict__ x,
+                                                   const T* __restrict__ rhs, T omega,
+                                                   const T* __restrict__ snap,
+                                                   const int* __restrict__ mask) {
+    constexpr int NT = GEN ? 14 : 6;
+    const int q = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    const int i = VEL ? q / 3 : q, f = VEL ? q % 3 : 3;
+    if (i >= cnt) return;
+    const int t = list[i];
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
+    const int nif = L.nif;
+    const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+    const int m = mask[t];
+    const T* cur = L.cx + f * cs;
+    const T* old = snap + (size_t)f * nif;
+    const int blk = VEL ? ST_A : ST_C;
+    T acc = T(0);
+#pragma unroll
+    for (int g = 0; g < NT; ++g) {
+        const int e = L.if_tap[g * nif + t];
+        acc += st[blk + 1 + g] * ((m >> g & 1) ? old[e] : cur[e]);
+    }
+    T v;
+    if (VEL) {
+        v = (rhs[f * len + L.if_self[t]] - acc) * st[ST_INVA];
+    } else {
+        const T p0 = cur[t];
+        v = p0 + omega * (rhs[3 * len + L.if_self[t]] - (st[ST_C] * p0 + acc)) * st[ST_INVC];
+    }
+    for (int qq = L.if_cptr[t]; qq < L.if_cptr[t + 1]; ++qq) x[f * len + L.if_copy[qq]] = v;
+    L.cx[f * cs + t] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Full passes over every vertex (volume interior + interface), one template
 // for the operators that read all 15 taps:
 //   MODE_APPLY   y = K x                         (Dirichlet velocity rows 0)

@@ -81,6 +81,10 @@ def test_plan_rejects_bad_arguments():
     _expect_einval(xyz, tet, nu, tags, op=2)
     _expect_einval(xyz, tet, nu, tags, op=-1)
     assert "exact coarse" in _expect_einval(xyz, tet, nu, tags, op=1, coarse_solver=1)
+    _expect_einval(xyz, tet, nu, tags, ordering=2)
+    assert "hybrid" in _expect_einval(xyz, tet, nu, tags, ordering=1, op=1)
+    assert "hybrid" in _expect_einval(xyz, tet, nu, tags, ordering=1, krylov=1)
+    assert P.plan(xyz, tet, nu, tags, 3, ordering=1) > P.plan(xyz, tet, nu, tags, 3)
     _expect_einval(xyz, tet, nu, tags, krylov=2)
     _expect_einval(xyz, tet, nu, tags, graphs=-1)
 
@@ -140,14 +144,35 @@ def test_hierarchy_matches_oracle_mesh(cid):
 
 
 @pytest.mark.parametrize("cid,R,order", [(1, 5, 1), (4, 4, 1), (5, 4, 1), (4, 4, 0), (4, 4, 2),
-                                         (5, 2, 1), (4, 3, 2)])
+                                         (5, 2, 1), (4, 3, 2), (8, 4, 1)])
 def test_kernel_index_arithmetic_on_host(cid, R, order):
     """The device index code (compiled for the host) reaches exactly the
     intended vertices on every level: no access outside a macro, every vertex
-    once per sweep, colour sweeps touch only their colour."""
+    once per sweep, colour sweeps touch only their colour; the hybrid
+    ordering's groups partition the interface by class and colour."""
     cfg = W.WORKLOADS[cid].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    P.Solver(xyz, tet, nu, tags, R, host_only=True, block_order=order).check_layout()
+    P.Solver(xyz, tet, nu, tags, R, host_only=True, block_order=order,
+             phys=cfg.physical()).check_layout()
+
+
+@pytest.mark.parametrize("cid", [1, 4, 8])
+def test_hybrid_groups_match_oracle_primitives(cid):
+    """The library's primitive classes (from its interface keys) agree with
+    the oracle's (from barycentric coordinates): every interface vertex of
+    the velocity and pressure groups sits in the class the oracle gives it,
+    and every macro vertex, edge and face vertex of the oracle is listed."""
+    from oracle.fem import primitives
+    R = 3
+    cfg = W.WORKLOADS[cid].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    s = P.Solver(xyz, tet, nu, tags, R, host_only=True, ordering=1, phys=cfg.physical())
+    H = build_hierarchy(xyz, tet, nu, tags, R, phys=cfg.physical())
+    for l, lv in enumerate(H.levels):
+        cls, _ = primitives(lv, H.macro_int, H.tet)
+        lib_cls = s.primitive_classes(l)       # lattice order, -1 at hole points
+        assert np.array_equal(lib_cls[lv.lat], cls)
+        assert np.all(np.delete(lib_cls, lv.lat) == -1)
 
 
 def _shell(R=3):

@@ -169,3 +169,81 @@ def test_paper_style_iteration_count():
     _, hist = umg.solve(x0, b, rtol=1e-8)
     it = len(hist) - 1
     assert abs(it - gold["umg_iterations"]["2"]) <= 2, hist
+
+
+def test_primitive_classes_of_the_unit_cube():
+    """fem.primitives against the combinatorics of the 6-tetrahedron Kuhn cube
+    (8 corners, 19 edges, 18 faces, 6 volumes; edge, face and volume
+    primitives hold n-1, (n-1)(n-2)/2 and (n-1)(n-2)(n-3)/6 nodes at 2^R = n)
+    and against closed-form rules for nodes inside the cube: the main
+    diagonal X = Y = Z is an edge, the planes X = Y, Y = Z, X = Z are faces,
+    and points with distinct coordinates lie in a volume."""
+    from oracle.fem import primitives
+    cfg = W.WORKLOADS[1].with_R(4)
+    xyz, tet, nu, tags = cfg.mesh()
+    H = build_hierarchy(xyz, tet, nu, tags, 4)
+    for lv in H.levels:
+        n = lv.n
+        cls, prim = primitives(lv, H.macro_int, H.tet)
+        counts = [len(np.unique(prim[cls == k])) for k in range(4)]
+        assert counts == [8, 19, 18, 6]
+        sizes = [1, n - 1, (n - 1) * (n - 2) // 2, (n - 1) * (n - 2) * (n - 3) // 6]
+        for k in range(4):
+            assert np.all(np.bincount(prim[cls == k])[np.unique(prim[cls == k])] == sizes[k])
+        X, Y, Z = lv.X.T
+        inner = (X > 0) & (Y > 0) & (Z > 0) & (X < n) & (Y < n) & (Z < n)
+        diag = inner & (X == Y) & (Y == Z)
+        plane = inner & ~diag & ((X == Y) | (Y == Z) | (X == Z))
+        free = inner & (X != Y) & (Y != Z) & (X != Z)
+        assert np.all(cls[diag] == 1) and np.all(cls[plane] == 2) and np.all(cls[free] == 3)
+
+
+def test_hybrid_sweeps_are_textbook_block_gauss_seidel(box_r3):
+    """ordering='hybrid' (Section 3.4): the forward sweep from zero is
+    W_f^{-1} r with W_f = D + (the entries of A towards earlier classes, and
+    towards earlier colours inside the node's own primitive); entries towards
+    other primitives of the same class are left out (block Jacobi).  The
+    backward sweep keeps the class order and reverses the colours inside a
+    primitive (W_b).  Velocity: d = d1 + W_b^{-1}(r - A d1), d1 = W_f^{-1} r;
+    pressure: (D/omega + L_f) d = s.  Both closed forms are built densely
+    from the partition; the velocity operator is not symmetric (the paper's
+    'pseudo-symmetric' SHGS), and it differs from the colour ordering."""
+    from oracle.fem import primitives
+    cfg, _ = box_r3
+    xyz, tet, nu, tags = cfg.mesh()
+    H = build_hierarchy(xyz, tet, nu, tags, 3)
+    umg = UMG(H, ordering="hybrid")
+    l = 1
+    lv = H.levels[l]
+    cls, prim = primitives(lv, H.macro_int, H.tet)
+    col = lv.colour
+    earlier_cls = cls[None, :] < cls[:, None]
+    same_prim = (cls[None, :] == cls[:, None]) & (prim[None, :] == prim[:, None])
+    low_f = earlier_cls | (same_prim & (col[None, :] < col[:, None]))
+    low_b = earlier_cls | (same_prim & (col[None, :] > col[:, None]))
+    fr = np.nonzero(lv.free)[0]
+    A = lv.A.toarray()[np.ix_(fr, fr)]
+    D = np.diag(np.diag(A))
+    Wf = D + np.where(low_f[np.ix_(fr, fr)], A, 0.0)
+    Wb = D + np.where(low_b[np.ix_(fr, fr)], A, 0.0)
+    r = np.zeros(lv.N)
+    r[fr] = np.random.default_rng(12).normal(size=fr.shape[0])
+    d = umg.sgs(l, r)
+    d1 = np.linalg.solve(Wf, r[fr])
+    ref = d1 + np.linalg.solve(Wb, r[fr] - A @ d1)
+    assert np.allclose(d[fr], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+    assert np.all(d[lv.dirichlet] == 0.0)
+    # the smoother's operator S with d = S r is not symmetric
+    S = np.linalg.inv(Wf) + np.linalg.solve(Wb, np.eye(fr.shape[0]) - A @ np.linalg.inv(Wf))
+    assert np.abs(S - S.T).max() > 1e-6 * np.abs(S).max()
+    # ... and the colour ordering gives another result
+    dc = UMG(H).sgs(l, r)
+    assert np.abs(dc - d).max() > 1e-6 * np.abs(d).max()
+    # pressure: forward hybrid SOR
+    C = lv.C.toarray()
+    w = umg.omega
+    s = np.random.default_rng(13).normal(size=lv.N)
+    dp = umg.sor(l, s)
+    Wp = np.diag(np.diag(C)) / w + np.where(low_f, C, 0.0)
+    refp = np.linalg.solve(Wp, s)
+    assert np.allclose(dp, refp, rtol=1e-11, atol=1e-13 * np.abs(refp).max())
