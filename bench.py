@@ -491,6 +491,8 @@ def main():
     napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
     s.set_timing(False)
     vel_avg_ms = ms_vel / max(nvel, 1)
+    if nvel == 0:
+        raise RuntimeError("no finest-level velocity sweep was timed")
     vs = 8.0 if precision == 0 else 4.0
     # algorithmic bytes of one colour launch: one direction of the velocity
     # Gauss-Seidel reads u (3 values), f (3) and p and writes u (3) per finest

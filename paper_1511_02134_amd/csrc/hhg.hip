@@ -907,6 +907,11 @@ inline int residual_partials(const LevelDev<T>& v) {
     return (v.n >= SPLIT_MIN_N ? 4 : 1) * v.nv_nat + (v.nif + TPB - 1) / TPB;
 }
 
+// levels with at least this many intervals per macro edge evaluate RU and BP
+// by quad windows (fewer load instructions); smaller ones one vertex per lane
+// (more lanes for a latency-bound launch)
+constexpr int WIN_MIN_N = 32;
+
 template <typename T, int MODE>
 void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
@@ -920,6 +925,14 @@ void full_pass(hhg_ctx* c, int l, const T* x, const T* b, T* y, hipStream_t s) {
     if (MODE == MODE_RU || MODE == MODE_BP || MODE == MODE_BTN) ops(c, l, 0, 1, 0, 0);
     if (MODE == MODE_ARES) ops(c, l, 1, 0, 0, 0);
     if (MODE == MODE_SCHUR) ops(c, l, 0, 1, 1, 0);
+    if constexpr (MODE == MODE_RU || MODE == MODE_BP) {
+        if (v.n >= WIN_MIN_N) {
+            // unfused f - B^T p or B u - g on large levels: quad windows
+            hipLaunchKernelGGL((k_full<T, MODE, false, false, true>), dim3(ib + v.n_vtiles),
+                               dim3(TPB), 0, s, v, x, b, y, c->partials, ib, (T*)nullptr, -1, T(0));
+            return;
+        }
+    }
     if (MODE == MODE_APPLY || MODE == MODE_RES)
         launch_kx<T, (MODE == MODE_RES ? MODE_RES : MODE_APPLY), false>(c, v, ib, x, b, y, s);
     else if (MODE == MODE_ARES && dpath(c))
@@ -959,10 +972,6 @@ void fill_iterate(hhg_ctx* c, int l, T* x, hipStream_t s) {
 
 // RU with the velocity sweep of colour col, or BP with the pressure sweep of
 // colour col, in one launch (x is updated in place, t receives the pass)
-// levels with at least this many intervals per macro edge evaluate RU and BP
-// by quad windows (fewer load instructions); smaller ones one vertex per lane
-// (more lanes for a latency-bound launch)
-constexpr int WIN_MIN_N = 32;
 
 template <typename T, int MODE>
 void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
@@ -1079,6 +1088,8 @@ void hybrid_pass(hhg_ctx* c, int l, bool vel, bool backward, T* x, const T* rhs,
     const dim3 grid(v.n_vtiles);
     for (int q = 0; q < 4; ++q) {
         const int col = backward ? 3 - q : q;
+        Timed tm(c, vel ? HHG_K_VEL : HHG_K_PRES, s, l == c->L,
+                 vel ? c->bytes_vel[col] : c->bytes_pres[col]);
         if (vel && c->mi.general)
             hipLaunchKernelGGL((k_colour<T, true, false, true>), grid, dim3(TPB), 0, s, v, col, x, rhs,
                                omega, 0);
