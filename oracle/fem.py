@@ -38,6 +38,11 @@ Readings taken where the paper is silent:
     1/nu the Uzawa iteration diverges for macro viscosities around 0.1;
   * velocity Dirichlet nodes are the nodes on closed macro faces tagged
     Dirichlet; pressure is an unknown at every node.
+  * free-slip faces (tag 3; Section 6.1): their nodes, unless also on a
+    Dirichlet face, carry the point-wise constraint u . n = 0 with the
+    mass-conservative normal n_i = <grad phi_i, 1> / |.|, the velocity
+    column sum of b at the constant pressure, n_i = -(B^T 1)_i / |.|.  The
+    tangential stress condition is the natural one of the weak form.
 """
 from __future__ import annotations
 
@@ -48,6 +53,7 @@ import scipy.sparse as sp
 
 DELTA = 1.0 / 12.0          # PSPG parameter delta_T (Section 2.1)
 FACE_DIRICHLET = 1
+FACE_SLIP = 3
 
 
 # --------------------------------------------------------------------------
@@ -113,6 +119,8 @@ class Level:
     Xphys: np.ndarray = None   # [N,3] physical coordinates
     E: list = None             # D form only: E[k][l] coupling blocks (N x N)
     A2: sp.csr_matrix = None   # D form only: the 3N x 3N velocity block (component major)
+    slip: np.ndarray = None    # [N] bool, free-slip node (velocity tangential)
+    normal: np.ndarray = None  # [N,3] mass-conservative unit normal at slip nodes, 0 elsewhere
 
     @property
     def N(self):
@@ -181,13 +189,14 @@ def assemble_level(lv: Level, nu_macro, chunk=1 << 21, op="laplace"):
                          for k in range(3)], format="csr")
 
 
-def _dirichlet_nodes(X, n, macro_int, tet, face_bc):
-    """Nodes (integer coords X at scale n) on a closed Dirichlet macro face."""
+def _dirichlet_nodes(X, n, macro_int, tet, face_bc, tag=FACE_DIRICHLET):
+    """Nodes (integer coords X at scale n) on a closed macro face tagged `tag`
+    (Dirichlet by default)."""
     mask = np.zeros(X.shape[0], dtype=bool)
     Xl = X.astype(np.int64)
     for t in range(tet.shape[0]):
         for f in range(4):
-            if face_bc[t, f] != FACE_DIRICHLET:
+            if face_bc[t, f] != tag:
                 continue
             a, b, c = (macro_int[v].astype(np.int64) * n for v in np.delete(tet[t], f))
             nrm = np.cross(b - a, c - a)
@@ -244,7 +253,58 @@ def _make_level(Pint, tet_macro, R, macro_int, tet, face_bc, nu, op="laplace", m
     lv.Xphys = Pphys.reshape(-1, 3)[first]
     lv.colour = (X.sum(axis=1) % 4).astype(np.int64)
     assemble_level(lv, nu, op=op)
+    lv.slip = _dirichlet_nodes(X, n, macro_int, tet, face_bc, FACE_SLIP) & ~lv.dirichlet
+    lv.normal = np.zeros((lv.N, 3))
+    if lv.slip.any():
+        one = np.ones(lv.N)
+        g = -np.stack([lv.B[k].T @ one for k in range(3)], axis=1)     # <grad phi_i, 1>
+        gs = g[lv.slip]
+        lv.normal[lv.slip] = gs / np.linalg.norm(gs, axis=1, keepdims=True)
     return lv
+
+
+def project_slip(lv, v):
+    """Removes the normal component of the velocity rows v[:3] at the
+    free-slip nodes (in place): v_i <- (I - n_i n_i^T) v_i."""
+    if lv.slip is not None and lv.slip.any():
+        n = lv.normal[lv.slip]
+        vs = v[:3, lv.slip]
+        v[:3, lv.slip] = vs - n.T * np.sum(n.T * vs, axis=0)
+    return v
+
+
+def tangential_basis(lv):
+    """Sparse T [3 nf, m]: the velocity unknowns of the constrained space in
+    Cartesian components (component-major over the free nodes): one column
+    per component at nodes without the constraint, two tangent vectors
+    (orthonormal, perpendicular to n_i) at free-slip nodes."""
+    fr = np.nonzero(lv.free)[0]
+    nf = fr.shape[0]
+    rows, cols, vals = [], [], []
+    col = 0
+    pos = {int(i): q for q, i in enumerate(fr)}
+    for i in fr:
+        q = pos[int(i)]
+        if lv.slip is not None and lv.slip[i]:
+            nrm = lv.normal[i]
+            a = np.zeros(3)
+            a[np.argmin(np.abs(nrm))] = 1.0
+            t1 = a - np.dot(a, nrm) * nrm
+            t1 /= np.linalg.norm(t1)
+            t2 = np.cross(nrm, t1)
+            for t in (t1, t2):
+                for k in range(3):
+                    rows.append(k * nf + q)
+                    cols.append(col)
+                    vals.append(t[k])
+                col += 1
+        else:
+            for k in range(3):
+                rows.append(k * nf + q)
+                cols.append(col)
+                vals.append(1.0)
+                col += 1
+    return sp.csr_matrix((vals, (rows, cols)), shape=(3 * nf, col))
 
 
 def _prolongation(coarse: Level, Pc_int, fine: Level):

@@ -41,6 +41,14 @@ Readings taken (listed again in the design notes):
     3..0), not the class order, so forward + backward (SHGS) is not
     symmetric.  The paper uses a row-wise red-black order inside a
     primitive; the 4-colouring is the order the device can run in parallel.
+  * free-slip nodes (Section 6.1, fem.project_slip): the velocity lives in
+    the tangent plane.  The velocity rows of K x, of the right-hand side and
+    of a restricted residual are projected there, and so is a prolongated
+    correction; the velocity sweep updates the three components of a colour
+    together and projects the new values of its slip nodes (for the Laplace
+    form the 3x3 centre block is a multiple of the identity, so this is the
+    exact constrained point update).  The level-0 system is solved in the
+    tangential basis (fem.tangential_basis).
   * D form (a_2, Section 2.1): the velocity block couples the three
     components, so the velocity sweep is a point-block Gauss-Seidel: at each
     vertex of the colour the 3x3 diagonal block is solved exactly.  The
@@ -54,7 +62,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from .fem import Hierarchy
+from .fem import Hierarchy, project_slip, tangential_basis
 
 
 class UMG:
@@ -87,6 +95,9 @@ class UMG:
                     g["v"].append((iv, lv.A[iv], dA[iv]))
                 g["p"].append((ip, lv.C[ip], dC[ip]))
             self._gs.append(g)
+        self.slip = any(lv.slip is not None and lv.slip.any() for lv in H.levels)
+        if self.slip and (self.dform or ordering == "hybrid"):
+            raise ValueError("free-slip nodes: Laplace form with the colour ordering only")
         if ordering == "hybrid":
             if self.dform:
                 raise ValueError("hybrid ordering: Laplace form only")
@@ -135,7 +146,7 @@ class UMG:
             b[k] = lv.M @ f_nodal[k]
             b[k][lv.dirichlet] = 0.0
         b[3] = sum(lv.Gf[k] @ f_nodal[k] for k in range(3))
-        return b
+        return project_slip(lv, b)
 
     def apply(self, l, x):
         """y = K x on free velocity rows and all pressure rows; x carries the
@@ -156,6 +167,19 @@ class UMG:
         and every vertex solves its 3x3 diagonal block)."""
         d = np.zeros_like(r)
         order = list(range(4)) + list(range(3, -1, -1))
+        if r.ndim == 2 and not self.dform:
+            # the three components of a colour together, the new values of its
+            # free-slip nodes projected onto their tangent planes
+            lv = self.H.levels[l]
+            for c in order:
+                idx, rows, diag = self._gs[l]["v"][c]
+                d[:, idx] += (r[:, idx] - (rows @ d.T).T) / diag
+                sl = idx[lv.slip[idx]]
+                if sl.shape[0]:
+                    n = lv.normal[sl]
+                    ds = d[:, sl]
+                    d[:, sl] = ds - n.T * np.sum(n.T * ds, axis=0)
+            return d
         if self.ordering == "hybrid":
             self._hybrid_pass(l, "v", r, d, range(4))
             return self._hybrid_pass(l, "v", r, d, range(3, -1, -1))
@@ -197,6 +221,10 @@ class UMG:
             ru = np.stack([b[k] - au[k] - lv.B[k].T @ p for k in range(3)])
             ru[:, lv.dirichlet] = 0.0
             u += self.sgs(l, ru)
+        elif self.slip:
+            ru = np.stack([b[k] - lv.A @ u[k] - lv.B[k].T @ p for k in range(3)])
+            ru[:, lv.dirichlet] = 0.0
+            u += self.sgs(l, ru)
         else:
             for k in range(3):
                 ru = b[k] - lv.A @ u[k] - lv.B[k].T @ p
@@ -214,14 +242,29 @@ class UMG:
         c = self.H.levels[l - 1]
         rc = np.stack([P.T @ r[k] for k in range(4)])
         rc[:3, c.dirichlet] = 0.0
-        return rc
+        return project_slip(c, rc)
 
     def prolong(self, l, e):
         P = self.H.P[l]
-        return np.stack([P @ e[k] for k in range(4)])
+        return project_slip(self.H.levels[l], np.stack([P @ e[k] for k in range(4)]))
 
     # -- coarse grid -------------------------------------------------------
     def _coarse_system(self, lv):
+        """Dense level-0 matrix over the free velocity unknowns and all
+        pressures; with free-slip nodes, the velocity in the tangential
+        basis T (K_T = diag(T, I)^T K diag(T, I))."""
+        fr, K = self._coarse_cartesian(lv)
+        if self.slip:
+            T = tangential_basis(lv).toarray()
+            nv = 3 * fr.shape[0]
+            Z = np.zeros((T.shape[1] + lv.N, nv + lv.N))
+            Z[:T.shape[1], :nv] = T.T
+            Z[T.shape[1]:, nv:] = np.eye(lv.N)
+            self._coarse_T = T
+            K = Z @ K @ Z.T
+        return fr, K
+
+    def _coarse_cartesian(self, lv):
         fr = np.nonzero(lv.free)[0]
         nf, N = fr.shape[0], lv.N
         A = lv.A[fr][:, fr].toarray()
@@ -253,14 +296,19 @@ class UMG:
         lv = self.H.levels[0]
         fr, lu = self._coarse
         nf = fr.shape[0]
-        rhs = np.concatenate([b[0][fr], b[1][fr], b[2][fr], b[3]])
+        rv = np.concatenate([b[0][fr], b[1][fr], b[2][fr]])
+        if self.slip:
+            rv = self._coarse_T.T @ rv
+        rhs = np.concatenate([rv, b[3]])
         if self.H.project:
             rhs = np.append(rhs, 0.0)
         sol = sla.lu_solve(lu, rhs)
+        nv = rv.shape[0]
+        sv = sol[:nv] if not self.slip else self._coarse_T @ sol[:nv]
         x = np.zeros((4, lv.N))
         for k in range(3):
-            x[k][fr] = sol[k * nf:(k + 1) * nf]
-        x[3] = sol[3 * nf:3 * nf + lv.N]
+            x[k][fr] = sv[k * nf:(k + 1) * nf]
+        x[3] = sol[nv:nv + lv.N]
         return x
 
     # -- cycle -----------------------------------------------------------------
@@ -347,7 +395,7 @@ def apply_level(lv, x):
         y[k] = (au[k] if au is not None else lv.A @ x[k]) + lv.B[k].T @ x[3]
         y[k][lv.dirichlet] = 0.0
     y[3] = sum(lv.B[k] @ x[k] for k in range(3)) - lv.C @ x[3]
-    return y
+    return project_slip(lv, y)
 
 
 def direct_solve(lv, b, project, xbc=None):
@@ -376,19 +424,29 @@ def direct_solve(lv, b, project, xbc=None):
         blocks[3][k] = Bk
         blocks[k][3] = Bk.T
     blocks[3][3] = -lv.C
-    K = sp.bmat(blocks, format="lil")
+    K = sp.bmat(blocks, format="csr")
     rhs = np.concatenate([r[0][fr], r[1][fr], r[2][fr], r[3]])
+    slip = lv.slip is not None and lv.slip.any()
+    if slip:
+        # free-slip nodes: the velocity in the tangential basis
+        T = tangential_basis(lv)
+        Z = sp.block_diag([T, sp.identity(N)], format="csr")
+        K = Z.T @ K @ Z
+        rhs = Z.T @ rhs
+    K = K.tolil()
+    nv = K.shape[0] - N
     if project:
-        i0 = 3 * nf
+        i0 = nv
         K[i0, :] = 0.0
         K[:, i0] = 0.0
         K[i0, i0] = 1.0
         rhs[i0] = 0.0
     sol = spla.spsolve(K.tocsc(), rhs)
+    sv = T @ sol[:nv] if slip else sol[:nv]
     x = xd.copy()
     for k in range(3):
-        x[k][fr] = sol[k * nf:(k + 1) * nf]
-    x[3] = sol[3 * nf:3 * nf + N]
+        x[k][fr] = sv[k * nf:(k + 1) * nf]
+    x[3] = sol[nv:nv + N]
     if project:
         x[3] -= np.dot(lv.mass, x[3]) / lv.mass.sum()
     return x

@@ -31,6 +31,8 @@ tetrahedra, Section 4 and Table "iteration numbers and time-to-solution"):
      Dirichlet data on both spheres, random start (the paper's setting), fp64
   8  the same shell, R=4, the analytic solution of the efficiency study as
      forcing and Dirichlet data (a manufactured solution on the shell)
+  9  the same shell, R=5, free-slip on both spheres (Section 6.1: u . n = 0
+     with the mass-conservative normals), the forcing of workload 8
 
 For the shell the nodal arrays live on the lattice of the bounding box of the
 hollow cube; lattice points in the removed central cell are not vertices
@@ -47,6 +49,7 @@ import numpy as np
 FACE_INTERIOR = 0
 FACE_DIRICHLET = 1
 FACE_NATURAL = 2
+FACE_SLIP = 3
 
 
 def box_mesh(a: int):
@@ -145,9 +148,9 @@ def shell_coordinates(xyz, m: int = 3, r_in: float = 0.55, r_out: float = 1.0):
     return c / np.linalg.norm(c, axis=1, keepdims=True) * r[:, None]
 
 
-def boundary_face_tags(tet):
-    """Tag 1 (Dirichlet) on every face that belongs to one tetrahedron only, 0
-    on faces shared by two."""
+def boundary_face_tags(tet, tag=FACE_DIRICHLET):
+    """`tag` (Dirichlet by default) on every face that belongs to one
+    tetrahedron only, 0 on faces shared by two."""
     nt = tet.shape[0]
     count = {}
     for t in range(nt):
@@ -159,7 +162,7 @@ def boundary_face_tags(tet):
         for f in range(4):
             key = tuple(sorted(np.delete(tet[t], f).tolist()))
             if count[key] == 1:
-                tags[t, f] = FACE_DIRICHLET
+                tags[t, f] = tag
     return tags
 
 
@@ -338,13 +341,15 @@ class Workload:
     inflow: bool = False
     solution: str | None = None     # "tme": the analytic solution of the efficiency study
     kind: str = "box"               # "box" | "shell" (the spherical shell of Section 4.4)
+    slip: bool = False              # shell: free-slip instead of no-slip on both spheres
     extra: dict = field(default_factory=dict)
 
     # -- inputs ----------------------------------------------------------
     def mesh(self):
         if self.kind == "shell":
             xyz, tet = hollow_cube_mesh(3)
-            return xyz, tet, np.ones(tet.shape[0]), boundary_face_tags(tet)
+            tag = FACE_SLIP if self.slip else FACE_DIRICHLET
+            return xyz, tet, np.ones(tet.shape[0]), boundary_face_tags(tet, tag)
         xyz, tet = box_mesh(self.a)
         tags = face_tags(xyz, tet, self.a, self.natural_x)
         if self.nu_range is None:
@@ -422,4 +427,6 @@ WORKLOADS = {
     7: Workload("shell-R5-fp64", a=3, R=5, precision="fp64", forcing="zero", kind="shell"),
     8: Workload("shell-tme-R4-fp64", a=3, R=4, precision="fp64", forcing="tme", solution="tme",
                 kind="shell"),
+    9: Workload("shell-slip-R5-fp64", a=3, R=5, precision="fp64", forcing="tme", kind="shell",
+                slip=True),
 }
