@@ -74,7 +74,17 @@ typedef enum {
  *                 lie in no macro: a hole, such as the inside of a shell);
  *   nu  [nt]      per-macro viscosity > 0 (NULL: all 1);
  *   face_bc [nt][4] tag of the face opposite vertex f: 0 interior (shared by
- *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing);
+ *                 two macros), 1 Dirichlet velocity, 2 natural (do-nothing),
+ *                 3 free-slip (Section 6.1): u . n = 0 at the face's vertices
+ *                 (those on a Dirichlet face excepted) with the
+ *                 mass-conservative normal n_i = <grad phi_i, 1> / |.|, zero
+ *                 tangential stress.  The velocity rows of K x, the residual
+ *                 and the right-hand side of such a vertex are projected onto
+ *                 its tangent plane, and so are its smoothed values and
+ *                 transferred corrections; hhg_solve projects x first.  Needs
+ *                 the Laplace form, the colour ordering, the direct coarse
+ *                 solver and krylov = 0; hhg_grad and hhg_adjoint_rhs reject
+ *                 such meshes;
  *   phys [nv][3]  physical coordinates of the vertices (NULL: xyz; the
  *                 field was appended to the struct, callers must set it).  Every
  *                 macro carries its refinement affinely (Section 2.1: uniform
@@ -115,7 +125,7 @@ typedef struct {
                               hhg_set_viscosity, Gauss-Jordan elimination; one
                               matrix-vector product per solve; default);
                               1: the block-diagonal preconditioned MINRES above.
-                              Either way at most 8192 level-0 unknowns */
+                              Either way at most 16384 level-0 unknowns */
     int32_t krylov;       /* 1: reserve the ten finest-level vectors (4 fields each) of
                              hhg_pminres and hhg_scg; 0 (default): those calls return
                              HHG_EINVAL */
@@ -199,9 +209,10 @@ int64_t hhg_num_nodes(const hhg_ctx* ctx, int32_t level); /* lattice nodes */
 int64_t hhg_num_dofs(const hhg_ctx* ctx, int32_t level);  /* 3*free velocity nodes + nodes
                                                              (vertices only, no hole points) */
 int64_t hhg_num_interface(const hhg_ctx* ctx, int32_t level); /* vertices on macro faces */
-/* Integer lattice coordinates [N][3] and velocity Dirichlet flags [N] (either
+/* Integer lattice coordinates [N][3] and velocity boundary flags [N] (either
  * may be NULL) of the level's lattice points in lattice order, into host
- * arrays (N = hhg_num_nodes; a lattice point of a hole has flag 0). */
+ * arrays (N = hhg_num_nodes): 1 Dirichlet, 2 free-slip, 0 otherwise (also at
+ * the lattice points of a hole). */
 hhg_status hhg_node_info(const hhg_ctx* ctx, int32_t level, int32_t* ijk, int8_t* dirichlet);
 
 /* HHG primitive class (Section 3.4) of every lattice point of the level into

@@ -237,14 +237,21 @@ class Solver:
     def num_interface(self, level=None):
         return lib.hhg_num_interface(self.ctx, self.L if level is None else level)
 
-    def node_info(self, level=None):
+    def node_flags(self, level=None):
+        """Lattice coordinates [N,3] and boundary flags [N] (1 Dirichlet, 2
+        free-slip, 0 otherwise)."""
         level = self.L if level is None else level
         N = self.num_nodes(level)
         ijk = np.zeros((N, 3), dtype=np.int32)
         d = np.zeros(N, dtype=np.int8)
         _check(lib.hhg_node_info(self.ctx, level, ijk.ctypes.data_as(ctypes.c_void_p),
                                  d.ctypes.data_as(ctypes.c_void_p)), self.ctx)
-        return ijk, d.astype(bool)
+        return ijk, d
+
+    def node_info(self, level=None):
+        """Lattice coordinates [N,3] and the velocity Dirichlet mask [N]."""
+        ijk, d = self.node_flags(level)
+        return ijk, d == 1
 
     def mass_weights(self, level=None):
         level = self.L if level is None else level

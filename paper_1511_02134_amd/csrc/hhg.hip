@@ -239,6 +239,10 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
     if (!opts_ok(&o, &err)) return fail(c, HHG_EINVAL, err);
     if (!validate_mesh(mesh, &c->mi, &err)) return fail(c, HHG_EINVAL, err);
     c->mi.lap_blocks = c->mi.general && o.op == 0;
+    if (c->mi.slip && (o.op != 0 || o.ordering != 0 || o.krylov != 0 || o.coarse_solver != 0))
+        return fail(c, HHG_EINVAL,
+                    "free-slip faces need the Laplace form, the colour ordering, the direct coarse "
+                    "solver and no Krylov vectors");
     c->opts = o;
     c->R = R;
     c->L = R - 2;
@@ -390,6 +394,7 @@ void fill_view(hhg_ctx* c, int l, LevelDev<T>& v) {
     v.if_flag = a.if_flag;
     for (int q = 0; q < 5; ++q) v.col_start[q] = h.col_start[q];
     for (int q = 0; q < 4; ++q) v.vel_end[q] = h.vel_end[q];
+    for (int q = 0; q < 4; ++q) v.slip_beg[q] = h.slip_beg[q];
     v.rif_tap = a.rif_tap;
     v.ncomp = h.ncomp;
     v.cstride = mirror_stride(h.ncomp);
@@ -1009,8 +1014,10 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
     LevelDev<T>& v = view<T>(c, l);
     const int cnt = vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
     // velocity sweeps: a lane per interface vertex and component (Laplace
-    // form), four lanes per interface vertex (D form)
-    const int ib = iface_blocks(!vel ? cnt : c->opts.op == 1 ? 4 * cnt : 3 * cnt);
+    // form; then a lane per free-slip vertex), four lanes per interface vertex
+    // (D form)
+    const int nslip = v.col_start[col + 1] - v.slip_beg[col];
+    const int ib = iface_blocks(!vel ? cnt : c->opts.op == 1 ? 4 * cnt : 3 * cnt + nslip);
     const int grid = ib + v.n_vtiles;
     const bool finest = l == c->L;
     ops(c, l, vel ? 0.25 : 0.0, 0, vel ? 0.0 : 0.25, 0);
@@ -1135,6 +1142,19 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
         full_pass<T, MODE_RU>(c, l, x, b, t, s);
     } else {
         full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
+        if (c->mi.slip) {
+            // the colour-0 free-slip vertices, which the fused pass leaves out
+            LevelDev<T>& v = view<T>(c, l);
+            const int ns = v.col_start[1] - v.slip_beg[0];
+            if (ns > 0) {
+                if (c->mi.general)
+                    hipLaunchKernelGGL((k_slip_colour<T, true>), dim3((ns + TPB - 1) / TPB),
+                                       dim3(TPB), 0, s, v, 0, x, (const T*)t);
+                else
+                    hipLaunchKernelGGL((k_slip_colour<T, false>), dim3((ns + TPB - 1) / TPB),
+                                       dim3(TPB), 0, s, v, 0, x, (const T*)t);
+            }
+        }
     }
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
@@ -1479,7 +1499,7 @@ hhg_status hhg_node_info(const hhg_ctx* c, int32_t l, int32_t* ijk, int8_t* dir)
             ijk[3 * v + 1] = (int32_t)((v / h.lat[0]) % h.lat[1]);
             ijk[3 * v + 2] = (int32_t)(v / ((int64_t)h.lat[0] * h.lat[1]));
         }
-        if (dir) dir[v] = h.node_dir[v];
+        if (dir) dir[v] = h.node_dir[v] ? 1 : h.node_slip[v] ? 2 : 0;
     }
     return HHG_OK;
 }
@@ -1808,6 +1828,12 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     hhg_solve_info* I = info ? info : &loc;
     std::memset(I, 0, sizeof(*I));
     reset_ops(c);
+    if (c->mi.slip) {
+        // the iterate starts in the constrained space (u . n = 0 on free-slip vertices)
+        LevelDev<double>& vf = view<double>(c, c->L);
+        hipLaunchKernelGGL(k_slip_project<double>, dim3((vf.nif + TPB - 1) / TPB), dim3(TPB), 0, s,
+                           vf, x);
+    }
     hipEvent_t e0 = next_event(c), e1 = next_event(c);
     double* r = c->A[c->L].r64;
     residual_norm<double>(c, c->L, x, b, r, c->scal, s);
@@ -1907,6 +1933,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
 hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, double* dnu,
                     void* df, hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->mi.slip) return fail(c, HHG_EINVAL, "the gradient does not handle free-slip faces");
     CHECK_PTR(c, x);
     CHECK_PTR(c, lam);
     CHECK_PTR(c, dnu);
@@ -1926,6 +1953,7 @@ hhg_status hhg_grad(hhg_ctx* c, const void* x, const void* lam, const void* f, d
 
 hhg_status hhg_adjoint_rhs(hhg_ctx* c, const void* g, void* y, hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->mi.slip) return fail(c, HHG_EINVAL, "the adjoint does not handle free-slip faces");
     CHECK_PTR(c, g);
     CHECK_PTR(c, y);
     if (g == y) return fail(c, HHG_EINVAL, "g and rhs must not alias");
@@ -2198,13 +2226,16 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
         CK((h.slot_node[s] >= 0) == (seen[s] == 1), "closure tiles and slot map disagree");
     // interface vertices
     for (int cc = 0; cc < 4; ++cc) {
-        CK(h.col_start[cc] <= h.vel_end[cc] && h.vel_end[cc] <= h.col_start[cc + 1], "colour ranges");
+        CK(h.col_start[cc] <= h.vel_end[cc] && h.vel_end[cc] <= h.slip_beg[cc] &&
+               h.slip_beg[cc] <= h.col_start[cc + 1],
+           "colour ranges");
         for (int t = h.col_start[cc]; t < h.col_start[cc + 1]; ++t) {
             int64_t lat = h.if_lat[t];
             int X = (int)(lat % h.lat[0]), Y = (int)((lat / h.lat[0]) % h.lat[1]),
                 Z = (int)(lat / ((int64_t)h.lat[0] * h.lat[1]));
             CK(((X + Y + Z) & 3) == cc, "interface colour");
-            CK((h.if_flag[t] & 1) == (t >= h.vel_end[cc] ? 1 : 0), "interface Dirichlet order");
+            CK(h.if_flag[t] == (t < h.vel_end[cc] ? 0 : t < h.slip_beg[cc] ? 1 : 2),
+               "interface order: free, Dirichlet, free-slip");
             CK(h.slot_node[h.if_self[t]] == lat, "interface self slot");
             for (int q = h.if_cptr[t]; q < h.if_cptr[t + 1]; ++q)
                 CK(h.if_copy[q] >= 0 && h.if_copy[q] < h.len && h.slot_node[h.if_copy[q]] == lat,
@@ -2321,6 +2352,7 @@ hhg_status hhg_kernel_time(hhg_ctx* c, int32_t cls, int64_t* launches, double* m
 hhg_status hhg_vel_cycle(hhg_ctx* c, int32_t nu1, int32_t nu2, void* x, const void* b,
                          hhg_stream stream) {
     CHECK_DEV(c);
+    if (c->mi.slip) return fail(c, HHG_EINVAL, "the velocity cycle does not handle free-slip faces");
     CHECK_PTR(c, x);
     CHECK_PTR(c, b);
     if (x == b) return fail(c, HHG_EINVAL, "x and b must not alias");

@@ -35,7 +35,11 @@ constexpr int ST_MASSNU = 228; // sum over the tetrahedra T around x of (|T|/4) 
 // and the inverse of the 3x3 centre block (row major) follows.
 constexpr int ST_A2 = 232;
 constexpr int ST_DINV = 367;
-constexpr int ST_SIZE = 376;
+// mass-conservative normal of a free-slip vertex (Section 6.1): -(B^T 1)
+// over the record's velocity rows, normalised (interface records; zero where
+// B^T 1 vanishes)
+constexpr int ST_NRM = 376;
+constexpr int ST_SIZE = 379;
 
 // Per-macro one-sided stencils for the viscosity gradient: the part of A, C
 // and G that comes from the fine tetrahedra of one macro only, at unit
@@ -95,9 +99,12 @@ struct LevelDev {
     const int32_t* if_sid;   // [nif] stencil id
     const int32_t* if_cptr;  // [nif+1]
     const int32_t* if_copy;  // all slots of the vertex
-    const int32_t* if_flag;  // bit 0: velocity Dirichlet
+    const int32_t* if_flag;  // bit 0: velocity Dirichlet, bit 1: free-slip (u . n = 0)
     int32_t col_start[5];    // interface range of each colour
     int32_t vel_end[4];      // end of velocity-free vertices inside colour c
+    int32_t slip_beg[4];     // start of the free-slip vertices inside colour c
+                             // (free, Dirichlet and free-slip vertices follow
+                             // each other in every colour)
     const T* st;             // stencil records
     const T* gst;            // gradient one-sided stencils [nm][16][GR_SIZE]
     // restriction of coarse interface vertices (this level as the coarse one):

@@ -310,8 +310,8 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
         m.nu = nu;
         for (int f = 0; f < 4; ++f) {
             int8_t b = mesh->face_bc[4 * t + f];
-            if (b < 0 || b > 2) {
-                *err = "face_bc entries must be 0, 1 or 2";
+            if (b < 0 || b > 3) {
+                *err = "face_bc entries must be 0, 1, 2 or 3";
                 return false;
             }
             m.bc[f] = b;
@@ -345,6 +345,7 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
             faces[k].push_back({t, f});
         }
     bool natural = false;
+    out->slip = false;
     for (auto& kv : faces) {
         auto& lst = kv.second;
         if (lst.size() > 2) {
@@ -365,6 +366,7 @@ bool validate_mesh(const hhg_mesh* mesh, MeshInfo* out, std::string* err) {
                 return false;
             }
             if (b == 2) natural = true;
+            if (b == 3) out->slip = true;
             // the face must lie in a plane of the bounding box
             bool onplane = false;
             for (int c = 0; c < 3 && !onplane; ++c)
@@ -446,6 +448,7 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
     L.node_slot.assign(L.N, -1);
     L.node_sid.assign(L.N, 0);
     L.node_dir.assign(L.N, 0);
+    L.node_slip.assign(L.N, 0);
 
     struct Ent {
         int64_t lat;
@@ -481,7 +484,7 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
     struct KeyInfo {
         int32_t id;
         int route[15];   // copy index that contains X + d_g, or -1
-        bool dirichlet;
+        bool dirichlet, slip;
     };
     std::map<Key, KeyInfo> keymap;
     L.keys.clear();
@@ -502,12 +505,15 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         if (it == keymap.end()) {
             KeyInfo ki;
             ki.id = (int32_t)L.keys.size();
-            ki.dirichlet = false;
+            ki.dirichlet = ki.slip = false;
             for (auto& mp : key) {
                 const MacroInfo& M = mi.macros[mp.first];
-                for (int f = 0; f < 4; ++f)
+                for (int f = 0; f < 4; ++f) {
                     if ((mp.second >> f & 1) && M.bc[f] == 1) ki.dirichlet = true;
+                    if ((mp.second >> f & 1) && M.bc[f] == 3) ki.slip = true;
+                }
             }
+            if (ki.dirichlet) ki.slip = false;   // no-slip wins where the faces meet
             for (int g = 0; g < 15; ++g) {
                 ki.route[g] = -1;
                 double d[3] = {(double)GDIR[g][0], (double)GDIR[g][1], (double)GDIR[g][2]};
@@ -530,7 +536,7 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         int X[3] = {(int)(lat % L.lat[0]), (int)((lat / L.lat[0]) % L.lat[1]),
                     (int)(lat / ((int64_t)L.lat[0] * L.lat[1]))};
         nd.colour = (X[0] + X[1] + X[2]) & 3;
-        nd.flag = ki.dirichlet ? 1 : 0;
+        nd.flag = ki.dirichlet ? 1 : ki.slip ? 2 : 0;
         nd.self = ents[g0].slot;
         nd.sid = nm + ki.id;
         for (size_t e = g0; e < g1; ++e) nd.copies.push_back(ents[e].slot);
@@ -552,7 +558,8 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         }
         L.node_slot[lat] = nd.self;
         L.node_sid[lat] = nd.sid;
-        L.node_dir[lat] = (int8_t)nd.flag;
+        L.node_dir[lat] = (int8_t)(nd.flag == 1);
+        L.node_slip[lat] = (int8_t)(nd.flag == 2);
         nodes.push_back(std::move(nd));
         g0 = g1;
     }
@@ -592,6 +599,8 @@ bool build_level(const MeshInfo& mi, int R, int block_order, HostLevel* out, std
         int e = L.col_start[c];
         while (e < L.col_start[c + 1] && L.if_flag[e] == 0) ++e;
         L.vel_end[c] = e;
+        while (e < L.col_start[c + 1] && L.if_flag[e] == 1) ++e;
+        L.slip_beg[c] = e;
     }
     // Compact mirror: interface vertices keep their list index; the volume
     // vertices they couple to follow.  Halo indices are handed out tap by tap
@@ -779,6 +788,19 @@ bool compute_stencils(const MeshInfo& mi, HostLevel* Lp, std::string* err) {
             return false;
         if (mi.lap_blocks) laplace_blocks(rec);
         finish_record(rec);
+        // mass-conservative normal <grad phi_x, 1> = -(B^T 1)_x (Section 6.1)
+        double nv[3], nn = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int g = 0; g < 15; ++g) acc += rec[ST_BT + 15 * k + g];
+            nv[k] = -acc;
+            nn += nv[k] * nv[k];
+        }
+        nn = std::sqrt(nn);
+        double scale = 0.0;
+        for (int g = 0; g < 15; ++g)
+            for (int k = 0; k < 3; ++k) scale = std::max(scale, std::fabs(rec[ST_BT + 15 * k + g]));
+        for (int k = 0; k < 3; ++k) rec[ST_NRM + k] = nn > 1e-12 * scale ? nv[k] / nn : 0.0;
     }
     // one-sided per-macro stencils at unit viscosity for the gradient
     for (int m = 0; m < nm; ++m) {
@@ -886,11 +908,17 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
     C.N = N;
     std::vector<int32_t> vidx(N, -1);
     C.vel_node.clear();
+    C.nslip = 0;
     for (int v = 0; v < N; ++v)
         if (!L.node_dir[C.node_lat[v]]) {
             vidx[v] = (int32_t)C.vel_node.size();
             C.vel_node.push_back(v);
+            if (L.node_slip[C.node_lat[v]]) ++C.nslip;
         }
+    if (C.nslip > 0 && (!direct || schur || dform)) {
+        *err = "free-slip boundaries need the direct coarse solver and the Laplace form";
+        return false;
+    }
     const int nfv = (int)C.vel_node.size();
     C.nfv = nfv;
     C.nd = 3 * nfv + N;
@@ -957,9 +985,13 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
         }
         C.rowptr.push_back((int32_t)C.col.size());
     }
-    // dense inverse of the SPD free-free block of A by Cholesky
-    std::vector<double> Lc(A);
-    for (int j = 0; j < nfv; ++j) {
+    // dense inverse of the SPD free-free block of A by Cholesky (the MINRES
+    // preconditioner and the velocity cycle's coarse solve; neither runs on
+    // meshes with free-slip faces)
+    C.ainv.clear();
+    std::vector<double> Lc(mi.slip ? 0 : A.size());
+    if (!mi.slip) Lc = A;
+    for (int j = 0; j < (mi.slip ? 0 : nfv); ++j) {
         double d = Lc[(size_t)j * nfv + j];
         for (int q = 0; q < j; ++q) d -= Lc[(size_t)j * nfv + q] * Lc[(size_t)j * nfv + q];
         if (!(d > 0.0)) {
@@ -974,9 +1006,9 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
             Lc[(size_t)i * nfv + j] = s / d;
         }
     }
-    C.ainv.assign((size_t)nfv * nfv, 0.0);
+    if (!mi.slip) C.ainv.assign((size_t)nfv * nfv, 0.0);
     std::vector<double> y(nfv);
-    for (int c = 0; c < nfv; ++c) {
+    for (int c = 0; c < (mi.slip ? 0 : nfv); ++c) {
         for (int i = 0; i < nfv; ++i) {
             double s = (i == c) ? 1.0 : 0.0;
             for (int q = 0; q < i; ++q) s -= Lc[(size_t)i * nfv + q] * y[q];
@@ -1106,6 +1138,34 @@ bool build_coarse(const MeshInfo& mi, const HostLevel& L, bool direct, bool schu
                 K[(size_t)(3 * nfv + v) * nb + nd] = m;
                 K[(size_t)nd * nb + 3 * nfv + v] = m;
             }
+        // free-slip vertices: Q K Q + a (I - Q) on their three velocity rows
+        // and columns, Q = I - n n^T, a the centre tap of A (a scale like the
+        // rest of the row); the normal component then solves to zero for a
+        // right-hand side without one, and the rest is the constrained system
+        for (int iv = 0; iv < nfv; ++iv) {
+            const int v = C.vel_node[iv];
+            if (!L.node_slip[C.node_lat[v]]) continue;
+            const double* nrm = rec_of(v) + ST_NRM;
+            double Q[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Q[a][b] = (a == b ? 1.0 : 0.0) - nrm[a] * nrm[b];
+            const size_t r[3] = {(size_t)iv, (size_t)(nfv + iv), (size_t)(2 * nfv + iv)};
+            for (int q = 0; q < nb; ++q) {   // rows
+                double o[3], w[3];
+                for (int a = 0; a < 3; ++a) o[a] = K[r[a] * nb + q];
+                for (int a = 0; a < 3; ++a) w[a] = Q[a][0] * o[0] + Q[a][1] * o[1] + Q[a][2] * o[2];
+                for (int a = 0; a < 3; ++a) K[r[a] * nb + q] = w[a];
+            }
+            for (int q = 0; q < nb; ++q) {   // columns
+                double o[3], w[3];
+                for (int a = 0; a < 3; ++a) o[a] = K[(size_t)q * nb + r[a]];
+                for (int a = 0; a < 3; ++a) w[a] = o[0] * Q[0][a] + o[1] * Q[1][a] + o[2] * Q[2][a];
+                for (int a = 0; a < 3; ++a) K[(size_t)q * nb + r[a]] = w[a];
+            }
+            const double aii = rec_of(v)[ST_A];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) K[r[a] * nb + r[b]] += aii * nrm[a] * nrm[b];
+        }
     }
     C.pdinv.resize(N);
     C.mass.resize(N);

@@ -29,6 +29,7 @@ struct MeshInfo {
     std::vector<MacroInfo> macros;
     int ext[3];      // bounding box extents (macro units), origin at 0
     bool project;    // pressure has a null space (no natural face)
+    bool slip = false;   // some face is free-slip (tag 3)
     bool general;    // physical coordinates given: general 15-point A and C
     bool holes;      // some lattice points of the bounding box lie in no macro
     // the coupled velocity blocks of the records (ST_A2, ST_DINV) hold the
@@ -57,6 +58,7 @@ struct HostLevel {
     std::vector<int64_t> if_lat;
     int32_t col_start[5] = {0, 0, 0, 0, 0};
     int32_t vel_end[4] = {0, 0, 0, 0};
+    int32_t slip_beg[4] = {0, 0, 0, 0};   // first free-slip vertex of colour c
     std::vector<Key> keys;                 // interface stencil id - nm -> key
     std::vector<double> st;                // (nm + keys) * ST_SIZE
     std::vector<double> st_vol_global;     // nm * ST_SIZE, volume stencils in global order
@@ -65,6 +67,7 @@ struct HostLevel {
     std::vector<int32_t> node_slot;        // [N] primary slot
     std::vector<int32_t> node_sid;         // [N] stencil id (interface) or -(m+1) (volume of m)
     std::vector<int8_t> node_dir;          // [N] velocity Dirichlet
+    std::vector<int8_t> node_slip;         // [N] free-slip (velocity tangential)
     std::vector<int32_t> rif_fine;         // [nif] index in the finer level's interface list
     // [15][nif] fine slots that the restriction sums at each interface vertex:
     // the coincident vertex, then its 14 neighbours (-1 where the finer
@@ -138,10 +141,11 @@ struct CoarseHost {
                                     // free velocity block
     std::vector<double> mass;       // [N] int phi_i
     std::vector<int32_t> vel_node;  // [nfv] vertex of each compact velocity vertex
+    int32_t nslip = 0;              // free-slip vertices among them
     std::vector<int32_t> node_slot; // [N]
     std::vector<int32_t> node_cptr, node_copy;   // every slot of each vertex
 };
-constexpr int COARSE_DIRECT_MAX = 8192;   // level-0 unknowns
+constexpr int COARSE_DIRECT_MAX = 16384;   // level-0 unknowns (the staged b0 of the direct solve fits the LDS)
 // direct: the bordered matrix (kb); schur: the dense Schur complement
 // inverse (sinv) of the MINRES preconditioner; dform: coupled velocity rows
 bool build_coarse(const MeshInfo& mi, const HostLevel& L0, bool direct, bool schur, bool dform,

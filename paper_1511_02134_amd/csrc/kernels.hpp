@@ -231,6 +231,69 @@ __device__ __forceinline__ void iface_colour(const LevelDev<T>& L, const T* __re
     }
 }
 
+// Free-slip vertices (Section 6.1): the velocity lives in the tangent plane
+// of the record's mass-conservative normal; v <- (I - n n^T) v.
+template <typename T>
+__device__ __forceinline__ void tangential(const T* __restrict__ nrm, T v[3]) {
+    const T d = nrm[0] * v[0] + nrm[1] * v[1] + nrm[2] * v[2];
+    v[0] -= d * nrm[0];
+    v[1] -= d * nrm[1];
+    v[2] -= d * nrm[2];
+}
+
+// The free-slip interface vertex t of a velocity colour sweep: the point
+// update of all three components (a_1: the centre block is a_xx I), then its
+// projection onto the tangent plane; every copy and the mirror are written.
+template <typename T, bool GEN>
+__device__ __forceinline__ void slip_colour(const LevelDev<T>& L, int t, T* __restrict__ x,
+                                            const T* __restrict__ rhs) {
+    constexpr int NT = GEN ? 14 : 6;
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
+    const int nif = L.nif;
+    const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+    const int self = L.if_self[t];
+    int nb[NT];
+#pragma unroll
+    for (int g = 0; g < NT; ++g) nb[g] = L.if_tap[g * nif + t];
+    T v[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const T* u = L.cx + f * cs;
+        T acc = T(0);
+#pragma unroll
+        for (int g = 0; g < NT; ++g) acc += st[ST_A + 1 + g] * u[nb[g]];
+        v[f] = (rhs[f * len + self] - acc) * st[ST_INVA];
+    }
+    tangential(st + ST_NRM, v);
+    for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) x[f * len + L.if_copy[q]] = v[f];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) L.cx[f * cs + t] = v[f];
+}
+
+// the free-slip vertices of colour c alone (the colour-0 sweep that the
+// fused f - B^T p pass leaves to them)
+template <typename T, bool GEN>
+__global__ void k_slip_colour(LevelDev<T> L, int c, T* __restrict__ x, const T* __restrict__ rhs) {
+    const int t = L.slip_beg[c] + (int)blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (t < L.col_start[c + 1]) slip_colour<T, GEN>(L, t, x, rhs);
+}
+
+// x <- (I - n n^T) x on the velocity of every free-slip vertex, all copies
+template <typename T>
+__global__ void k_slip_project(LevelDev<T> L, T* __restrict__ x) {
+    const int t = (int)blockIdx.x * blockDim.x + (int)threadIdx.x;
+    if (t >= L.nif || !(L.if_flag[t] & 2)) return;
+    const size_t len = (size_t)L.len;
+    const int self = L.if_self[t];
+    T v[3] = {x[self], x[len + self], x[2 * len + self]};
+    tangential(L.st + (size_t)L.if_sid[t] * ST_SIZE + ST_NRM, v);
+    for (int q = L.if_cptr[t]; q < L.if_cptr[t + 1]; ++q)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) x[f * len + L.if_copy[q]] = v[f];
+}
+
 // Colour sweeps keep the mirror of x current: a level's smoothing starts
 // with a current mirror (refreshed, filled or written by the prolongation).
 // DOP: point-block velocity sweeps (D form); GEN: sweeps over all 15 taps of
@@ -364,11 +427,17 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
     if (VEL && !DOP) {
         // a lane per interface vertex and velocity component: the scattered
         // loads of a colour's interface vertices spread over three times as
-        // many workgroups (on small levels they are the launch's longest path)
-        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, t = t0 + q / 3, f = q % 3;
-        if (t >= tend) return;
-        iface_colour<T, VEL, GEN>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f,
-                                  f + 1);
+        // many workgroups (on small levels they are the launch's longest path);
+        // then a lane per free-slip vertex (three components and the projection)
+        const int q = (int)blockIdx.x * TPB + (int)threadIdx.x, nfc = tend - t0;
+        if (q < 3 * nfc) {
+            const int t = t0 + q / 3, f = q % 3;
+            iface_colour<T, VEL, GEN>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega, f,
+                                      f + 1);
+            return;
+        }
+        const int ts = L.slip_beg[c] + (q - 3 * nfc);
+        if (ts < L.col_start[c + 1]) slip_colour<T, GEN>(L, ts, x, rhs);
         return;
     }
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
@@ -887,6 +956,9 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     const bool dir = (L.if_flag[t] & 1) != 0;
     eval_node<T, MODE, DOP>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out, fa,
                             fb);
+    // velocity rows of a free-slip vertex: their tangential part
+    if ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_RHS) && (L.if_flag[t] & 2))
+        tangential(st + ST_NRM, out);
     if (FUSE && t >= L.col_start[fcol] &&
         t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
         const int c0 = L.if_cptr[t];
@@ -1152,6 +1224,26 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
     for (int g = 0; g < 14; ++g) nb[g] = C.rif_tap[(g + 1) * nif + t];
     const bool dir = (C.if_flag[t] & 1) != 0;
     const int c0 = C.if_cptr[t], c1 = C.if_cptr[t + 1];
+    if (f < 3 && (C.if_flag[t] & 2)) {
+        // free-slip vertex: lane 0 restricts the three velocity fields and
+        // keeps their tangential part
+        if (f > 0) return;
+        T w[3];
+#pragma unroll
+        for (int ff = 0; ff < 3; ++ff) {
+            const T* v = rf + ff * lf;
+            T acc = T(0);
+#pragma unroll
+            for (int g = 0; g < 14; ++g)
+                if (nb[g] >= 0) acc += v[nb[g]];
+            w[ff] = v[self] + T(0.5) * acc;
+        }
+        tangential(C.st + (size_t)C.if_sid[t] * ST_SIZE + ST_NRM, w);
+        for (int q = c0; q < c1; ++q)
+#pragma unroll
+            for (int ff = 0; ff < 3; ++ff) bc[ff * lc + C.if_copy[q]] = w[ff];
+        return;
+    }
     const T* v = rf + f * lf;
     T acc = T(0);
 #pragma unroll
@@ -1209,28 +1301,26 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     // velocity slots kept by SET: those of Dirichlet vertices (interface
     // vertices, so their mirror entry is their list index)
     const bool keep = SET && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 1);
+    // free-slip vertex: the interpolated velocity keeps its tangential part
+    const bool slip = NF >= 3 && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 2);
     const int pi = i & 1, pj = j & 1, pk = k & 1;
+    T e[NF];
     if ((pi | pj | pk) == 0) {
         const int sc = slot_of(C.slab_base, C.n, mbc, i >> 1, j >> 1, k >> 1);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            T v = ec[f * lc + sc];
-            if (!SET)
-                v += xf[f * lf + sf];
-            else if (keep && f < 3)
-                v = xf[f * lf + sf];
-            xf[f * lf + sf] = v;
-            if (cm >= 0) F.cx[f * cs + cm] = v;
-        }
-        return;
+        for (int f = 0; f < NF; ++f) e[f] = ec[f * lc + sc];
+    } else {
+        int di, dj, dk;
+        parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
+        const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
+        const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) e[f] = T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
     }
-    int di, dj, dk;
-    parity_dir(pi | (pj << 1) | (pk << 2), &di, &dj, &dk);
-    const int sa = slot_of(C.slab_base, C.n, mbc, (i - di) >> 1, (j - dj) >> 1, (k - dk) >> 1);
-    const int sb2 = slot_of(C.slab_base, C.n, mbc, (i + di) >> 1, (j + dj) >> 1, (k + dk) >> 1);
+    if (slip) tangential(F.st + (size_t)F.if_sid[cm] * ST_SIZE + ST_NRM, e);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        T v = T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
+        T v = e[f];
         if (!SET)
             v += xf[f * lf + sf];
         else if (keep && f < 3)

@@ -221,3 +221,26 @@ def test_plan_rejects_bad_physical_coordinates():
     flat = bxyz.copy()
     flat[:, 2] = 0.0                                      # every macro degenerate
     _expect_einval(bxyz, btet, bnu, btags, phys=flat)
+
+
+@pytest.mark.parametrize("cid", [8, 9])
+def test_slip_flags_match_oracle(cid):
+    """Free-slip faces (tag 3): the library's free-slip and Dirichlet vertices
+    are the oracle's on every level; the interface lists keep free, Dirichlet
+    and free-slip vertices in that order inside each colour (layout check);
+    options that do not handle free-slip faces are rejected."""
+    R = 4
+    cfg = W.WORKLOADS[cid].with_R(R)
+    xyz, tet, nu, tags = cfg.mesh()
+    phys = cfg.physical()
+    s = P.Solver(xyz, tet, nu, tags, R, host_only=True, phys=phys)
+    s.check_layout()
+    H = build_hierarchy(xyz, tet, nu, tags, R, phys=phys)
+    for l, lv in enumerate(H.levels):
+        _, flags = s.node_flags(l)
+        assert np.array_equal(flags[lv.lat] == 1, lv.dirichlet)
+        assert np.array_equal(flags[lv.lat] == 2, lv.slip)
+        assert s.num_dofs(l) == lv.ndofs()
+    if cid == 9:
+        for bad in ({"op": 1}, {"ordering": 1}, {"coarse_solver": 1}, {"krylov": 1}):
+            assert "free-slip" in _expect_einval(xyz, tet, nu, tags, R=3, phys=phys, **bad)
