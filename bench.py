@@ -267,18 +267,19 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     print(json.dumps(line), flush=True)
 
 
-def run_shell(R: int, steps: int, warmup: int, ordering: int = 0):
+def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = False):
     """The spherical shell 0.55 < |x| < 1 (Section 4.4) as 156 affinely mapped
-    macros: f = 0, homogeneous Dirichlet data on both spheres, a seeded random
-    start (the paper's setting), variable V(3,3) to a 1e-8 relative residual
-    and the direct coarse solver.  Reports DoFs solved per second, the phase
+    macros: f = 0, homogeneous Dirichlet data on both spheres (or, with slip,
+    free-slip there: Section 6.1), a seeded random start (the paper's
+    setting), variable V(3,3) to a 1e-8 relative residual and the direct
+    coarse solver.  Reports DoFs solved per second, the phase
     split of one solve and the mean time and algorithmic HBM rate of the
     finest velocity colour sweep (15-tap stencils)."""
     import torch
     import workloads as W
     import paper_1511_02134_amd as P
 
-    cfg = W.WORKLOADS[7].with_R(R)
+    cfg = W.WORKLOADS[9 if slip else 7].with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
     t0 = time.perf_counter()
     s = P.Solver(xyz, tet, nu, tags, R, phys=cfg.physical(), cycle=1, ordering=ordering)
@@ -311,7 +312,9 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0):
     line = {"metric": "Stokes DoFs solved/s to 1e-8 rel. residual (spherical shell)",
             "value": dofs / (ms * 1e-3), "unit": "DoF/s", "ms_per_step": ms,
             "steps": steps, "warmup": warmup, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"shell-R{R}-fp64", "mesh": "spherical shell 0.55<|x|<1, "
+            "config": {"workload": f"shell{'-slip' if slip else ''}-R{R}-fp64",
+                       "boundary": "free-slip (mass-conservative normals)" if slip else "no-slip",
+                       "mesh": "spherical shell 0.55<|x|<1, "
                        "156 affinely mapped macros (hollow cube [0,3]^3 minus its centre cell)",
                        "refinements": R, "dofs": dofs, "vertices": nvert,
                        "cycle": "Vvar(3,3)",
@@ -398,6 +401,8 @@ def main():
     ap.add_argument("--shell", type=int, default=0, metavar="R",
                     help="spherical shell 0.55 < |x| < 1 at R refinements: the paper's setting "
                          "(f = 0, random start) on general macro geometry (prints its own line)")
+    ap.add_argument("--slip", action="store_true",
+                    help="with --shell: free-slip instead of no-slip on both spheres")
     args = ap.parse_args()
     if args.ops:
         run_ops(args.workload)
@@ -411,7 +416,7 @@ def main():
         return
     ordering = 1 if args.ordering == "hybrid" else 0
     if args.shell:
-        run_shell(args.shell, args.steps, args.warmup, ordering)
+        run_shell(args.shell, args.steps, args.warmup, ordering, args.slip)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the solver has no multi-GPU path "
