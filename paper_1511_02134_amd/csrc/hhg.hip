@@ -1026,9 +1026,15 @@ void colour_pass(hhg_ctx* c, int l, int col, bool vel, T* x, const T* rhs, hipSt
         if (c->opts.op == 1)
             hipLaunchKernelGGL((k_colour<T, true, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs,
                                T(0), ib);
+        else if (c->mi.general && c->mi.slip)
+            hipLaunchKernelGGL((k_colour<T, true, false, true, true>), dim3(grid), dim3(TPB), 0, s, v,
+                               col, x, rhs, T(0), ib);
         else if (c->mi.general)
             hipLaunchKernelGGL((k_colour<T, true, false, true>), dim3(grid), dim3(TPB), 0, s, v, col,
                                x, rhs, T(0), ib);
+        else if (c->mi.slip)
+            hipLaunchKernelGGL((k_colour<T, true, false, false, true>), dim3(grid), dim3(TPB), 0, s, v,
+                               col, x, rhs, T(0), ib);
         else
             hipLaunchKernelGGL((k_colour<T, true>), dim3(grid), dim3(TPB), 0, s, v, col, x, rhs, T(0),
                                ib);

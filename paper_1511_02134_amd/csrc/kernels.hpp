@@ -297,8 +297,10 @@ __global__ void k_slip_project(LevelDev<T> L, T* __restrict__ x) {
 // Colour sweeps keep the mirror of x current: a level's smoothing starts
 // with a current mirror (refreshed, filled or written by the prolongation).
 // DOP: point-block velocity sweeps (D form); GEN: sweeps over all 15 taps of
-// a_1 or c_l (general meshes).
-template <typename T, bool VEL, bool DOP = false, bool GEN = false>
+// a_1 or c_l (general meshes); SLIP: the level has free-slip vertices (their
+// lanes follow the component lanes; without them the kernel keeps the
+// register budget of the plain sweep).
+template <typename T, bool VEL, bool DOP = false, bool GEN = false, bool SLIP = false>
 __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restrict__ x,
                                                 const T* __restrict__ rhs, T omega, int ib) {
     static_assert(!(DOP && GEN), "one velocity form per launch");
@@ -337,6 +339,9 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
             const T ia = st[ST_INVA];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
+                // one component's 14 loads in flight at a time (all three
+                // hoisted need 112 VGPRs and halve the waves per SIMD)
+                __builtin_amdgcn_sched_barrier(0);
                 T* u = x + f * len;
                 T acc = rhs[f * len + v[0]];
 #pragma unroll
@@ -436,8 +441,10 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
                                       f + 1);
             return;
         }
-        const int ts = L.slip_beg[c] + (q - 3 * nfc);
-        if (ts < L.col_start[c + 1]) slip_colour<T, GEN>(L, ts, x, rhs);
+        if (SLIP) {
+            const int ts = L.slip_beg[c] + (q - 3 * nfc);
+            if (ts < L.col_start[c + 1]) slip_colour<T, GEN>(L, ts, x, rhs);
+        }
         return;
     }
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
