@@ -387,6 +387,8 @@ def main():
     ap.add_argument("--ordering", choices=("colour", "hybrid"), default="colour",
                     help="Gauss-Seidel order of the smoother: the global 4-colouring (default) "
                          "or the hybrid primitive-class order of HHG (Section 3.4)")
+    ap.add_argument("--graphs", type=int, choices=(0, 1), default=0,
+                    help="1: replay each cycle from a captured HIP graph (opts.graphs)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision solve reported beside the FP64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -441,7 +443,7 @@ def main():
         cycle = 1 if args.cycle == "Vvar" else 0
     dform = args.op == "D"
     s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if dform else 0,
-                 cycle=cycle, ordering=ordering)
+                 cycle=cycle, ordering=ordering, graphs=args.graphs)
     dofs = s.num_dofs()
     nvert = s.num_nodes()
     name = cfg.name.rsplit("-", 1)[0] + ("-fp64" if precision == 0 else "-mixed")
@@ -548,6 +550,7 @@ def main():
             "cycle": "Vvar(3,3)" if cycle else "V(3,3)",
             "form": "D (a_2)" if dform else "Laplace (a_1)",
             "ordering": args.ordering,
+            "graphs": args.graphs,
             "rtol": 1e-8,
             "cycles": info["cycles"],
             "coarse": ("exact (inverse of the bordered level-0 system)" if s.opts.coarse_solver == 0
