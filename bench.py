@@ -44,6 +44,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Stokes DoFs solved/s to 1e-8 rel. residual; TME factor; smoother HBM GB/s"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_unitcube_R8_fp64.md")
+SHELL_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_shell_R7_fp64.md")
 
 
 def sources_digest() -> str:
@@ -59,12 +60,12 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_PROFILE):
     """HBM bytes per launch of the finest velocity sweep from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when it was taken for
     other sources (or is absent)."""
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(path) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -107,18 +108,21 @@ print(json.dumps({{"seconds": t, "dofs": lv.ndofs(), "cycles": len(hist) - 1}}))
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
-def run_ops(workload_id: int):
+def run_ops(workload_id: int, R: int = 0):
     """A short sequence of finest-level operations for counter collection
     (rocprofv3 --pmc): K x, the residual, restriction and prolongation three
     times each, two smoothing steps, then three device copies of 512 MiB whose
-    counter readings calibrate FETCH_SIZE and WRITE_SIZE."""
+    counter readings calibrate FETCH_SIZE and WRITE_SIZE.  R: refinements
+    (default: the workload's own)."""
     import torch
     import workloads as W
     import paper_1511_02134_amd as P
 
     cfg = W.WORKLOADS[workload_id]
+    if R:
+        cfg = cfg.with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=0)
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=0, phys=cfg.physical())
     L, N = s.L, s.num_nodes()
     rng = np.random.default_rng(0)
     x = s.scatter(torch.tensor(rng.normal(size=(4, N)), device="cuda"))
@@ -309,6 +313,7 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
     vel_us = 1000.0 * ms_vel / max(nvel, 1)
     alg_bytes = 10.0 * 8.0 * nvert / 4.0
     achieved = alg_bytes / (vel_us * 1e-6) / 1e9
+    traffic = measured_traffic(SHELL_TRAFFIC_PROFILE) if R == 7 and not slip and not ordering else None
     line = {"metric": "Stokes DoFs solved/s to 1e-8 rel. residual (spherical shell)",
             "value": dofs / (ms * 1e-3), "unit": "DoF/s", "ms_per_step": ms,
             "steps": steps, "warmup": warmup, "dtype": "f64", "data": "synthetic",
@@ -326,7 +331,10 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
             "setup_s": t_setup,
             "velocity_sweep": {"kernel": "k_colour<double,velocity,15 taps> (finest level)",
                                "avg_us": vel_us, "bytes_per_launch": alg_bytes,
-                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS},
+                               "achieved_GBs": achieved, "frac_of_hbm_peak": achieved / HBM_PEAK_GBS,
+                               "traffic": traffic,
+                               "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + "
+                                               "WRITE_SIZE, copy-calibrated)"},
             "kernel_classes": {"velocity_sweep": {"launches": nvel, "ms": ms_vel},
                                "pressure_sweep": {"launches": npres, "ms": ms_pres},
                                "full_passes": {"launches": napp, "ms": ms_app}}}
@@ -407,7 +415,7 @@ def main():
                     help="with --shell: free-slip instead of no-slip on both spheres")
     args = ap.parse_args()
     if args.ops:
-        run_ops(args.workload)
+        run_ops(args.workload, args.R)
         return
     if args.tme:
         run_tme(args.tme, max(args.steps, 3), args.warmup)
