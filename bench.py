@@ -45,6 +45,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "Stokes DoFs solved/s to 1e-8 rel. residual; TME factor; smoother HBM GB/s"
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_unitcube_R8_fp64.md")
 SHELL_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_shell_R7_fp64.md")
+RB_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
+                                  "traffic_velocity_sweep_redblack_unitcube_R8_fp64.md")
 
 
 def sources_digest() -> str:
@@ -80,7 +82,8 @@ def measured_traffic(path=TRAFFIC_PROFILE):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(workload_id: int, R: int, cycle: int, timeout: float = 600.0):
+def cpu_baseline(workload_id: int, R: int, cycle: int, ordering: str = "colour",
+                 timeout: float = 600.0):
     """Times the oracle's solve (setup excluded) in a child process."""
     code = f"""
 import json, time, sys
@@ -91,7 +94,7 @@ from oracle import build_hierarchy, UMG
 cfg = W.WORKLOADS[{workload_id}].with_R({R})
 xyz, tet, nu, tags = cfg.mesh()
 H = build_hierarchy(xyz, tet, nu, tags, {R})
-umg = UMG(H, variable={bool(cycle)})
+umg = UMG(H, variable={bool(cycle)}, ordering={ordering!r})
 lv = H.finest
 f = cfg.forcing_field()
 t0 = time.perf_counter()
@@ -108,7 +111,7 @@ print(json.dumps({{"seconds": t, "dofs": lv.ndofs(), "cycles": len(hist) - 1}}))
     return json.loads(out.stdout.strip().splitlines()[-1])
 
 
-def run_ops(workload_id: int, R: int = 0):
+def run_ops(workload_id: int, R: int = 0, ordering: int = 0):
     """A short sequence of finest-level operations for counter collection
     (rocprofv3 --pmc): K x, the residual, restriction and prolongation three
     times each, two smoothing steps, then three device copies of 512 MiB whose
@@ -122,7 +125,7 @@ def run_ops(workload_id: int, R: int = 0):
     if R:
         cfg = cfg.with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
-    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=0, phys=cfg.physical())
+    s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=0, phys=cfg.physical(), ordering=ordering)
     L, N = s.L, s.num_nodes()
     rng = np.random.default_rng(0)
     x = s.scatter(torch.tensor(rng.normal(size=(4, N)), device="cuda"))
@@ -323,7 +326,7 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
                        "156 affinely mapped macros (hollow cube [0,3]^3 minus its centre cell)",
                        "refinements": R, "dofs": dofs, "vertices": nvert,
                        "cycle": "Vvar(3,3)",
-                       "ordering": "hybrid" if ordering else "colour",
+                       "ordering": "hybrid" if ordering == 1 else "colour",
                        "coarse": "exact (inverse of the bordered level-0 system, 5788 unknowns)",
                        "cycles": info["cycles"], "rho_mean": info["rho_mean"],
                        "status": info["status"]},
@@ -392,9 +395,11 @@ def main():
                          "refinements and the channel, V otherwise)")
     ap.add_argument("--op", choices=("laplace", "D"), default="laplace",
                     help="velocity form: Laplace (a_1, default) or D (a_2 = 2<nu D(u), D(v)>)")
-    ap.add_argument("--ordering", choices=("colour", "hybrid"), default="colour",
-                    help="Gauss-Seidel order of the smoother: the global 4-colouring (default) "
-                         "or the hybrid primitive-class order of HHG (Section 3.4)")
+    ap.add_argument("--ordering", choices=("auto", "colour", "hybrid", "redblack"), default="auto",
+                    help="Gauss-Seidel order of the smoother: the global 4-colouring, the hybrid "
+                         "primitive-class order of HHG (Section 3.4), or red-black (Kuhn meshes: "
+                         "the parities of X+Y+Z).  Default: red-black where the stencils allow it "
+                         "(Kuhn macros, Laplace form), the 4-colouring otherwise")
     ap.add_argument("--graphs", type=int, choices=(0, 1), default=0,
                     help="1: replay each cycle from a captured HIP graph (opts.graphs)")
     ap.add_argument("--no-mixed", action="store_true",
@@ -414,8 +419,15 @@ def main():
     ap.add_argument("--slip", action="store_true",
                     help="with --shell: free-slip instead of no-slip on both spheres")
     args = ap.parse_args()
+    if args.ordering == "auto":
+        # red-black needs 7-point a_1 and c_l: Kuhn macros (no physical
+        # coordinates: not the shell) and the Laplace form
+        args.ordering = "colour" if args.shell or args.op == "D" else "redblack"
+        if args.ops and args.workload in (7, 8, 9):
+            args.ordering = "colour"
+    ordering = {"colour": 0, "hybrid": 1, "redblack": 2}[args.ordering]
     if args.ops:
-        run_ops(args.workload, args.R)
+        run_ops(args.workload, args.R, ordering)
         return
     if args.tme:
         run_tme(args.tme, max(args.steps, 3), args.warmup)
@@ -424,7 +436,6 @@ def main():
         run_compare(args.compare, min(max(args.steps, 1), 3), min(args.warmup, 1),
                     args.op == "D")
         return
-    ordering = 1 if args.ordering == "hybrid" else 0
     if args.shell:
         run_shell(args.shell, args.steps, args.warmup, ordering, args.slip)
         return
@@ -511,11 +522,14 @@ def main():
     vs = 8.0 if precision == 0 else 4.0
     # algorithmic bytes of one colour launch: one direction of the velocity
     # Gauss-Seidel reads u (3 values), f (3) and p and writes u (3) per finest
-    # vertex, 10 values; its four colour launches share them
-    alg_bytes = 10.0 * vs * nvert / 4.0
+    # vertex, 10 values; its four colour launches share them (the red-black
+    # order's two parity launches)
+    per_launch = 0.5 if ordering == 2 else 0.25
+    alg_bytes = 10.0 * vs * nvert * per_launch
     achieved = alg_bytes / (vel_avg_ms * 1e-3) / 1e9
-    traffic = (measured_traffic() if args.workload == 3 and not args.R and precision == 0
-               and not dform else None)
+    traffic = (measured_traffic(RB_TRAFFIC_PROFILE if ordering == 2 else TRAFFIC_PROFILE)
+               if args.workload == 3 and not args.R and precision == 0 and not dform
+               and ordering in (0, 2) else None)
 
     # practical ceiling: device copies moving the same bytes (half read, half
     # written), timed like the sweeps: groups of six back-to-back launches,
@@ -570,7 +584,8 @@ def main():
         "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"k_colour<{'double' if precision == 0 else 'float'},velocity"
+            "kernel": (f"{'k_colour_rb' if ordering == 2 else 'k_colour'}"
+                       f"<{'double' if precision == 0 else 'float'},velocity"
                        f"{',D' if dform else ''}> (finest level)"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -579,7 +594,8 @@ def main():
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "bytes_model": ("10 values per finest vertex per sweep direction (read u, f, p; "
-                            "write u), a quarter per colour launch"),
+                            "write u), " + ("half per red-black parity launch" if ordering == 2
+                                            else "a quarter per colour launch")),
             "bytes_per_launch": alg_bytes,
             "launches": nvel,
             "avg_us": 1000.0 * vel_avg_ms,
@@ -604,7 +620,7 @@ def main():
         print("[bench] mixed-precision solves done", file=sys.stderr, flush=True)
         del sm, xm
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(args.workload, args.cpu_R, cycle)
+        cb = cpu_baseline(args.workload, args.cpu_R, cycle, args.ordering)
         nproc, model = host_cpu()
         line["cpu_baseline"] = {
             "value": cb["dofs"] / cb["seconds"],
@@ -615,7 +631,8 @@ def main():
             "sample": (f"oracle (numpy/scipy FP64; its sparse products run on one thread of "
                        f"the {nproc} host cores) full solve of the same problem at "
                        f"{args.cpu_R} refinements instead of {cfg.R} ({cb['dofs']} DoFs, "
-                       f"{'Vvar' if cycle else 'V'}(3,3), {cb['cycles']} cycles, "
+                       f"{'Vvar' if cycle else 'V'}(3,3), {args.ordering} ordering, "
+                       f"{cb['cycles']} cycles, "
                        f"{cb['seconds']:.1f} s; setup excluded): the oracle's assembly of the "
                        f"full size does not fit a benchmark run"),
         }

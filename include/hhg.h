@@ -150,7 +150,16 @@ typedef struct {
                              of other primitives of its class as they were when the
                              class started); inside a primitive the colours 0..3
                              (backward sweep 3..0, class order kept).  Laplace form,
-                             without the Krylov vectors */
+                             without the Krylov vectors;
+                             2 red-black: the parities of X+Y+Z (red: colours 0 and 2,
+                             black: 1 and 3), one launch per parity.  Valid where a_1
+                             and c_l couple only the six axis neighbours, whose
+                             colours differ by one: meshes given without phys (with
+                             phys every macro takes general 15-point stencils, and
+                             the ordering is rejected).  Velocity sweep red, black, red (a second
+                             black update in a row would change nothing); pressure
+                             sweep red, black, then black, red when p_sweep = 1.
+                             Laplace form, without the Krylov vectors */
 } hhg_opts;
 
 /* Result of hhg_solve. */

@@ -41,6 +41,11 @@ Readings taken (listed again in the design notes):
     3..0), not the class order, so forward + backward (SHGS) is not
     symmetric.  The paper uses a row-wise red-black order inside a
     primitive; the 4-colouring is the order the device can run in parallel.
+  * ordering="redblack": on Kuhn meshes a_1 and c_l couple only the six axis
+    neighbours, whose colours differ by one, so the parities of X+Y+Z (red:
+    colours 0 and 2, black: 1 and 3) are independent sets too.  The sweeps
+    then run red, black (forward) and black, red (backward) -- the paper's
+    red-black colouring applied to the whole lattice.
   * free-slip nodes (Section 6.1, fem.project_slip): the velocity lives in
     the tangent plane.  The velocity rows of K x, of the right-hand side and
     of a restricted residual are projected there, and so is a prolongated
@@ -68,7 +73,7 @@ from .fem import Hierarchy, project_slip, tangential_basis
 class UMG:
     def __init__(self, H: Hierarchy, nu1=3, nu2=3, omega=0.3, variable=False,
                  p_sweep="forward", ordering="colour"):
-        if ordering not in ("colour", "hybrid"):
+        if ordering not in ("colour", "hybrid", "redblack"):
             raise ValueError(ordering)
         self.ordering = ordering
         self.H = H
@@ -95,6 +100,29 @@ class UMG:
                     g["v"].append((iv, lv.A[iv], dA[iv]))
                 g["p"].append((ip, lv.C[ip], dC[ip]))
             self._gs.append(g)
+        ncol = 4
+        if ordering == "redblack":
+            if self.dform:
+                raise ValueError("red-black ordering: Laplace form only")
+            ncol = 2
+            for l, lv in enumerate(H.levels):
+                par = lv.colour % 2
+                for Mx in (lv.A, lv.C):
+                    m = Mx.tocoo()
+                    off = (m.row != m.col) & (m.data != 0)
+                    if np.any(off & (par[m.row] == par[m.col])):
+                        raise ValueError("red-black ordering: a parity couples to itself")
+                dA, dC = lv.A.diagonal(), lv.C.diagonal()
+                g = {"v": [], "p": []}
+                for c in range(2):
+                    iv = np.nonzero(lv.free & (par == c))[0]
+                    ip = np.nonzero(par == c)[0]
+                    g["v"].append((iv, lv.A[iv], dA[iv]))
+                    g["p"].append((ip, lv.C[ip], dC[ip]))
+                self._gs[l] = g
+        fwd = list(range(ncol))
+        self._vorder = fwd + fwd[::-1]
+        self._porder = fwd + (fwd[::-1] if p_sweep == "symmetric" else [])
         self.slip = any(lv.slip is not None and lv.slip.any() for lv in H.levels)
         if self.slip and (self.dform or ordering == "hybrid"):
             raise ValueError("free-slip nodes: Laplace form with the colour ordering only")
@@ -166,7 +194,7 @@ class UMG:
         (Laplace form: per component; D form: r and the result are [3, N]
         and every vertex solves its 3x3 diagonal block)."""
         d = np.zeros_like(r)
-        order = list(range(4)) + list(range(3, -1, -1))
+        order = self._vorder
         if r.ndim == 2 and not self.dform:
             # the three components of a colour together, the new values of its
             # free-slip nodes projected onto their tangent planes
@@ -200,15 +228,12 @@ class UMG:
         """Shat^{-1} s with Shat = D/omega + L (forward), or its symmetric
         version (forward then backward) when p_sweep == 'symmetric'."""
         d = np.zeros_like(s)
-        order = list(range(4))
         if self.ordering == "hybrid":
             self._hybrid_pass(l, "p", s, d, range(4), self.omega)
             if self.p_sweep == "symmetric":
                 self._hybrid_pass(l, "p", s, d, range(3, -1, -1), self.omega)
             return d
-        if self.p_sweep == "symmetric":
-            order += list(range(3, -1, -1))
-        for c in order:
+        for c in self._porder:
             idx, rows, diag = self._gs[l]["p"][c]
             d[idx] += self.omega * (s[idx] - rows @ d) / diag
         return d

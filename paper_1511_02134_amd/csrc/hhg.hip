@@ -146,7 +146,8 @@ struct hhg_ctx {
     // algorithmic bytes per launch (finest level) of the timed classes
     double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
     double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
-    double bytes_ru_fused[4] = {0, 0, 0, 0}, bytes_bp_fused[4] = {0, 0, 0, 0};
+    // index 0..3: one fused colour; 4, 5: the two colours of a red-black parity
+    double bytes_ru_fused[6] = {0, 0, 0, 0, 0, 0}, bytes_bp_fused[6] = {0, 0, 0, 0, 0, 0};
     int dev = -1;                  // device of the workspace
     double* scratch = nullptr;     // that device's copy of the static scratch
     // phase timing of hhg_solve (smoothing, transfers, coarse solve, residuals)
@@ -200,8 +201,12 @@ bool opts_ok(const hhg_opts* o, std::string* err) {
         *err = "the D form needs the exact coarse solver (coarse_solver = 0)";
         return false;
     }
-    if (o->ordering < 0 || o->ordering > 1) {
-        *err = "ordering must be 0 (colours) or 1 (hybrid primitive classes)";
+    if (o->ordering < 0 || o->ordering > 2) {
+        *err = "ordering must be 0 (colours), 1 (hybrid primitive classes) or 2 (red-black)";
+        return false;
+    }
+    if (o->ordering == 2 && (o->op != 0 || o->krylov != 0)) {
+        *err = "the red-black ordering runs the Laplace form without the Krylov solvers";
         return false;
     }
     if (o->ordering == 1 && (o->op != 0 || o->krylov != 0)) {
@@ -239,6 +244,9 @@ hhg_status build_host(hhg_ctx* c, const hhg_mesh* mesh, int R, const hhg_opts* o
     if (!opts_ok(&o, &err)) return fail(c, HHG_EINVAL, err);
     if (!validate_mesh(mesh, &c->mi, &err)) return fail(c, HHG_EINVAL, err);
     c->mi.lap_blocks = c->mi.general && o.op == 0;
+    if (o.ordering == 2 && c->mi.general)
+        return fail(c, HHG_EINVAL,
+                    "the red-black ordering needs Kuhn macros (general stencils couple colours two apart)");
     if (c->mi.slip && (o.op != 0 || o.ordering != 0 || o.krylov != 0 || o.coarse_solver != 0))
         return fail(c, HHG_EINVAL,
                     "free-slip faces need the Laplace form, the colour ordering, the direct coarse "
@@ -653,6 +661,12 @@ hhg_status upload_all(hhg_ctx* c) {
         c->bytes_ru_fused[col] = c->bytes_ru + vs * 3.0 * (nbr + Nfc[col]);
         c->bytes_bp_fused[col] = c->bytes_bp + vs * (nbr + 2.0 * Nc[col]);
     }
+    for (int p = 0; p < 2; ++p) {
+        // parity p: the neighbours (colours p +- 1) read once, both colours written
+        const double nbr = Nc[(p + 1) & 3] + Nc[(p + 3) & 3];
+        c->bytes_ru_fused[4 + p] = c->bytes_ru + vs * 3.0 * (nbr + Nfc[p] + Nfc[p + 2]);
+        c->bytes_bp_fused[4 + p] = c->bytes_bp + vs * (nbr + 2.0 * (Nc[p] + Nc[p + 2]));
+    }
     c->bytes_res = vs * (4.0 * Nall + 2.0 * (3.0 * Nf + Nall));
     return HHG_OK;
 }
@@ -987,8 +1001,9 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
     Timed tm(c, HHG_K_APPLY, s, finest, bytes);
-    if (MODE == MODE_RU) ops(c, l, 0.25, 1, 0, 0);
-    else ops(c, l, 0, 1, 0.25, 0);
+    const double share = col < 4 ? 0.25 : 0.5;   // one colour or a red-black parity
+    if (MODE == MODE_RU) ops(c, l, share, 1, 0, 0);
+    else ops(c, l, 0, 1, share, 0);
     if (c->mi.general) {
         // 15-tap fused updates
         if (v.n >= WIN_MIN_N)
@@ -1132,11 +1147,59 @@ void uzawa_step_hybrid(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s)
     if (c->opts.p_sweep == 1) hybrid_pass<T>(c, l, false, true, x, t, s);
 }
 
+// One launch of the red-black order (ordering 2): parity p (0 red: colours 0
+// and 2, 1 black: colours 1 and 3) of the velocity or the pressure.
+template <typename T>
+void colour_pass_rb(hhg_ctx* c, int l, int p, bool vel, T* x, const T* rhs, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    int cnt = 0;
+    for (int col : {p, p + 2})
+        cnt += vel ? v.vel_end[col] - v.col_start[col] : v.col_start[col + 1] - v.col_start[col];
+    const int ib = iface_blocks(vel ? 3 * cnt : cnt);
+    const int grid = ib + rb_blocks(v.n_vtiles);
+    const bool finest = l == c->L;
+    ops(c, l, vel ? 0.5 : 0.0, 0, vel ? 0.0 : 0.5, 0);
+    if (vel) {
+        Timed tm(c, HHG_K_VEL, s, finest, c->bytes_vel[p] + c->bytes_vel[p + 2]);
+        hipLaunchKernelGGL((k_colour_rb<T, true>), dim3(grid), dim3(TPB), 0, s, v, p, x, rhs, T(0),
+                           ib);
+    } else {
+        Timed tm(c, HHG_K_PRES, s, finest, c->bytes_pres[p] + c->bytes_pres[p + 2]);
+        hipLaunchKernelGGL((k_colour_rb<T, false>), dim3(grid), dim3(TPB), 0, s, v, p, x, rhs,
+                           (T)c->opts.omega, ib);
+    }
+}
+
+// one inexact Uzawa step in the red-black order: the symmetric velocity sweep
+// red, black, red (a second black sweep right after the first would
+// recompute identical values), its first red half inside the pass that forms
+// f - B^T p; the pressure red (inside the pass that forms B u - g), black,
+// and with p_sweep = 1 black, red again
+template <typename T>
+void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
+    full_pass_fused<T, MODE_RU>(c, l, x, b, t, 4, s);
+    {
+        TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
+        colour_pass_rb<T>(c, l, 1, true, x, t, s);
+        colour_pass_rb<T>(c, l, 0, true, x, t, s);
+    }
+    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 4, s);
+    colour_pass_rb<T>(c, l, 1, false, x, t, s);
+    if (c->opts.p_sweep == 1) {
+        colour_pass_rb<T>(c, l, 1, false, x, t, s);
+        colour_pass_rb<T>(c, l, 0, false, x, t, s);
+    }
+}
+
 // one inexact Uzawa step (eq. Uzawa_smooth) in place
 template <typename T>
 void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     if (c->opts.ordering == 1) {
         uzawa_step_hybrid<T>(c, l, x, b, t, s);
+        return;
+    }
+    if (c->opts.ordering == 2) {
+        uzawa_step_rb<T>(c, l, x, b, t, s);
         return;
     }
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of

@@ -294,6 +294,42 @@ __global__ void k_slip_project(LevelDev<T> L, T* __restrict__ x) {
         for (int f = 0; f < 3; ++f) x[f * len + L.if_copy[q]] = v[f];
 }
 
+// Point update of volume vertex (i, j, k) of a Kuhn macro, whose a_1 and c_l
+// couple only the six axis neighbours: the velocity Gauss-Seidel of the three
+// components, or the relaxed pressure update; the mirror entry follows when
+// the vertex has one.
+template <typename T, bool VEL>
+__device__ __forceinline__ void axis_update(const LevelDev<T>& L, const T* __restrict__ st,
+                                            const Rows& R, int n, int i, int j, int k,
+                                            T* __restrict__ x, const T* __restrict__ rhs, T omega) {
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
+    int s[7];
+    axis_slots(R, i, s);
+    const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
+    if (VEL) {
+        const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
+                a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T* u = x + f * len;
+            T v = rhs[f * len + s[0]] -
+                  (a1 * u[s[1]] + a2 * u[s[2]] + a3 * u[s[3]] + a4 * u[s[4]] + a7 * u[s[5]] +
+                   a8 * u[s[6]]);
+            v *= ia;
+            u[s[0]] = v;
+            if (cm >= 0) L.cx[f * cs + cm] = v;
+        }
+    } else {
+        T* p = x + 3 * len;
+        const T cp = st[ST_C + 0] * p[s[0]] + st[ST_C + 1] * p[s[1]] + st[ST_C + 2] * p[s[2]] +
+                     st[ST_C + 3] * p[s[3]] + st[ST_C + 4] * p[s[4]] + st[ST_C + 7] * p[s[5]] +
+                     st[ST_C + 8] * p[s[6]];
+        const T v = p[s[0]] + omega * (rhs[3 * len + s[0]] - cp) * st[ST_INVC];
+        p[s[0]] = v;
+        if (cm >= 0) L.cx[3 * cs + cm] = v;
+    }
+}
+
 // Colour sweeps keep the mirror of x current: a level's smoothing starts
 // with a current mirror (refreshed, filled or written by the prolongation).
 // DOP: point-block velocity sweeps (D form); GEN: sweeps over all 15 taps of
@@ -365,31 +401,7 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
             if (cm >= 0) L.cx[3 * cs + cm] = val;
             return;
         }
-        int s[7];
-        axis_slots(R, i, s);
-        const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
-        if (VEL) {
-            const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
-                    a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                T* u = x + f * len;
-                T v = rhs[f * len + s[0]] -
-                      (a1 * u[s[1]] + a2 * u[s[2]] + a3 * u[s[3]] + a4 * u[s[4]] + a7 * u[s[5]] +
-                       a8 * u[s[6]]);
-                v *= ia;
-                u[s[0]] = v;
-                if (cm >= 0) L.cx[f * cs + cm] = v;
-            }
-        } else {
-            T* p = x + 3 * len;
-            const T cp = st[ST_C + 0] * p[s[0]] + st[ST_C + 1] * p[s[1]] + st[ST_C + 2] * p[s[2]] +
-                         st[ST_C + 3] * p[s[3]] + st[ST_C + 4] * p[s[4]] + st[ST_C + 7] * p[s[5]] +
-                         st[ST_C + 8] * p[s[6]];
-            const T v = p[s[0]] + omega * (rhs[3 * len + s[0]] - cp) * st[ST_INVC];
-            p[s[0]] = v;
-            if (cm >= 0) L.cx[3 * cs + cm] = v;
-        }
+        axis_update<T, VEL>(L, st, R, n, i, j, k, x, rhs, omega);
         return;
     }
     const int t0 = L.col_start[c];
@@ -450,6 +462,59 @@ __global__ void __launch_bounds__(TPB) k_colour(LevelDev<T> L, int c, T* __restr
     const int t = t0 + (int)blockIdx.x * TPB + (int)threadIdx.x;
     if (t >= tend) return;
     iface_colour<T, VEL, GEN>(L, L.st + (size_t)L.if_sid[t] * ST_SIZE, t, x, rhs, omega);
+}
+
+// Volume blocks of a red-black launch: two per tile (the quad's two vertices
+// of the parity), block v taking tile 8 (v / 16) + v % 8 and half (v / 8) % 2,
+// so that both halves of a tile run on its XCD.
+__host__ __device__ __forceinline__ int rb_tile(int v) { return (v >> 4) * 8 + (v & 7); }
+__host__ __device__ __forceinline__ int rb_half(int v) { return (v >> 3) & 1; }
+__host__ __device__ __forceinline__ int rb_blocks(int n_vtiles) { return 2 * ((n_vtiles + 7) / 8 * 8); }
+
+// Red-black sweep of Kuhn meshes (ordering 2): a_1 and c_l couple only the six
+// axis neighbours, whose colours differ from the vertex's by one, so the
+// colours p and p + 2 never couple and one launch updates both (parity p:
+// 0 red, 1 black).  Volume: two blocks per tile, each taking one of a quad's
+// two vertices of the parity in every lane; interface: a lane per vertex and
+// velocity component (pressure: per vertex) of either colour range.
+template <typename T, bool VEL>
+__global__ void __launch_bounds__(TPB) k_colour_rb(LevelDev<T> L, int p, T* __restrict__ x,
+                                                   const T* __restrict__ rhs, T omega, int ib) {
+    if ((int)blockIdx.x >= ib) {
+        // two blocks per tile, one per vertex of the parity in every quad,
+        // dealt to the tile's XCD like the full passes' sub-row blocks
+        const int v = (int)blockIdx.x - ib;
+        const int ti = rb_tile(v), e = rb_half(v);
+        if (ti >= L.n_vtiles) return;
+        const Tile tl = L.vtiles[ti];
+        if (tl.macro < 0) return;
+        const int n = L.n, k = tl.k, mm = n - k;
+        const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+        if (!P.ok) return;
+        const int j = P.j;
+        const int i = 4 * P.q + ((p + 2 * j + k + 2 * e) & 3);
+        if (i < 1 || i > mm - 1 - j) return;
+        Rows R;
+        make_rows(L.slab_base, n, (int)(tl.macro * L.mstride), j, k, R);
+        axis_update<T, VEL>(L, L.st + (size_t)tl.macro * ST_SIZE, R, n, i, j, k, x, rhs, omega);
+        return;
+    }
+    const int n0 = (VEL ? L.vel_end[p] : L.col_start[p + 1]) - L.col_start[p];
+    const int n2 = (VEL ? L.vel_end[p + 2] : L.col_start[p + 3]) - L.col_start[p + 2];
+    const int q = (int)blockIdx.x * TPB + (int)threadIdx.x;
+    const int v = VEL ? q / 3 : q, f = VEL ? q % 3 : 0;
+    int t;
+    if (v < n0)
+        t = L.col_start[p] + v;
+    else if (v < n0 + n2)
+        t = L.col_start[p + 2] + (v - n0);
+    else
+        return;
+    const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
+    if (VEL)
+        iface_colour<T, true>(L, st, t, x, rhs, omega, f, f + 1);
+    else
+        iface_colour<T, false>(L, st, t, x, rhs, omega);
 }
 
 // ---------------------------------------------------------------------------
@@ -944,6 +1009,18 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
     }
 }
 
+// Interface vertex t of a fused pass updated along with it: fcol 0..3 names one
+// colour, 4 + p the two colours p and p + 2 of the red-black order; velocity
+// updates skip the velocity Dirichlet vertices (and the free-slip ones, which
+// have their own launch).
+template <typename T>
+__device__ __forceinline__ bool fused_vertex(const LevelDev<T>& L, int t, int fcol, bool vel) {
+    const int c0 = fcol & 3;
+    if (t >= L.col_start[c0] && t < (vel ? L.vel_end[c0] : L.col_start[c0 + 1])) return true;
+    if (fcol < 4) return false;
+    return t >= L.col_start[c0 + 2] && t < (vel ? L.vel_end[c0 + 2] : L.col_start[c0 + 3]);
+}
+
 // Interface vertex t of a full pass with the stencil record st.  With MIRROR
 // its taps of x come from the mirror; with FUSE (which needs the mirror) the
 // colour-fc vertices (velocity: those without Dirichlet data) are updated too.
@@ -966,8 +1043,7 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     // velocity rows of a free-slip vertex: their tangential part
     if ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_RHS) && (L.if_flag[t] & 2))
         tangential(st + ST_NRM, out);
-    if (FUSE && t >= L.col_start[fcol] &&
-        t < (MODE == MODE_RU ? L.vel_end[fcol] : L.col_start[fcol + 1])) {
+    if (FUSE && fused_vertex(L, t, fcol, MODE == MODE_RU)) {
         const int c0 = L.if_cptr[t];
         fused_update<T, MODE, true, GEN>(st, s, L.cx, cs, xw, len, out, omega, L.if_cptr[t + 1] - c0,
                                     L.if_copy + c0, L.cx, cs, t, fa, fb);
@@ -1018,9 +1094,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     if (i < 1 || i > mm - 1 - j) continue;
                     for (int f = f0; f < f1; ++f) y[f * len + w[0][r + 1]] = out[r][f];
                 }
-                if (FUSE) {
-                    // the quad's vertex of colour fcol
-                    const int rc = (fcol + 2 * j + k) & 3, i = 4 * P.q + rc;
+                // the quad's vertex of colour fcol, or its two vertices of
+                // parity fcol - 4 (red-black order)
+                for (int e = 0; e < (FUSE ? (fcol < 4 ? 1 : 2) : 0); ++e) {
+                    const int rc = ((fcol & 3) + 2 * j + k + 2 * e) & 3, i = 4 * P.q + rc;
                     if (i >= 1 && i <= mm - 1 - j) {
                         T o[4];
 #pragma unroll
@@ -1102,7 +1179,8 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
                     }
-                    if (FUSE && ((i + 2 * j + 3 * k) & 3) == fcol) {
+                    if (FUSE && (fcol < 4 ? ((i + 2 * j + 3 * k) & 3) == fcol
+                                          : ((i + 2 * j + 3 * k) & 1) == fcol - 4)) {
                         const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
                         const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
                         fused_update<T, MODE, false, GEN>(st, GEN ? s : tp, x, len, xw, len, out,
@@ -1157,7 +1235,7 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             out[3] = part - b[3 * len + L.if_self[t]];
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
             for (int qq = c0; qq < c1; ++qq) y[3 * len + L.if_copy[qq]] = out[3];
-            if (t >= L.col_start[fcol] && t < L.col_start[fcol + 1])
+            if (fused_vertex(L, t, fcol, false))
                 fused_update<T, MODE, true, GEN>(st, sl, L.cx, cs, xw, len, out, omega, c1 - c0,
                                             L.if_copy + c0, L.cx, cs, t);
         }

@@ -81,7 +81,12 @@ def test_plan_rejects_bad_arguments():
     _expect_einval(xyz, tet, nu, tags, op=2)
     _expect_einval(xyz, tet, nu, tags, op=-1)
     assert "exact coarse" in _expect_einval(xyz, tet, nu, tags, op=1, coarse_solver=1)
-    _expect_einval(xyz, tet, nu, tags, ordering=2)
+    _expect_einval(xyz, tet, nu, tags, ordering=3)
+    assert "red-black" in _expect_einval(xyz, tet, nu, tags, ordering=2, op=1)
+    assert "red-black" in _expect_einval(xyz, tet, nu, tags, ordering=2, krylov=1)
+    sh = W.WORKLOADS[8].with_R(3)
+    sxyz, stet, snu, stags = sh.mesh()
+    assert "red-black" in _expect_einval(sxyz, stet, snu, stags, ordering=2, phys=sh.physical())
     assert "hybrid" in _expect_einval(xyz, tet, nu, tags, ordering=1, op=1)
     assert "hybrid" in _expect_einval(xyz, tet, nu, tags, ordering=1, krylov=1)
     assert P.plan(xyz, tet, nu, tags, 3, ordering=1) > P.plan(xyz, tet, nu, tags, 3)

@@ -247,3 +247,41 @@ def test_hybrid_sweeps_are_textbook_block_gauss_seidel(box_r3):
     Wp = np.diag(np.diag(C)) / w + np.where(low_f, C, 0.0)
     refp = np.linalg.solve(Wp, s)
     assert np.allclose(dp, refp, rtol=1e-11, atol=1e-13 * np.abs(refp).max())
+
+
+def test_redblack_sweeps_are_textbook(box_r3):
+    """ordering='redblack': on Kuhn meshes the parities of X+Y+Z are
+    independent sets of A and C (checked), and the velocity smoother is the
+    textbook symmetric Gauss-Seidel (D+L)^-1 ... (D+U)^-1 in the red-black
+    order, the pressure smoother forward SOR (D/omega + L) in that order; the
+    iterates differ from the 4-colour order's.  On the shell (15-point
+    stencils) the red-black order is rejected."""
+    cfg, _ = box_r3
+    xyz, tet, nu, tags = cfg.mesh()
+    H = build_hierarchy(xyz, tet, nu, tags, 3)
+    umg = UMG(H, ordering="redblack")
+    l = 1
+    lv = H.levels[l]
+    par = lv.colour % 2
+    fr = np.nonzero(lv.free)[0]
+    idx = fr[np.argsort(par[fr], kind="stable")]
+    A = lv.A.toarray()[np.ix_(idx, idx)]
+    D = np.diag(np.diag(A))
+    Lo, Up = np.tril(A, -1), np.triu(A, 1)
+    r = np.zeros(lv.N)
+    r[fr] = np.random.default_rng(31).normal(size=fr.shape[0])
+    d = umg.sgs(l, r)
+    d1 = np.linalg.solve(D + Lo, r[idx])
+    ref = d1 + np.linalg.solve(D + Up, r[idx] - A @ d1)
+    assert np.allclose(d[idx], ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+    assert np.abs(UMG(H).sgs(l, r) - d).max() > 1e-6 * np.abs(d).max()
+    ip = np.argsort(par, kind="stable")
+    C = lv.C.toarray()[np.ix_(ip, ip)]
+    s = np.random.default_rng(32).normal(size=lv.N)
+    dp = umg.sor(l, s)
+    refp = np.linalg.solve(np.diag(np.diag(C)) / umg.omega + np.tril(C, -1), s[ip])
+    assert np.allclose(dp[ip], refp, rtol=1e-11, atol=1e-13 * np.abs(refp).max())
+    sh = W.WORKLOADS[8].with_R(3)
+    sxyz, stet, snu, stags = sh.mesh()
+    with pytest.raises(ValueError):
+        UMG(build_hierarchy(sxyz, stet, snu, stags, 3, phys=sh.physical()), ordering="redblack")
