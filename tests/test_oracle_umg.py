@@ -281,6 +281,22 @@ def test_redblack_sweeps_are_textbook(box_r3):
     dp = umg.sor(l, s)
     refp = np.linalg.solve(np.diag(np.diag(C)) / umg.omega + np.tril(C, -1), s[ip])
     assert np.allclose(dp[ip], refp, rtol=1e-11, atol=1e-13 * np.abs(refp).max())
+    # symmetric pressure sweep: then (D/omega + U) on the remaining residual
+    us = UMG(H, ordering="redblack", p_sweep="symmetric")
+    dps = us.sor(l, s)
+    Dw = np.diag(np.diag(C)) / us.omega
+    refs = refp + np.linalg.solve(Dw + np.triu(C, 1), s[ip] - C @ refp)
+    assert np.allclose(dps[ip], refs, rtol=1e-11, atol=1e-13 * np.abs(refs).max())
+    # the red-black multigrid contracts like the 4-colour one
+    lf = H.finest
+    b = umg.rhs(cfg.forcing_field())
+    x0 = np.zeros((4, lf.N))
+    x0[:3] = cfg.dirichlet_field()
+    x0[:3, lf.free] = 0.0
+    _, h_rb = umg.solve(x0.copy(), b, rtol=1e-8, max_cycles=40)
+    _, h_c = UMG(H).solve(x0.copy(), b, rtol=1e-8, max_cycles=40)
+    rho = (h_rb[-1] / h_rb[0]) ** (1.0 / (len(h_rb) - 1))
+    assert rho <= 0.3 and abs(len(h_rb) - len(h_c)) <= 1
     sh = W.WORKLOADS[8].with_R(3)
     sxyz, stet, snu, stags = sh.mesh()
     with pytest.raises(ValueError):
