@@ -274,11 +274,12 @@ def run_compare(R: int, steps: int, warmup: int, dform: bool = False):
     print(json.dumps(line), flush=True)
 
 
-def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = False):
+def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: str | None = None):
     """The spherical shell 0.55 < |x| < 1 (Section 4.4) as 156 affinely mapped
     macros: f = 0, homogeneous Dirichlet data on both spheres (or, with slip,
-    free-slip there: Section 6.1), a seeded random start (the paper's
-    setting), variable V(3,3) to a 1e-8 relative residual and the direct
+    free-slip on the inner sphere or on both: Section 6.1), the paper's seeded
+    random start (u in U[0,1], p in U[0, 1/h_min]), variable V(3,3) to a 1e-8
+    relative residual and the direct
     coarse solver.  Reports DoFs solved per second, the phase
     split of one solve and the mean time and algorithmic HBM rate of the
     finest velocity colour sweep (15-tap stencils)."""
@@ -286,7 +287,7 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
     import workloads as W
     import paper_1511_02134_amd as P
 
-    cfg = W.WORKLOADS[9 if slip else 7].with_R(R)
+    cfg = (W.WORKLOADS[9].with_slip(slip) if slip else W.WORKLOADS[7]).with_R(R)
     xyz, tet, nu, tags = cfg.mesh()
     t0 = time.perf_counter()
     s = P.Solver(xyz, tet, nu, tags, R, phys=cfg.physical(), cycle=1, ordering=ordering)
@@ -294,7 +295,7 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
     dev = torch.device("cuda")
     dofs, N = s.num_dofs(), s.num_nodes()
     nvert = int(np.count_nonzero(s.mass_weights() > 0))
-    x0n = np.random.default_rng(0).uniform(0.0, 1.0, size=(4, N))
+    x0n = W.random_initial_guess(N, 1.0 / cfg.h_min(), seed=0)
     _, dmask = s.node_info()
     x0n[:3, dmask.astype(bool)] = 0.0
     x0 = s.scatter(torch.tensor(x0n, device=dev))
@@ -320,8 +321,10 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: bool = F
     line = {"metric": "Stokes DoFs solved/s to 1e-8 rel. residual (spherical shell)",
             "value": dofs / (ms * 1e-3), "unit": "DoF/s", "ms_per_step": ms,
             "steps": steps, "warmup": warmup, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"shell{'-slip' if slip else ''}-R{R}-fp64",
-                       "boundary": "free-slip (mass-conservative normals)" if slip else "no-slip",
+            "config": {"workload": f"shell{'-slip-' + slip if slip else ''}-R{R}-fp64",
+                       "boundary": ({"inner": "free-slip on the inner sphere, no-slip on the outer",
+                                     "both": "free-slip on both spheres"}[slip] + " (mass-"
+                                    "conservative normals)") if slip else "no-slip",
                        "mesh": "spherical shell 0.55<|x|<1, "
                        "156 affinely mapped macros (hollow cube [0,3]^3 minus its centre cell)",
                        "refinements": R, "dofs": dofs, "vertices": nvert,
@@ -416,8 +419,9 @@ def main():
     ap.add_argument("--shell", type=int, default=0, metavar="R",
                     help="spherical shell 0.55 < |x| < 1 at R refinements: the paper's setting "
                          "(f = 0, random start) on general macro geometry (prints its own line)")
-    ap.add_argument("--slip", action="store_true",
-                    help="with --shell: free-slip instead of no-slip on both spheres")
+    ap.add_argument("--slip", nargs="?", const="inner", choices=("inner", "both"), default=None,
+                    help="with --shell: free-slip on the inner sphere (no-slip on the outer), or "
+                         "on both spheres")
     args = ap.parse_args()
     if args.ordering == "auto":
         # red-black needs 7-point a_1 and c_l: Kuhn macros (no physical

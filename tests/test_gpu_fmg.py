@@ -51,7 +51,7 @@ def test_fmg_matches_oracle(cid, R, cycles, op):
 def test_fmg_on_the_shell_matches_oracle(cid, opts):
     """Full multigrid on the spherical shell (general macro geometry, a hole
     in the lattice): no-slip with the analytic data of the efficiency study,
-    free-slip on both spheres (the prolongated solution keeps its tangential
+    free-slip on the inner sphere (the prolongated solution keeps its tangential
     part), and the hybrid ordering; every level against the oracle."""
     import paper_1511_02134_amd as P
     R = 4

@@ -191,8 +191,8 @@ def test_shell_coarse_solvers_match_oracle(shell4):
 @pytest.mark.parametrize("cycle,coarse", [(0, 0), (1, 0), (1, 1)])
 def test_shell_cycles_match_oracle(cycle, coarse):
     """V(3,3) and the variable V-cycle, with either coarse solver, iterate by
-    iterate from the paper's setting (random start, f = 0, homogeneous
-    Dirichlet data) at 3 levels."""
+    iterate from a random start with f = 0 and homogeneous Dirichlet data at
+    3 levels."""
     sh = Shell(7, 4, cycle=cycle, **(MINRES if coarse else {}))
     umg = sh.umg
     lv = umg.H.finest
@@ -318,8 +318,9 @@ def test_shell_full_size_rows_and_solve():
     err = np.abs(y[:, sel] - kx).max() / scale.max()
     _announce(f"K x rows: max difference / row scale {err:.2e}")
     assert np.all(np.abs(y[:, sel] - kx) <= 1e-13 * scale + 1e-300)
-    # the paper's setting
-    x0 = rng.normal(size=(4, s.num_nodes()))
+    # the paper's setting: u0 in U[0,1], p0 in U[0, 1/h_min]
+    x0 = W.random_initial_guess(s.num_nodes(), 1.0 / cfg.h_min(), seed=72)
+    x0[:, ~present] = 0.0
     x0[:3, d == 1] = 0.0
     xd = s.scatter(_dev(x0))
     bd = s.scatter(_dev(np.zeros((4, s.num_nodes()))))

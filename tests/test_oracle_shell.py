@@ -1,7 +1,8 @@
 """Pins of the oracle on a general (non-Kuhn) macro mesh: the spherical shell
 0.55 < |x| < 1 of Section 4.4, built as the hollow cube [0,3]^3 minus its
-central cell (156 Kuhn macros in lattice coordinates) mapped radially, so
-that every macro is an arbitrary affine tetrahedron.
+central cell (156 Kuhn macros in lattice coordinates) with its vertices put
+on the two spheres by the equiangular cubed-sphere map, so that every macro
+is an arbitrary affine tetrahedron.
 
 Each check compares with something the oracle does not compute: the volume of
 the polyhedral shell from its boundary triangles (divergence theorem),

@@ -40,9 +40,10 @@ def cube():
     return cfg, build_hierarchy(xyz, tet, nu, tags, 3)
 
 
-@pytest.fixture(scope="module")
-def shell():
-    cfg = W.WORKLOADS[9].with_R(3)
+@pytest.fixture(scope="module", params=["inner", "both"])
+def shell(request):
+    """The shell with free-slip on the inner sphere (workload 9) or on both."""
+    cfg = W.WORKLOADS[9].with_slip(request.param).with_R(3)
     xyz, tet, nu, tags = cfg.mesh()
     return cfg, build_hierarchy(xyz, tet, nu, tags, 3, phys=cfg.physical())
 
@@ -66,7 +67,7 @@ def test_normals_on_flat_faces(cube, shell):
     lv = Hs.finest
     n = lv.n
     checked = 0
-    for t, f in zip(*np.nonzero(tags)):
+    for t, f in zip(*np.nonzero(tags == FACE_SLIP)):
         face = np.delete(tet[t], f)
         a, b, c = (xyz[v] * n for v in face)
         pa, pb, pc = (phys[v] for v in face)
@@ -83,16 +84,18 @@ def test_normals_on_flat_faces(cube, shell):
         assert np.all(lv.slip[strict])
         assert np.allclose(lv.normal[strict], nrm, atol=1e-12)
         checked += strict.sum()
-    assert checked > 1000
+    assert checked >= 200
 
 
 def test_mass_conservation(shell):
-    """With the mass-conservative normals every constrained velocity has
-    zero net outflow, 1^T B u = 0 (up to rounding), while an unconstrained
-    one does not."""
+    """With the mass-conservative normals every constrained velocity (zero at
+    the no-slip vertices, tangential at the free-slip ones) has zero net
+    outflow, 1^T B u = 0 (up to rounding), while one that is only zero at the
+    no-slip vertices does not."""
     _, H = shell
     for lv in H.levels:
         u = np.random.default_rng(3).normal(size=(4, lv.N))
+        u[:3, lv.dirichlet] = 0.0
         one = np.ones(lv.N)
         out = sum(one @ (lv.B[k] @ u[k]) for k in range(3))
         scale = sum(np.abs(lv.B[k]) @ np.abs(u[k]) for k in range(3)).sum()
@@ -177,7 +180,7 @@ def test_flat_slip_smoother_is_componentwise_sgs(cube):
 
 
 def test_shell_slip_multigrid(shell):
-    """Free-slip on both spheres: the variable V(3,3) contracts by <= 0.45
+    """Free-slip on one or both spheres: the variable V(3,3) contracts by <= 0.45
     per cycle to a 1e-10 residual; the normal velocity vanishes at every slip
     node and the net outflow 1^T B u is zero; on level 0 the multigrid's
     dense solve in the tangential basis equals the sparse direct solve."""

@@ -27,12 +27,15 @@ tetrahedra, Section 4 and Table "iteration numbers and time-to-solution"):
   6  unit cube, 6 macros, R=7, the analytic solution of the efficiency study
      (Section 5) with its forcing and Dirichlet data, fp64 full multigrid
   7  spherical shell 0.55 < |x| < 1 (Section 4.4), 156 macros (the hollow cube
-     [0,3]^3 minus its central cell, mapped radially), R=5, f=0, homogeneous
-     Dirichlet data on both spheres, random start (the paper's setting), fp64
+     [0,3]^3 minus its central cell, its vertices put on the two spheres by the
+     equiangular cubed-sphere map), R=5, f=0, homogeneous Dirichlet data on
+     both spheres, the paper's random start (u in [0,1], p in [0, 1/h_min]), fp64
   8  the same shell, R=4, the analytic solution of the efficiency study as
      forcing and Dirichlet data (a manufactured solution on the shell)
-  9  the same shell, R=5, free-slip on both spheres (Section 6.1: u . n = 0
-     with the mass-conservative normals), the forcing of workload 8
+  9  the same shell, R=5, free-slip on the inner sphere (Section 6.1: u . n = 0
+     with the mass-conservative normals; the obstacle of the paper's sphere-bed
+     application) and no-slip on the outer one, the forcing of workload 8;
+     with_slip("both") puts free-slip on both spheres
 
 For the shell the nodal arrays live on the lattice of the bounding box of the
 hollow cube; lattice points in the removed central cell are not vertices
@@ -137,15 +140,27 @@ def hollow_cube_mesh(m: int = 3):
 def shell_coordinates(xyz, m: int = 3, r_in: float = 0.55, r_out: float = 1.0):
     """Physical coordinates of the hollow-cube macro vertices on the spherical
     shell r_in < |x| < r_out (Section 4.4 uses 0.55 < |x| < 1): a vertex on the
-    surface of the removed central cell goes radially to |x| = r_in, a vertex
-    on the outer surface to |x| = r_out (every macro vertex lies on one of the
-    two, for m = 3)."""
+    surface of the removed central cell goes to |x| = r_in, a vertex on the
+    outer surface to |x| = r_out (every macro vertex lies on one of the two,
+    for m = 3).  Directions follow the equiangular cubed-sphere map (Ronchi,
+    Iacono and Paolucci, J. Comput. Phys. 124, 1996): a point a of a cube face
+    (|a|_inf = 1) goes to the direction of tan(pi a / 4), which spaces the face
+    lines at equal angles; its macros are less skewed than under the central
+    projection a / |a| (the shell's multigrid contracts faster on them)."""
     c = xyz - m / 2.0
     mx = np.abs(c).max(axis=1)
     r = np.where(np.isclose(mx, 0.5), r_in, r_out)
     if not np.all(np.isclose(mx, 0.5) | np.isclose(mx, m / 2.0)):
         raise ValueError("every macro vertex must lie on the inner or the outer surface")
-    return c / np.linalg.norm(c, axis=1, keepdims=True) * r[:, None]
+    d = np.tan(0.25 * np.pi * c / mx[:, None])
+    return d / np.linalg.norm(d, axis=1, keepdims=True) * r[:, None]
+
+
+def perturbed_coordinates(xyz, amp: float, seed: int):
+    """Physical coordinates xyz + amp * U[-1,1]^3 per vertex (seeded): every
+    macro of a box mesh becomes a different general tetrahedron."""
+    rng = np.random.default_rng(seed)
+    return xyz + amp * rng.uniform(-1.0, 1.0, size=xyz.shape)
 
 
 def boundary_face_tags(tet, tag=FACE_DIRICHLET):
@@ -341,15 +356,22 @@ class Workload:
     inflow: bool = False
     solution: str | None = None     # "tme": the analytic solution of the efficiency study
     kind: str = "box"               # "box" | "shell" (the spherical shell of Section 4.4)
-    slip: bool = False              # shell: free-slip instead of no-slip on both spheres
+    slip: str | None = None         # shell: free-slip on the inner sphere ("inner") or on both
+                                    # ("both"); no-slip elsewhere
     extra: dict = field(default_factory=dict)
 
     # -- inputs ----------------------------------------------------------
     def mesh(self):
         if self.kind == "shell":
             xyz, tet = hollow_cube_mesh(3)
-            tag = FACE_SLIP if self.slip else FACE_DIRICHLET
-            return xyz, tet, np.ones(tet.shape[0]), boundary_face_tags(tet, tag)
+            tags = boundary_face_tags(tet, FACE_DIRICHLET)
+            if self.slip is not None:
+                # the inner sphere holds the vertices of the removed central cell
+                inner = np.isclose(np.abs(xyz - 1.5).max(axis=1), 0.5)
+                for t, f in zip(*np.nonzero(tags)):
+                    if self.slip == "both" or np.all(inner[np.delete(tet[t], f)]):
+                        tags[t, f] = FACE_SLIP
+            return xyz, tet, np.ones(tet.shape[0]), tags
         xyz, tet = box_mesh(self.a)
         tags = face_tags(xyz, tet, self.a, self.natural_x)
         if self.nu_range is None:
@@ -363,6 +385,22 @@ class Workload:
         d = dict(self.__dict__)
         d["R"] = R
         return Workload(**d)
+
+    def with_slip(self, slip: str | None) -> "Workload":
+        d = dict(self.__dict__)
+        d["slip"] = slip
+        return Workload(**d)
+
+    def h_min(self) -> float:
+        """min_T h_T = min_T |T|^(1/3) over the finest tetrahedra: uniform
+        refinement splits a tetrahedron into 8 of equal volume, so a macro's
+        children at R refinements have volume |T_macro| / 8^R."""
+        xyz, tet, _, _ = self.mesh()
+        P = self.physical()
+        P = xyz if P is None else P
+        e = np.stack([P[tet[:, q + 1]] - P[tet[:, 0]] for q in range(3)], axis=1)
+        vol = np.abs(np.linalg.det(e)) / 6.0
+        return float((vol.min() / 8.0 ** self.R) ** (1.0 / 3.0))
 
     def physical(self):
         """Physical coordinates of the macro vertices (None: the lattice ones)."""
@@ -428,5 +466,5 @@ WORKLOADS = {
     8: Workload("shell-tme-R4-fp64", a=3, R=4, precision="fp64", forcing="tme", solution="tme",
                 kind="shell"),
     9: Workload("shell-slip-R5-fp64", a=3, R=5, precision="fp64", forcing="tme", kind="shell",
-                slip=True),
+                slip="inner"),
 }
