@@ -2148,6 +2148,24 @@ bool check_level(const hhg_ctx* c, int l, std::string* err) {
             for (int j = 1; j <= n - k - 2; ++j)
                 for (int i = 1; i <= n - k - 1 - j; ++i)
                     CK(seen[local_slot(h, m, i, j, k)] == 1, "interior vertex not covered");
+    // red-black volume blocks: each tile once per colour of the parity (the
+    // lanes' colour picks are the colour sweeps' above), both halves of a tile
+    // eight blocks apart, so on one XCD whatever the leading interface blocks
+    {
+        const int nvt = (int)h.vtiles.size();
+        std::vector<int> half_block((size_t)nvt * 2, -1);
+        for (int v = 0; v < rb_blocks(nvt); ++v) {
+            const int ti = rb_tile(v), e = rb_half(v);
+            if (ti >= nvt) continue;
+            CK(half_block[(size_t)ti * 2 + e] < 0, "red-black tile half visited twice");
+            half_block[(size_t)ti * 2 + e] = v;
+        }
+        for (int ti = 0; ti < nvt; ++ti) {
+            const int v0 = half_block[(size_t)ti * 2], v1 = half_block[(size_t)ti * 2 + 1];
+            CK(v0 >= 0 && v1 >= 0, "red-black tile half not covered");
+            CK(((v0 ^ v1) & 7) == 0, "red-black halves of a tile on different XCDs");
+        }
+    }
     // compact mirror: taps name the same vertex as the slot taps; every copy
     // of an interface vertex and every halo slot maps to its entry; a slot
     // with an entry passes the kernels' near-boundary test
