@@ -334,6 +334,7 @@ def run_shell(R: int, steps: int, warmup: int, ordering: int = 0, slip: str | No
                        "cycles": info["cycles"], "rho_mean": info["rho_mean"],
                        "status": info["status"]},
             "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
+            "levels_ms": {f"R{l + 2}": round(v, 3) for l, v in enumerate(pinfo["t_level_ms"])},
             "setup_s": t_setup,
             "velocity_sweep": {"kernel": "k_colour<double,velocity,15 taps> (finest level)",
                                "avg_us": vel_us, "bytes_per_launch": alg_bytes,
@@ -586,6 +587,7 @@ def main():
         "tme_factor": ms_per_step / t_apply,
         "t_apply_ms": t_apply,
         "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
+        "levels_ms": {f"R{l + 2}": round(v, 3) for l, v in enumerate(pinfo["t_level_ms"])},
         "roofline": {
             "bound": "hbm",
             "kernel": (f"{'k_colour_rb' if ordering == 2 else 'k_colour'}"

@@ -53,6 +53,10 @@ extern "C" {
 typedef struct hhg_ctx hhg_ctx;
 typedef void* hhg_stream; /* hipStream_t */
 
+/* Entries of the per-level arrays of hhg_solve_info; a hierarchy has at most
+ * 9 levels, since n_refine <= 10. */
+#define HHG_MAX_LEVELS 16
+
 typedef enum {
     HHG_OK = 0,
     HHG_EINVAL = 1,   /* bad argument or malformed mesh; nothing was launched */
@@ -188,6 +192,11 @@ typedef struct {
      * t_solve_ms minus their sum is the rest (projection, mixed-precision
      * scaling, event gaps). */
     double t_smooth_ms, t_transfer_ms, t_coarse_ms, t_residual_ms;
+    /* The same event pairs by level (entries 0..L; the rest 0): level l's
+     * smoothing, its residual, the restriction from it and the prolongation
+     * into it, the zeroing of its iterate; level 0 the coarse solves.  They sum
+     * to the four phase times. */
+    double t_level_ms[HHG_MAX_LEVELS];
 } hhg_solve_info;
 
 /* Fills opts with the defaults above. */

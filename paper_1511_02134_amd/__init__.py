@@ -57,7 +57,7 @@ class SolveInfo(ctypes.Structure):
                 ("t_solve_ms", ctypes.c_double), ("res_hist", ctypes.c_double * 256),
                 ("n_op", ctypes.c_double * 4), ("t_smooth_ms", ctypes.c_double),
                 ("t_transfer_ms", ctypes.c_double), ("t_coarse_ms", ctypes.c_double),
-                ("t_residual_ms", ctypes.c_double)]
+                ("t_residual_ms", ctypes.c_double), ("t_level_ms", ctypes.c_double * 16)]
 
 
 def _load():
@@ -378,7 +378,8 @@ class Solver:
                 "t_solve_ms": info.t_solve_ms, "res_hist": list(info.res_hist[:min(k, 255) + 1]),
                 "n_op": dict(zip("ABCM", list(info.n_op))),
                 "t_phase_ms": {"smooth": info.t_smooth_ms, "transfer": info.t_transfer_ms,
-                               "coarse": info.t_coarse_ms, "residual": info.t_residual_ms}}
+                               "coarse": info.t_coarse_ms, "residual": info.t_residual_ms},
+                "t_level_ms": list(info.t_level_ms[:self.L + 1])}
 
     def solve(self, x, b, rtol=1e-8, max_cycles=100, raise_on_noconv=False):
         info = SolveInfo()

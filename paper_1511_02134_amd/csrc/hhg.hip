@@ -93,7 +93,8 @@ constexpr int KV_N = 10;   // finest-level vectors of the Krylov solvers
 
 struct TimerPair {
     hipEvent_t a, b;
-    int n;   // launches between the two events
+    int n;          // launches between the two events
+    int lev = -1;   // phase pairs: the level whose work they bracket
 };
 
 }  // namespace
@@ -743,8 +744,8 @@ struct TimedGroup {
     }
 };
 
-// Event pair around the launches of one phase of a cycle, on all levels
-// (hhg_solve's phase timers; off unless requested).
+// Event pair around the launches of one phase of a cycle on one level
+// (hhg_solve's phase and level timers; off unless requested).
 enum { PH_SMOOTH = 0, PH_TRANSFER = 1, PH_COARSE = 2, PH_RESIDUAL = 3 };
 struct PhaseTimed {
     hhg_ctx* c;
@@ -752,9 +753,10 @@ struct PhaseTimed {
     hipStream_t s;
     TimerPair tp{nullptr, nullptr, 1};
     bool on;
-    PhaseTimed(hhg_ctx* c_, int ph_, hipStream_t s_)
+    PhaseTimed(hhg_ctx* c_, int ph_, int lev, hipStream_t s_)
         : c(c_), ph(ph_), s(s_), on(c_->phase_timing && c_->phase_active) {
         if (!on) return;
+        tp.lev = lev;
         tp.a = next_event(c);
         tp.b = next_event(c);
         if (!tp.a || !tp.b) {
@@ -1316,7 +1318,7 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     vecs<T>(c, l, &xl, &bl, &rl, &tl);
     if (l == 0) {
         // x += K_0^-1 (b - K_0 x)
-        PhaseTimed pt(c, PH_COARSE, s);
+        PhaseTimed pt(c, PH_COARSE, 0, s);
         full_pass<T, MODE_RES>(c, 0, x, b, rl, s);
         coarse_solve<T>(c, rl, tl, s);
         const size_t n4 = 4 * (size_t)c->H[0].len;
@@ -1327,34 +1329,34 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     // the previous cycle's sweeps and projection) and the sweeps keep it so
     const int extra = c->opts.cycle == 1 ? 2 * (top - l) : 0;
     {
-        PhaseTimed pt(c, PH_SMOOTH, s);
+        PhaseTimed pt(c, PH_SMOOTH, l, s);
         for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
     }
     {
-        PhaseTimed pt(c, PH_RESIDUAL, s);
+        PhaseTimed pt(c, PH_RESIDUAL, l, s);
         residual_mirror<T>(c, l, x, b, rl, s);
     }
     T *xc, *bc, *rc, *tc;
     vecs<T>(c, l - 1, &xc, &bc, &rc, &tc);
     {
-        PhaseTimed pt(c, PH_TRANSFER, s);
+        PhaseTimed pt(c, PH_TRANSFER, l, s);
         restrict_to<T>(c, l, rl, bc, s);
     }
     if (l - 1 == 0) {
-        PhaseTimed pt(c, PH_COARSE, s);
+        PhaseTimed pt(c, PH_COARSE, 0, s);
         coarse_solve<T>(c, bc, xc, s);
     } else {
         {
-            PhaseTimed pt(c, PH_TRANSFER, s);
+            PhaseTimed pt(c, PH_TRANSFER, l - 1, s);
             fill_iterate<T>(c, l - 1, xc, s);
         }
         vcycle<T>(c, l - 1, top, xc, bc, s);
     }
     {
-        PhaseTimed pt(c, PH_TRANSFER, s);
+        PhaseTimed pt(c, PH_TRANSFER, l, s);
         prolong_add<T>(c, l, xc, x, s);
     }
-    PhaseTimed pt(c, PH_SMOOTH, s);
+    PhaseTimed pt(c, PH_SMOOTH, l, s);
     for (int q = 0; q < c->opts.nu2 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
 }
 
@@ -1938,7 +1940,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
             cycle_mixed(c, x, st);
         else
             cycle_fp64(c, x, b, st);
-        PhaseTimed pt(c, PH_RESIDUAL, st);
+        PhaseTimed pt(c, PH_RESIDUAL, c->L, st);
         residual_norm<double>(c, c->L, x, b, r, c->scal, st, fp64);
     };
     for (auto& v : c->ppairs) v.clear();
@@ -1984,9 +1986,14 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     put_ops(c, I);
     {
         double* dst[4] = {&I->t_smooth_ms, &I->t_transfer_ms, &I->t_coarse_ms, &I->t_residual_ms};
+        for (int q = 0; q < HHG_MAX_LEVELS; ++q) I->t_level_ms[q] = 0.0;
         for (int ph = 0; ph < 4; ++ph) {
             double t = 0.0;
-            for (const TimerPair& tp : c->ppairs[ph]) t += event_ms(tp.a, tp.b);
+            for (const TimerPair& tp : c->ppairs[ph]) {
+                const double ms = event_ms(tp.a, tp.b);
+                t += ms;
+                if (tp.lev >= 0 && tp.lev < HHG_MAX_LEVELS) I->t_level_ms[tp.lev] += ms;
+            }
             *dst[ph] = t;
             c->ppairs[ph].clear();
         }

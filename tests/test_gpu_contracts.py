@@ -96,9 +96,10 @@ def test_solve_stops_when_the_residual_cannot_fall():
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_phase_timers(precision):
-    """With the phase timers on, every phase of the cycle reports a positive
-    time, their sum stays within the solve time, and the iterates are
-    bitwise those of an untimed solve."""
+    """With the phase timers on, every phase of the cycle and every level
+    reports a positive time, the level times sum to the phase times, their sum
+    stays within the solve time, and the iterates are bitwise those of an
+    untimed solve."""
     cfg, s = _solver(1, 5, precision=precision)
     f = cfg.forcing_field()
     b = s.rhs(s.scatter(_dev(f)))
@@ -106,6 +107,7 @@ def test_phase_timers(precision):
     xa = s.scatter(_dev(x0))
     ia = s.solve(xa, b, rtol=1e-8, max_cycles=50)
     assert all(v == 0.0 for v in ia["t_phase_ms"].values())
+    assert all(v == 0.0 for v in ia["t_level_ms"])
     s.set_phase_timing(True)
     xb = s.scatter(_dev(x0))
     ib = s.solve(xb, b, rtol=1e-8, max_cycles=50)
@@ -116,6 +118,10 @@ def test_phase_timers(precision):
     assert torch.equal(xa, xb)
     assert all(v > 0.0 for v in ph.values())
     assert sum(ph.values()) <= ib["t_solve_ms"] * 1.001
+    lv = ib["t_level_ms"]
+    _announce(f"levels {lv}")
+    assert len(lv) == s.L + 1 and all(v > 0.0 for v in lv)
+    assert sum(lv) == pytest.approx(sum(ph.values()), rel=1e-9)
 
 
 @pytest.mark.parametrize("cid,R", [(4, 3), (5, 3), (1, 4)])
