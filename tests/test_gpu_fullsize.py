@@ -1,7 +1,8 @@
 """Full-size checks in the benchmark's launch configuration (default options,
 XCD-aware tile order), on the target workloads themselves: unit cube at 7
 refinements in FP64 (Laplace and D form), at 8 refinements in mixed precision
-and in FP64, and the channel at 7 refinements in mixed precision.
+and in FP64 (with the 4-colour and with the red-black order, the benchmark's),
+and the channel at 7 refinements in mixed precision.
 
 The oracle cannot assemble these systems, so it evaluates rows one by one
 (oracle.rows, pinned against its global assembly) at sampled vertices: every
@@ -72,19 +73,21 @@ def _sample(cfg, seed, per_set=40):
 # precision and in FP64 (the benchmark's workload) and the channel in mixed
 # precision, all three in the variable V(3,3) cycle, where the plain V(3,3)
 # cycle contracts by more than 0.3 per cycle at these sizes
-FULL = [(2, "laplace", "fp64", 0), (3, "laplace", "mixed", 1), (3, "laplace", "fp64", 1),
-        (5, "laplace", "mixed", 1), (2, "D", "fp64", 0)]
+FULL = [(2, "laplace", "fp64", 0, 0), (3, "laplace", "mixed", 1, 0), (3, "laplace", "fp64", 1, 0),
+        (3, "laplace", "fp64", 1, 2), (3, "laplace", "mixed", 1, 2), (5, "laplace", "mixed", 1, 0),
+        (2, "D", "fp64", 0, 0)]
 
 
-@pytest.mark.parametrize("cid,op,prec,cycle", FULL)
-def test_full_size_solve_residual_rows(cid, op, prec, cycle):
+@pytest.mark.parametrize("cid,op,prec,cycle,ordering", FULL)
+def test_full_size_solve_residual_rows(cid, op, prec, cycle, ordering):
     import paper_1511_02134_amd as P
     cfg = W.WORKLOADS[cid]
     xyz, tet, nu, tags = cfg.mesh()
     precision = 1 if prec == "mixed" else 0
-    _announce(f"{cfg.name}: R={cfg.R}, precision={prec}, form={op}, cycle={'Vvar' if cycle else 'V'}")
+    _announce(f"{cfg.name}: R={cfg.R}, precision={prec}, form={op}, "
+              f"cycle={'Vvar' if cycle else 'V'}, ordering={ordering}")
     s = P.Solver(xyz, tet, nu, tags, cfg.R, precision=precision, op=1 if op == "D" else 0,
-                 cycle=cycle)
+                 cycle=cycle, ordering=ordering)
     dev = torch.device("cuda")
     f = cfg.forcing_field()
     x0 = np.zeros((4, s.num_nodes()))
