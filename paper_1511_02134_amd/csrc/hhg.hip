@@ -896,10 +896,16 @@ template <typename T, int MODE, bool MIRROR, bool DOP>
 void launch_kx_op(LevelDev<T>& v, int ib, const T* x, const T* b, T* y, double* partials,
                   hipStream_t s) {
     if (v.n >= SPLIT_MIN_N) {
-        // volume launch: one vertex per lane (four blocks per tile)
-        hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1, DOP>),
-                           dim3(full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, x, b, y, partials, 0,
-                           (T*)nullptr, -1, T(0));
+        if constexpr (DOP) {
+            // volume launch: one vertex per lane (four blocks per tile)
+            hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 1, DOP>),
+                               dim3(full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, x, b, y, partials,
+                               0, (T*)nullptr, -1, T(0));
+        } else {
+            // volume launch: a quad per lane, quad windows (one block per tile)
+            hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, true, 1, false>), dim3(v.n_vtiles),
+                               dim3(TPB), 0, s, v, x, b, y, partials, 0, (T*)nullptr, -1, T(0));
+        }
         if (ib > 0)
             hipLaunchKernelGGL((k_full<T, MODE, false, MIRROR, false, 2, DOP>), dim3(ib), dim3(TPB), 0,
                                s, v, x, b, y, partials, ib, (T*)nullptr, -1, T(0));

@@ -973,14 +973,77 @@ __device__ __forceinline__ void quad_window_load(const T* __restrict__ f, const 
     }
 }
 
-// RU (t_k = b_k - (B^T p)_k) or BP (t_3 = B u - b_3) for the four vertices of
-// a quad; out[r] receives the values of vertex 4q + r.
+// RU (t_k = b_k - (B^T p)_k), BP (t_3 = B u - b_3), K x or the residual
+// b - K x for the four vertices of a quad; out[r] receives the values of
+// vertex 4q + r.
 template <typename T, int MODE>
 __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[7][6],
                                           const T* __restrict__ x, const T* __restrict__ b,
                                           size_t len, T out[4][4]) {
     T v[7][6];
-    if (MODE == MODE_RU) {
+    if (MODE == MODE_APPLY || MODE == MODE_RES) {
+        // interior rows from the pair symmetries (as eval_vol_pairs), one
+        // field's window at a time: the pressure's (B^T p into the velocity
+        // rows, -C p into the pressure row), then each velocity component's
+        // (A u_f into row f, B_f u_f into the pressure row).  Opposite taps
+        // 2q+1, 2q+2 of vertex r sit at window (QW_ROW, r + QW_OFF).
+        T ku[4][3], kp[4];
+        quad_window_load(x + 3 * len, w, v);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            T pd[7], ps[3];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                const T a = v[QW_ROW[2 * q + 1]][r + QW_OFF[2 * q + 1]];
+                const T c = v[QW_ROW[2 * q + 2]][r + QW_OFF[2 * q + 2]];
+                pd[q] = a - c;
+                if (q == 0) ps[0] = a + c;
+                if (q == 1) ps[1] = a + c;
+                if (q == 3) ps[2] = a + c;
+            }
+            kp[r] = -(st[ST_C] * v[QW_ROW[0]][r + QW_OFF[0]] + st[ST_C + 1] * ps[0] +
+                      st[ST_C + 3] * ps[1] + st[ST_C + 7] * ps[2]);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                T acc = T(0);
+#pragma unroll
+                for (int q = 0; q < 7; ++q) acc += st[ST_BT + 15 * f + 2 * q + 1] * pd[q];
+                ku[r][f] = acc;
+            }
+        }
+        // a loop the compiler keeps rolled: one velocity window in registers at
+        // a time (unrolled, all four windows' loads were issued together)
+#pragma unroll 1
+        for (int f = 0; f < 3; ++f) {
+            quad_window_load(x + f * len, w, v);
+            const T* bf = st + ST_B + 15 * f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T bu = T(0), us[3];
+#pragma unroll
+                for (int q = 0; q < 7; ++q) {
+                    const T a = v[QW_ROW[2 * q + 1]][r + QW_OFF[2 * q + 1]];
+                    const T c = v[QW_ROW[2 * q + 2]][r + QW_OFF[2 * q + 2]];
+                    bu += bf[2 * q + 1] * (a - c);
+                    if (q == 0) us[0] = a + c;
+                    if (q == 1) us[1] = a + c;
+                    if (q == 3) us[2] = a + c;
+                }
+                const T au = st[ST_A] * v[QW_ROW[0]][r + QW_OFF[0]] + st[ST_A + 1] * us[0] +
+                             st[ST_A + 3] * us[1] + st[ST_A + 7] * us[2];
+#pragma unroll
+                for (int g = 0; g < 3; ++g) ku[r][g] += g == f ? au : T(0);
+                kp[r] += bu;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                out[r][f] = MODE == MODE_RES ? b[f * len + w[0][r + 1]] - ku[r][f] : ku[r][f];
+            out[r][3] = MODE == MODE_RES ? b[3 * len + w[0][r + 1]] - kp[r] : kp[r];
+        }
+    } else if (MODE == MODE_RU) {
         quad_window_load(x + 3 * len, w, v);
 #pragma unroll
         for (int f = 0; f < 3; ++f)
@@ -1062,7 +1125,9 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
-    static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP, "quad windows: RU and BP");
+    static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP ||
+                      ((MODE == MODE_APPLY || MODE == MODE_RES) && PART == 1 && !DOP && !GEN),
+                  "quad windows: RU, BP, and the volume launch of K x and the residual");
     static_assert(!DOP || ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_ARES) && !FUSE),
                   "D form: K x and the residuals");
     if (PART == 1) ib = 0;
@@ -1076,6 +1141,12 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
     int slot = -1;   // partial-sum slot of this block
     if (WIN && vol) {
         const Tile tl = L.vtiles[blockIdx.x - ib];
+        // K x and the residual: the tile's four partial-sum slots (one per
+        // sub-row in the one-vertex-per-lane launch), the sum in the first
+        if (MODE == MODE_RES && tl.macro >= 0) {
+            slot = 4 * tl.nat;
+            if (threadIdx.x >= 1 && threadIdx.x < 4) partials[slot + threadIdx.x] = 0.0;
+        }
         if (tl.macro >= 0) {
             const int n = L.n, k = tl.k, mm = n - k;
             const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
@@ -1092,7 +1163,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * P.q + r;
                     if (i < 1 || i > mm - 1 - j) continue;
-                    for (int f = f0; f < f1; ++f) y[f * len + w[0][r + 1]] = out[r][f];
+                    for (int f = f0; f < f1; ++f) {
+                        y[f * len + w[0][r + 1]] = out[r][f];
+                        if (MODE == MODE_RES) ss += (double)out[r][f] * (double)out[r][f];
+                    }
                 }
                 // the quad's vertex of colour fcol, or its two vertices of
                 // parity fcol - 4 (red-black order)
