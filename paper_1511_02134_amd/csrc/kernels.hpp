@@ -1113,6 +1113,79 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     }
 }
 
+// The fused colour updates of a windowed quad on Kuhn meshes: the quad's
+// vertex of colour fcol, or its two vertices of parity fcol - 4.  Every
+// neighbour value of every update is loaded before the first store (the
+// updated vertices never read each other: their axis neighbours are of the
+// other colours), so the lane waits on memory once rather than once per
+// vertex and component; the arithmetic is fused_update's.
+template <typename T, int MODE>
+__device__ __forceinline__ void quad_fused_axis(const LevelDev<T>& L, const T* __restrict__ st,
+                                                const Rows& R, int n, int j, int k, int q, int fcol,
+                                                const T out[4][4], const T* __restrict__ x, T* xw,
+                                                T omega) {
+    const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
+    const int mm = n - k;
+    int tp[2][7], cm[2];
+    bool ok[2];
+    T o[2][4];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int rc = ((fcol & 3) + 2 * j + k + 2 * e) & 3, i = 4 * q + rc;
+        ok[e] = (e == 0 || fcol >= 4) && i >= 1 && i <= mm - 1 - j;
+        axis_slots(R, i, tp[e]);
+        cm[e] = ok[e] && near_boundary(n, i, j, k) ? L.comp_of_slot[tp[e][0]] : -1;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            o[e][f] = rc == 0 ? out[0][f] : rc == 1 ? out[1][f] : rc == 2 ? out[2][f] : out[3][f];
+    }
+    if (MODE == MODE_RU) {
+        T u[2][3][6];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!ok[e]) continue;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int g = 0; g < 6; ++g) u[e][f][g] = x[f * len + tp[e][g + 1]];
+        }
+        const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
+                a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!ok[e]) continue;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const T v = o[e][f] - (a1 * u[e][f][0] + a2 * u[e][f][1] + a3 * u[e][f][2] +
+                                       a4 * u[e][f][3] + a7 * u[e][f][4] + a8 * u[e][f][5]);
+                const T un = v * ia;
+                xw[f * len + tp[e][0]] = un;
+                if (cm[e] >= 0) L.cx[f * cs + cm[e]] = un;
+            }
+        }
+    } else {
+        // the vertex's own pressure is read where it is written (through xw)
+        T p[2][7];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!ok[e]) continue;
+            p[e][0] = xw[3 * len + tp[e][0]];
+#pragma unroll
+            for (int g = 1; g < 7; ++g) p[e][g] = x[3 * len + tp[e][g]];
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            if (!ok[e]) continue;
+            const T cp = st[ST_C] * p[e][0] + st[ST_C + 1] * p[e][1] + st[ST_C + 2] * p[e][2] +
+                         st[ST_C + 3] * p[e][3] + st[ST_C + 4] * p[e][4] + st[ST_C + 7] * p[e][5] +
+                         st[ST_C + 8] * p[e][6];
+            const T pn = p[e][0] + omega * (o[e][3] - cp) * st[ST_INVC];
+            xw[3 * len + tp[e][0]] = pn;
+            if (cm[e] >= 0) L.cx[3 * cs + cm[e]] = pn;
+        }
+    }
+}
+
 // WIN (RU and BP only): one block per tile, a quad per lane, quad windows.
 // PART 1 / 2: a launch of the volume blocks only (ib = 0) or of the interface
 // blocks only (grid = ib); each then gets the registers of its own branch.
@@ -1170,6 +1243,9 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 }
                 // the quad's vertex of colour fcol, or its two vertices of
                 // parity fcol - 4 (red-black order)
+                if constexpr (FUSE && !GEN) {
+                    quad_fused_axis<T, MODE>(L, st, R, n, j, k, P.q, fcol, out, x, xw, omega);
+                } else
                 for (int e = 0; e < (FUSE ? (fcol < 4 ? 1 : 2) : 0); ++e) {
                     const int rc = ((fcol & 3) + 2 * j + k + 2 * e) & 3, i = 4 * P.q + rc;
                     if (i >= 1 && i <= mm - 1 - j) {
