@@ -1553,13 +1553,18 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
         for (int f = 0; f < NF; ++f) e[f] = T(0.5) * (ec[f * lc + sa] + ec[f * lc + sb2]);
     }
     if (slip) tangential(F.st + (size_t)F.if_sid[cm] * ST_SIZE + ST_NRM, e);
+    // every field of the fine vertex read before the first store, so that
+    // the lane waits on memory once
+    T xv[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) xv[f] = (!SET || (keep && f < 3)) ? xf[f * lf + sf] : T(0);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         T v = e[f];
         if (!SET)
-            v += xf[f * lf + sf];
+            v += xv[f];
         else if (keep && f < 3)
-            v = xf[f * lf + sf];
+            v = xv[f];
         xf[f * lf + sf] = v;
         if (cm >= 0) F.cx[f * cs + cm] = v;
     }
