@@ -309,14 +309,22 @@ __device__ __forceinline__ void axis_update(const LevelDev<T>& L, const T* __res
     if (VEL) {
         const T a1 = st[ST_A + 1], a2 = st[ST_A + 2], a3 = st[ST_A + 3], a4 = st[ST_A + 4],
                 a7 = st[ST_A + 7], a8 = st[ST_A + 8], ia = st[ST_INVA];
+        // all 21 values before the first store: one wait on memory per lane
+        // (the vertex's neighbours are of other colours, never written here)
+        T r[3], u[3][6];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-            T* u = x + f * len;
-            T v = rhs[f * len + s[0]] -
-                  (a1 * u[s[1]] + a2 * u[s[2]] + a3 * u[s[3]] + a4 * u[s[4]] + a7 * u[s[5]] +
-                   a8 * u[s[6]]);
+            const T* uf = x + f * len;
+            r[f] = rhs[f * len + s[0]];
+#pragma unroll
+            for (int g = 0; g < 6; ++g) u[f][g] = uf[s[g + 1]];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            T v = r[f] - (a1 * u[f][0] + a2 * u[f][1] + a3 * u[f][2] + a4 * u[f][3] + a7 * u[f][4] +
+                          a8 * u[f][5]);
             v *= ia;
-            u[s[0]] = v;
+            x[f * len + s[0]] = v;
             if (cm >= 0) L.cx[f * cs + cm] = v;
         }
     } else {
