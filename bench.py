@@ -2,7 +2,8 @@
 
 One step = one complete solve of the unit-cube Stokes problem refined 8 times
 (257^3 lattice, 66,718,718 DoFs, FP64, manufactured forcing, variable V(3,3)
-Uzawa multigrid to a 1e-8 relative residual from x0 = 0): right-hand side
+Uzawa multigrid with the red-black smoother order to a 1e-8 relative residual
+from x0 = 0): right-hand side
 assembly, every cycle and the per-cycle residual check.  Inputs are resident
 in HBM before the timed region.  The same problem in mixed precision (FP32
 cycles inside FP64 refinement) is timed beside it.
@@ -11,13 +12,15 @@ Printed as one JSON line with, besides the contract fields:
   tme_factor      solve time / time of one K apply on the finest level (the
                   paper's work unit, Section 5), both measured here;
   phases_ms       smoothing, transfers, coarse solves and residuals of one
-                  solve (hipEvent pairs around every phase);
-  roofline        the finest velocity colour sweep (the dominant kernel)
-                  against the 8 TB/s HBM peak: algorithmic bytes per launch
-                  (10 values per finest vertex per sweep direction, a quarter
-                  per colour launch) / its mean launch time (hipEvents on its
-                  stream, one pair around the six back-to-back sweeps of each
-                  smoothing step);
+                  solve (hipEvent pairs around every phase), levels_ms the
+                  same by level;
+  roofline        the dominant kernel of the finest level, the velocity sweep
+                  or the fused f - B^T p pass, whichever has the larger total
+                  time in the timed solves (the other as roofline_<name>),
+                  against the 8 TB/s HBM peak: algorithmic bytes per launch /
+                  its mean launch time (hipEvents on its stream; one pair
+                  around the back-to-back velocity sweeps of each smoothing
+                  step, one around every fused pass);
   mixed_precision the FP32-in-FP64 solve of the same problem;
   cpu_baseline    the FP64 oracle (numpy/scipy) solving the same problem at a
                   bounded size on the host, setup excluded.
@@ -47,6 +50,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_unitcub
 SHELL_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_velocity_sweep_shell_R7_fp64.md")
 RB_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
                                   "traffic_velocity_sweep_redblack_unitcube_R8_fp64.md")
+RU_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fused_ru_redblack_unitcube_R8_fp64.md")
 
 
 def sources_digest() -> str:
@@ -510,9 +514,11 @@ def main():
     s.set_phase_timing(False)
     torch.cuda.synchronize()
 
-    # roofline of the dominant kernel: every finest-level velocity colour sweep
-    # of the same steps, timed by hipEvents on the solver's stream (one pair
-    # around the consecutive sweeps of each smoothing step)
+    # roofline of the dominant kernel: the finest-level velocity sweeps and the
+    # fused f - B^T p passes of the same steps, timed by hipEvents on the
+    # solver's stream (one pair around the consecutive velocity sweeps of each
+    # smoothing step, one around every fused pass); the one with the larger
+    # total is the roofline entry, the other is reported beside it
     s.set_timing(True)
     for _ in range(min(args.steps, 3)):
         step()
@@ -520,6 +526,7 @@ def main():
     nvel, ms_vel, bytes_vel = s.kernel_time(P.K_VEL)
     npres, ms_pres, bytes_pres = s.kernel_time(P.K_PRES)
     napp, ms_app, bytes_app = s.kernel_time(P.K_APPLY)
+    nru, ms_ru, bytes_ru = s.kernel_time(P.K_RU)
     s.set_timing(False)
     vel_avg_ms = ms_vel / max(nvel, 1)
     if nvel == 0:
@@ -555,6 +562,57 @@ def main():
     copy_gbs = 2 * src.numel() * 8 / (ctime * 1e-3) / 1e9
     del src, dst
 
+    prec_name = "double" if precision == 0 else "float"
+    entries = {"velocity_sweep": {
+        "bound": "hbm",
+        "kernel": (f"{'k_colour_rb' if ordering == 2 else 'k_colour'}<{prec_name},velocity"
+                   f"{',D' if dform else ''}> (finest level)"),
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "bytes_model": ("10 values per finest vertex per sweep direction (read u, f, p; "
+                        "write u), " + ("half per red-black parity launch" if ordering == 2
+                                        else "a quarter per colour launch")),
+        "bytes_per_launch": alg_bytes,
+        "launches": nvel,
+        "avg_us": 1000.0 * vel_avg_ms,
+        "copy_probe": {"GB/s": copy_gbs, "bytes": 2 * int(alg_bytes // 16) * 8,
+                       "frac_of_copy": achieved / copy_gbs},
+    }}
+    if nru > 0:
+        # f - B^T p with the fused update: read f (3 values), p, the other
+        # colours' velocity and write t (3) and the updated colour's velocity,
+        # per finest vertex: 10 values with a red-black parity, 9.25 with colour 0
+        ru_bytes = (10.0 if ordering == 2 else 9.25) * vs * nvert
+        ru_avg_ms = ms_ru / nru
+        ru_achieved = ru_bytes / (ru_avg_ms * 1e-3) / 1e9
+        ru_traffic = (measured_traffic(RU_TRAFFIC_PROFILE)
+                      if args.workload == 3 and not args.R and precision == 0 and not dform
+                      and ordering == 2 else None)
+        entries["fused_ru"] = {
+            "bound": "hbm",
+            "kernel": f"k_full<{prec_name},f - B^T p,fused,windows> (finest level)",
+            "achieved": ru_achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ru_achieved / HBM_PEAK_GBS,
+            "traffic": ru_traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
+            "bytes_model": ("read f (3 values), p and the other colours' velocity, write t (3) "
+                            "and the updated colour's velocity, per finest vertex: "
+                            + ("10 values (red parity)" if ordering == 2 else
+                               "9.25 values (colour 0)")),
+            "bytes_per_launch": ru_bytes,
+            "launches": nru,
+            "avg_us": 1000.0 * ru_avg_ms,
+            "copy_probe": {"GB/s": copy_gbs, "frac_of_copy": ru_achieved / copy_gbs},
+        }
+    dominant = "fused_ru" if nru > 0 and ms_ru > ms_vel else "velocity_sweep"
+
     line = {
         "metric": METRIC,
         "value": dofs / (ms_per_step * 1e-3),
@@ -588,28 +646,11 @@ def main():
         "t_apply_ms": t_apply,
         "phases_ms": {k: round(v, 3) for k, v in pinfo["t_phase_ms"].items()},
         "levels_ms": {f"R{l + 2}": round(v, 3) for l, v in enumerate(pinfo["t_level_ms"])},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": (f"{'k_colour_rb' if ordering == 2 else 'k_colour'}"
-                       f"<{'double' if precision == 0 else 'float'},velocity"
-                       f"{',D' if dform else ''}> (finest level)"),
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "bytes_model": ("10 values per finest vertex per sweep direction (read u, f, p; "
-                            "write u), " + ("half per red-black parity launch" if ordering == 2
-                                            else "a quarter per colour launch")),
-            "bytes_per_launch": alg_bytes,
-            "launches": nvel,
-            "avg_us": 1000.0 * vel_avg_ms,
-            "copy_probe": {"GB/s": copy_gbs, "bytes": 2 * int(alg_bytes // 16) * 8,
-                           "frac_of_copy": achieved / copy_gbs},
-        },
+        "roofline": dict(entries[dominant], name=dominant),
+        **{f"roofline_{k}": v for k, v in entries.items() if k != dominant},
         "kernel_classes": {
             "velocity_sweep": {"launches": nvel, "ms": ms_vel},
+            "fused_ru": {"launches": nru, "ms": ms_ru},
             "pressure_sweep": {"launches": npres, "ms": ms_pres},
             "full_passes": {"launches": napp, "ms": ms_app},
         },

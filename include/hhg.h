@@ -426,8 +426,11 @@ hhg_status hhg_set_viscosity(hhg_ctx* ctx, const double* nu);
 enum {
     HHG_K_VEL = 0,     /* velocity colour sweep, finest level */
     HHG_K_PRES = 1,    /* pressure colour sweep, finest level */
-    HHG_K_APPLY = 2,   /* B^T p / B u / residual passes, finest level */
-    HHG_K_NCLASS = 3
+    HHG_K_APPLY = 2,   /* B^T p / B u / residual passes, finest level (the
+                          fused f - B^T p pass excepted) */
+    HHG_K_RU = 3,      /* f - B^T p with its fused colour-0 or red velocity
+                          update, finest level */
+    HHG_K_NCLASS = 4
 };
 hhg_status hhg_set_timing(hhg_ctx* ctx, int32_t on);
 /* Phase timers of hhg_solve (the t_*_ms fields of hhg_solve_info): on = 1

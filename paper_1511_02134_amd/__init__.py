@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhhg.so")
 
 HHG_OK, HHG_EINVAL, HHG_ENOMEM, HHG_EDEVICE, HHG_ENOCONV, HHG_ENAN = range(6)
-K_VEL, K_PRES, K_APPLY = 0, 1, 2
+K_VEL, K_PRES, K_APPLY, K_RU = 0, 1, 2, 3
 STATUS_NAMES = {0: "HHG_OK", 1: "HHG_EINVAL", 2: "HHG_ENOMEM", 3: "HHG_EDEVICE",
                 4: "HHG_ENOCONV", 5: "HHG_ENAN"}
 

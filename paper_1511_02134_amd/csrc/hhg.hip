@@ -143,7 +143,7 @@ struct hhg_ctx {
     std::vector<TimerPair> tpairs[HHG_K_NCLASS];
     int tgroup_cls = -1;   // class whose launches a TimedGroup brackets together
     int tgroup_n = 0;
-    double tbytes[HHG_K_NCLASS] = {0, 0, 0};
+    double tbytes[HHG_K_NCLASS] = {0, 0, 0, 0};
     // algorithmic bytes per launch (finest level) of the timed classes
     double bytes_vel[4] = {0, 0, 0, 0}, bytes_pres[4] = {0, 0, 0, 0};
     double bytes_ru = 0, bytes_bp = 0, bytes_res = 0;
@@ -1008,7 +1008,7 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
     const int ib = iface_blocks(MODE == MODE_RU ? 3 * v.nif : v.n < WIN_MIN_N ? 4 * v.nif : v.nif);
     const bool finest = l == c->L;
     const double bytes = MODE == MODE_RU ? c->bytes_ru_fused[col] : c->bytes_bp_fused[col];
-    Timed tm(c, HHG_K_APPLY, s, finest, bytes);
+    Timed tm(c, MODE == MODE_RU ? HHG_K_RU : HHG_K_APPLY, s, finest, bytes);
     const double share = col < 4 ? 0.25 : 0.5;   // one colour or a red-black parity
     if (MODE == MODE_RU) ops(c, l, share, 1, 0, 0);
     else ops(c, l, 0, 1, share, 0);

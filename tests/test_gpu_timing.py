@@ -1,7 +1,9 @@
 """Kernel-class timing of the finest level: switching it on changes no result,
 and it counts every velocity and pressure colour sweep of the smoothing steps
 (Section 4: V(3,3), six Uzawa steps per cycle on the finest level), the
-velocity sweeps of a step being timed as one group."""
+velocity sweeps of a step being timed as one group, and the fused f - B^T p
+pass of every step (Laplace form; the D form runs it unfused, with the other
+full passes)."""
 import numpy as np
 import pytest
 
@@ -37,6 +39,7 @@ def test_timing_counts_sweeps_and_changes_nothing(cid, R, op):
     it = s.solve(xt, b, rtol=1e-8, max_cycles=100)
     nvel, ms_vel, bytes_vel = s.kernel_time(P.K_VEL)
     npres, ms_pres, bytes_pres = s.kernel_time(P.K_PRES)
+    nru, ms_ru, bytes_ru = s.kernel_time(P.K_RU)
     s.set_timing(False)
     torch.cuda.synchronize()
     assert it["res_hist"] == ia["res_hist"]
@@ -49,6 +52,8 @@ def test_timing_counts_sweeps_and_changes_nothing(cid, R, op):
     assert npres == steps * 3
     assert ms_vel > 0.0 and ms_pres > 0.0
     assert bytes_vel > 0.0 and bytes_pres > 0.0
+    assert nru == (0 if op == 1 else steps)
+    assert (ms_ru > 0.0 and bytes_ru > 0.0) if op == 0 else (ms_ru == 0.0)
     # timing switched off and on again starts from zero
     s.set_timing(True)
     n0, ms0, by0 = s.kernel_time(P.K_VEL)
