@@ -1001,8 +1001,10 @@ void fill_iterate(hhg_ctx* c, int l, T* x, hipStream_t s) {
 // colour col, in one launch (x is updated in place, t receives the pass)
 
 template <typename T, int MODE>
-void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStream_t s) {
+void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int colx, hipStream_t s) {
     LevelDev<T>& v = view<T>(c, l);
+    // colx = col + 8: the updated vertices' rows of the pass are not stored
+    const int col = colx >= 8 ? colx - 8 : colx;
     // f - B^T p takes a lane per interface vertex and velocity component, B u
     // - g four lanes per interface vertex on levels without quad windows
     const int ib = iface_blocks(MODE == MODE_RU ? 3 * v.nif : v.n < WIN_MIN_N ? 4 * v.nif : v.nif);
@@ -1017,17 +1019,17 @@ void full_pass_fused(hhg_ctx* c, int l, T* x, const T* b, T* t, int col, hipStre
         if (v.n >= WIN_MIN_N)
             hipLaunchKernelGGL((k_full<T, MODE, true, true, true, 0, false, true>),
                                dim3(ib + v.n_vtiles), dim3(TPB), 0, s, v, (const T*)x, b, t,
-                               c->partials, ib, x, col, (T)c->opts.omega);
+                               c->partials, ib, x, colx, (T)c->opts.omega);
         else
             hipLaunchKernelGGL((k_full<T, MODE, true, true, false, 0, false, true>),
                                dim3(ib + full_blocks(v.n_vtiles)), dim3(TPB), 0, s, v, (const T*)x, b,
-                               t, c->partials, ib, x, col, (T)c->opts.omega);
+                               t, c->partials, ib, x, colx, (T)c->opts.omega);
     } else if (v.n >= WIN_MIN_N) {
         hipLaunchKernelGGL((k_full<T, MODE, true, true, true>), dim3(ib + v.n_vtiles), dim3(TPB), 0, s,
-                           v, (const T*)x, b, t, c->partials, ib, x, col, (T)c->opts.omega);
+                           v, (const T*)x, b, t, c->partials, ib, x, colx, (T)c->opts.omega);
     } else {
         hipLaunchKernelGGL((k_full<T, MODE, true, true>), dim3(ib + full_blocks(v.n_vtiles)),
-                           dim3(TPB), 0, s, v, (const T*)x, b, t, c->partials, ib, x, col,
+                           dim3(TPB), 0, s, v, (const T*)x, b, t, c->partials, ib, x, colx,
                            (T)c->opts.omega);
     }
 }
@@ -1191,7 +1193,7 @@ void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
         colour_pass_rb<T>(c, l, 1, true, x, t, s);
         colour_pass_rb<T>(c, l, 0, true, x, t, s);
     }
-    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 4, s);
+    full_pass_fused<T, MODE_BP>(c, l, x, b, t, c->opts.p_sweep == 1 ? 4 : 4 + 8, s);
     colour_pass_rb<T>(c, l, 1, false, x, t, s);
     if (c->opts.p_sweep == 1) {
         colour_pass_rb<T>(c, l, 1, false, x, t, s);
@@ -1239,7 +1241,7 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
         for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
     }
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
-    full_pass_fused<T, MODE_BP>(c, l, x, b, t, 0, s);
+    full_pass_fused<T, MODE_BP>(c, l, x, b, t, c->opts.p_sweep == 1 ? 0 : 8, s);
     for (int col = 1; col < 4; ++col) colour_pass<T>(c, l, col, false, x, t, s);
     if (c->opts.p_sweep == 1)
         for (int col = 3; col >= 0; --col) colour_pass<T>(c, l, col, false, x, t, s);

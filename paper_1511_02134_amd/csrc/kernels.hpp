@@ -1211,6 +1211,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                   "quad windows: RU, BP, and the volume launch of K x and the residual");
     static_assert(!DOP || ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_ARES) && !FUSE),
                   "D form: K x and the residuals");
+    // fcol + 8: the rows of the vertices the pass updates are not stored (a
+    // B u - g pass whose relaxed colour is not swept again in the step)
+    const bool own_rows = fcol < 8;
+    if (fcol >= 8) fcol -= 8;
     if (PART == 1) ib = 0;
     // volume block or interface block (decided at compile time for PART 1, 2)
     const bool vol = PART == 1 ? true : PART == 2 ? false : (int)blockIdx.x >= ib;
@@ -1244,6 +1248,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * P.q + r;
                     if (i < 1 || i > mm - 1 - j) continue;
+                    if (MODE == MODE_BP && FUSE && !own_rows) {
+                        const int cr = (i + 2 * j + 3 * k) & 3;
+                        if (fcol < 4 ? cr == fcol : (cr & 1) == fcol - 4) continue;
+                    }
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + w[0][r + 1]] = out[r][f];
                         if (MODE == MODE_RES) ss += (double)out[r][f] * (double)out[r][f];
@@ -1333,12 +1341,14 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     } else {
                         eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
                     }
-                    for (int f = f0; f < f1; ++f) {
-                        y[f * len + s[0]] = out[f];
-                        if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
-                    }
-                    if (FUSE && (fcol < 4 ? ((i + 2 * j + 3 * k) & 3) == fcol
-                                          : ((i + 2 * j + 3 * k) & 1) == fcol - 4)) {
+                    const bool upd = FUSE && (fcol < 4 ? ((i + 2 * j + 3 * k) & 3) == fcol
+                                                       : ((i + 2 * j + 3 * k) & 1) == fcol - 4);
+                    if (!(MODE == MODE_BP && upd && !own_rows))
+                        for (int f = f0; f < f1; ++f) {
+                            y[f * len + s[0]] = out[f];
+                            if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
+                        }
+                    if (upd) {
                         const int tp[7] = {s[0], s[1], s[2], s[3], s[4], s[7], s[8]};
                         const int cm = near_boundary(n, i, j, k) ? L.comp_of_slot[s[0]] : -1;
                         fused_update<T, MODE, false, GEN>(st, GEN ? s : tp, x, len, xw, len, out,
@@ -1392,8 +1402,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             T out[4];
             out[3] = part - b[3 * len + L.if_self[t]];
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
-            for (int qq = c0; qq < c1; ++qq) y[3 * len + L.if_copy[qq]] = out[3];
-            if (fused_vertex(L, t, fcol, false))
+            const bool upd = fused_vertex(L, t, fcol, false);
+            if (own_rows || !upd)
+                for (int qq = c0; qq < c1; ++qq) y[3 * len + L.if_copy[qq]] = out[3];
+            if (upd)
                 fused_update<T, MODE, true, GEN>(st, sl, L.cx, cs, xw, len, out, omega, c1 - c0,
                                             L.if_copy + c0, L.cx, cs, t);
         }
@@ -1406,8 +1418,10 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
             T out[4];
             iface_full<T, MODE, FUSE, MIRROR, DOP, GEN>(L, st, t, x, b, xw, fcol, omega, out);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+            const bool skip = MODE == MODE_BP && FUSE && !own_rows && fused_vertex(L, t, fcol, false);
             for (int f = f0; f < f1; ++f) {
-                for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
+                if (!skip)
+                    for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
                 if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
             }
         }
