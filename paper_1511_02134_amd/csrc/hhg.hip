@@ -982,6 +982,35 @@ void residual_mirror(hhg_ctx* c, int l, const T* x, const T* b, T* r, hipStream_
     launch_kx<T, MODE_RES, true>(c, v, ib, x, b, r, s);
 }
 
+// ||b - K x||_2 into *out from the mirror of x (which must be current), with
+// t = b_k - (B^T p)_k (k = 0..2) written in place of the residual: the right-
+// hand side of the velocity sweeps of a Uzawa step that starts from this x
+// (Laplace form on Kuhn macros)
+template <typename T>
+void residual_norm_t(hhg_ctx* c, int l, const T* x, const T* b, T* t, double* out, hipStream_t s) {
+    LevelDev<T>& v = view<T>(c, l);
+    const int ib = iface_blocks(v.nif);
+    {
+        Timed tm(c, HHG_K_APPLY, s, l == c->L, c->bytes_res);
+        ops(c, l, 1, 2, 1, 0);
+        if (v.n >= SPLIT_MIN_N) {
+            hipLaunchKernelGGL((k_full<T, MODE_RES, false, true, true, 1, false, false, true>),
+                               dim3(v.n_vtiles), dim3(TPB), 0, s, v, x, b, t, c->partials, 0,
+                               (T*)nullptr, -1, T(0));
+            if (ib > 0)
+                hipLaunchKernelGGL((k_full<T, MODE_RES, false, true, false, 2, false, false, true>),
+                                   dim3(ib), dim3(TPB), 0, s, v, x, b, t, c->partials, ib,
+                                   (T*)nullptr, -1, T(0));
+        } else {
+            hipLaunchKernelGGL((k_full<T, MODE_RES, false, true, false, 0, false, false, true>),
+                               dim3(ib + v.n_vtiles), dim3(TPB), 0, s, v, x, b, t, c->partials, ib,
+                               (T*)nullptr, -1, T(0));
+        }
+    }
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+                       residual_partials(v), out, 1);
+}
+
 // mirror of x taken afresh (entry points that smooth a caller's vector)
 template <typename T>
 void mirror_refresh(hhg_ctx* c, int l, const T* x, hipStream_t s) {
@@ -1185,11 +1214,14 @@ void colour_pass_rb(hhg_ctx* c, int l, int p, bool vel, T* x, const T* rhs, hipS
 // recompute identical values), its first red half inside the pass that forms
 // f - B^T p; the pressure red (inside the pass that forms B u - g), black,
 // and with p_sweep = 1 black, red again
+// (t_ready: t already holds f - B^T p of this x, and the first red half is a
+// sweep of its own)
 template <typename T>
-void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
-    full_pass_fused<T, MODE_RU>(c, l, x, b, t, 4, s);
+void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t_ready) {
+    if (!t_ready) full_pass_fused<T, MODE_RU>(c, l, x, b, t, 4, s);
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
+        if (t_ready) colour_pass_rb<T>(c, l, 0, true, x, t, s);
         colour_pass_rb<T>(c, l, 1, true, x, t, s);
         colour_pass_rb<T>(c, l, 0, true, x, t, s);
     }
@@ -1201,15 +1233,18 @@ void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     }
 }
 
-// one inexact Uzawa step (eq. Uzawa_smooth) in place
+// one inexact Uzawa step (eq. Uzawa_smooth) in place; t_ready (Laplace form,
+// colour or red-black order): t already holds f - B^T p of this x (written by
+// the residual that precedes the step), so the step starts with the velocity
+// sweeps
 template <typename T>
-void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
+void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t_ready = false) {
     if (c->opts.ordering == 1) {
         uzawa_step_hybrid<T>(c, l, x, b, t, s);
         return;
     }
     if (c->opts.ordering == 2) {
-        uzawa_step_rb<T>(c, l, x, b, t, s);
+        uzawa_step_rb<T>(c, l, x, b, t, s, t_ready);
         return;
     }
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
@@ -1219,7 +1254,7 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     static const int vorder[6] = {1, 2, 3, 2, 1, 0};
     if (c->opts.op == 1) {
         full_pass<T, MODE_RU>(c, l, x, b, t, s);
-    } else {
+    } else if (!t_ready) {
         full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
         if (c->mi.slip) {
             // the colour-0 free-slip vertices, which the fused pass leaves out
@@ -1237,7 +1272,7 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s) {
     }
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
-        if (c->opts.op == 1) colour_pass<T>(c, l, 0, true, x, t, s);
+        if (c->opts.op == 1 || t_ready) colour_pass<T>(c, l, 0, true, x, t, s);
         for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
     }
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
@@ -1319,9 +1354,10 @@ void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
 }
 
 // V-cycle from level l whose top level is `top` (the variable cycle adds
-// 2 (top - l) smoothing steps on level l)
+// 2 (top - l) smoothing steps on level l); t_ready: the level's t holds
+// f - B^T p of x on entry (see uzawa_step)
 template <typename T>
-void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
+void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s, bool t_ready = false) {
     T *xl, *bl, *rl, *tl;
     vecs<T>(c, l, &xl, &bl, &rl, &tl);
     if (l == 0) {
@@ -1338,7 +1374,8 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s) {
     const int extra = c->opts.cycle == 1 ? 2 * (top - l) : 0;
     {
         PhaseTimed pt(c, PH_SMOOTH, l, s);
-        for (int q = 0; q < c->opts.nu1 + extra; ++q) uzawa_step<T>(c, l, x, b, tl, s);
+        for (int q = 0; q < c->opts.nu1 + extra; ++q)
+            uzawa_step<T>(c, l, x, b, tl, s, t_ready && q == 0);
     }
     {
         PhaseTimed pt(c, PH_RESIDUAL, l, s);
@@ -1815,9 +1852,10 @@ hhg_status hhg_project(hhg_ctx* c, int32_t l, void* x, hhg_stream stream) {
 namespace {
 
 // one solver iteration on the finest level; on entry of the mixed variant
-// r64_L must hold b - K x and scal[0] its norm
-void cycle_fp64(hhg_ctx* c, double* x, const double* b, hipStream_t s) {
-    vcycle<double>(c, c->L, c->L, x, b, s);
+// r64_L must hold b - K x and scal[0] its norm, of the FP64 one with t_ready
+// t64_L f - B^T p
+void cycle_fp64(hhg_ctx* c, double* x, const double* b, hipStream_t s, bool t_ready = false) {
+    vcycle<double>(c, c->L, c->L, x, b, s, t_ready);
     project<double>(c, c->L, x, s);
 }
 
@@ -1915,7 +1953,20 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     }
     hipEvent_t e0 = next_event(c), e1 = next_event(c);
     double* r = c->A[c->L].r64;
-    residual_norm<double>(c, c->L, x, b, r, c->scal, s);
+    // FP64 cycles smooth x itself: take its mirror once; the cycles and the
+    // projection keep it current, so the stopping test may use it too.  On
+    // Kuhn macros in the Laplace form (colour or red-black order) the
+    // stopping test also leaves f - B^T p of x in t for the next cycle's
+    // first Uzawa step.
+    const bool fp64 = c->opts.precision != 1;
+    const bool tfuse = fp64 && !dpath(c) && c->opts.ordering != 1;
+    double* tL = c->A[c->L].t64;
+    if (tfuse) {
+        mirror_refresh<double>(c, c->L, x, s);
+        residual_norm_t<double>(c, c->L, x, b, tL, c->scal, s);
+    } else {
+        residual_norm<double>(c, c->L, x, b, r, c->scal, s);
+    }
     double nrm;
     HIPCHECK(c, hipMemcpyAsync(&nrm, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(c, hipStreamSynchronize(s));
@@ -1936,10 +1987,7 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
     int stagn = 0;
     hhg_status st = HHG_ENOCONV;
     if (e0) (void)hipEventRecord(e0, s);
-    // FP64 cycles smooth x itself: take its mirror once; the cycles and the
-    // projection keep it current, so the stopping test may use it too
-    const bool fp64 = c->opts.precision != 1;
-    if (fp64) mirror_refresh<double>(c, c->L, x, s);
+    if (fp64 && !tfuse) mirror_refresh<double>(c, c->L, x, s);
     int k = 0;
     // one cycle and its stopping-test residual: the same launches every cycle,
     // replayed from a captured graph unless graphs are off or timing is on
@@ -1947,9 +1995,12 @@ hhg_status hhg_solve(hhg_ctx* c, void* xv, const void* bv, double rtol, int32_t 
         if (!fp64)
             cycle_mixed(c, x, st);
         else
-            cycle_fp64(c, x, b, st);
+            cycle_fp64(c, x, b, st, tfuse);
         PhaseTimed pt(c, PH_RESIDUAL, c->L, st);
-        residual_norm<double>(c, c->L, x, b, r, c->scal, st, fp64);
+        if (tfuse)
+            residual_norm_t<double>(c, c->L, x, b, tL, c->scal, st);
+        else
+            residual_norm<double>(c, c->L, x, b, r, c->scal, st, fp64);
     };
     for (auto& v : c->ppairs) v.clear();
     c->phase_active = c->phase_timing;

@@ -623,11 +623,13 @@ __device__ __forceinline__ void eval_ares(const T* __restrict__ st, const int* t
     }
 }
 
+// tt (residual rows, Laplace form): also b_k - (B^T p)_k, k = 0..2, summed
+// over the taps in the order of the f - B^T p pass (bitwise its values).
 template <typename T, int MODE, bool DOP = false>
 __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s, bool dir,
                                           const T* __restrict__ x, size_t xs,
                                           const T* __restrict__ b, size_t bs, int bslot,
-                                          T out[4], int fa = 0, int fb = 3) {
+                                          T out[4], int fa = 0, int fb = 3, T* tt = nullptr) {
     if (MODE == MODE_ARES && DOP) {
         // D form: every tap of all three components
         T ru[3] = {T(0), T(0), T(0)};
@@ -769,6 +771,7 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
         }
         const T ku = au + btp;
         out[f] = dir ? T(0) : (MODE == MODE_RES ? b[f * bs + bslot] - ku : ku);
+        if (MODE == MODE_RES && tt) tt[f] = dir ? T(0) : b[f * bs + bslot] - btp;
     }
     T cp = T(0);
 #pragma unroll
@@ -783,21 +786,34 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ st, const int* s
 // records are built): with pair sums for the three axis pairs (taps 1-2, 3-4,
 // 7-8, where A and C live) and pair differences for all seven pairs, 29
 // coefficients and half the products of the general row.
+// tt: as in eval_node.
 template <typename T, int MODE>
 __device__ __forceinline__ void eval_vol_pairs(const T* __restrict__ st, const int* s,
                                                const T* __restrict__ x, const T* __restrict__ b,
-                                               size_t len, T out[4]) {
+                                               size_t len, T out[4], T* tt = nullptr) {
     uint32_t o[15];
 #pragma unroll
     for (int g = 0; g < 15; ++g) o[g] = (uint32_t)s[g] * (uint32_t)sizeof(T);
     T ku[3], kp;
     {
         const T* p = x + 3 * len;
-        const T p0 = ldo(p, o[0]);
+        T pv[15];
+#pragma unroll
+        for (int g = 0; g < 15; ++g) pv[g] = ldo(p, o[g]);
+        const T p0 = pv[0];
+        if (MODE == MODE_RES && tt) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                T acc = T(0);
+#pragma unroll
+                for (int g = 0; g < 15; ++g) acc += st[ST_BT + 15 * f + g] * pv[g];
+                tt[f] = b[f * len + s[0]] - acc;
+            }
+        }
         T pd[7], ps[3];
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
-            const T a = ldo(p, o[2 * q + 1]), c = ldo(p, o[2 * q + 2]);
+            const T a = pv[2 * q + 1], c = pv[2 * q + 2];
             pd[q] = a - c;
             if (q == 0) ps[0] = a + c;
             if (q == 1) ps[1] = a + c;
@@ -984,10 +1000,13 @@ __device__ __forceinline__ void quad_window_load(const T* __restrict__ f, const 
 // RU (t_k = b_k - (B^T p)_k), BP (t_3 = B u - b_3), K x or the residual
 // b - K x for the four vertices of a quad; out[r] receives the values of
 // vertex 4q + r.
-template <typename T, int MODE>
+// TOUT (residual): tt[r] also receives b_k - (B^T p)_k, k = 0..2, from the
+// pair form of the residual's own B^T p (the RU branch's value up to
+// rounding); the A u_f parts are kept apart until the end for it.
+template <typename T, int MODE, bool TOUT = false>
 __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[7][6],
                                           const T* __restrict__ x, const T* __restrict__ b,
-                                          size_t len, T out[4][4]) {
+                                          size_t len, T out[4][4], T (*tt)[3] = nullptr) {
     T v[7][6];
     if (MODE == MODE_APPLY || MODE == MODE_RES) {
         // interior rows from the pair symmetries (as eval_vol_pairs), one
@@ -995,8 +1014,13 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
         // rows, -C p into the pressure row), then each velocity component's
         // (A u_f into row f, B_f u_f into the pressure row).  Opposite taps
         // 2q+1, 2q+2 of vertex r sit at window (QW_ROW, r + QW_OFF).
-        T ku[4][3], kp[4];
+        T ku[4][3], kp[4], ka[4][3];
         quad_window_load(x + 3 * len, w, v);
+        if (TOUT)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) ka[r][f] = T(0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             T pd[7], ps[3];
@@ -1040,15 +1064,27 @@ __device__ __forceinline__ void quad_eval(const T* __restrict__ st, const int w[
                 const T au = st[ST_A] * v[QW_ROW[0]][r + QW_OFF[0]] + st[ST_A + 1] * us[0] +
                              st[ST_A + 3] * us[1] + st[ST_A + 7] * us[2];
 #pragma unroll
-                for (int g = 0; g < 3; ++g) ku[r][g] += g == f ? au : T(0);
+                for (int g = 0; g < 3; ++g) {
+                    if (TOUT)
+                        ka[r][g] = g == f ? au : ka[r][g];
+                    else
+                        ku[r][g] += g == f ? au : T(0);
+                }
                 kp[r] += bu;
             }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
+            for (int f = 0; f < 3; ++f) {
+                if (TOUT) {
+                    const T bv = b[f * len + w[0][r + 1]];
+                    out[r][f] = bv - (ku[r][f] + ka[r][f]);
+                    tt[r][f] = bv - ku[r][f];
+                    continue;
+                }
                 out[r][f] = MODE == MODE_RES ? b[f * len + w[0][r + 1]] - ku[r][f] : ku[r][f];
+            }
             out[r][3] = MODE == MODE_RES ? b[3 * len + w[0][r + 1]] - kp[r] : kp[r];
         }
     } else if (MODE == MODE_RU) {
@@ -1098,7 +1134,8 @@ __device__ __forceinline__ bool fused_vertex(const LevelDev<T>& L, int t, int fc
 template <typename T, int MODE, bool FUSE, bool MIRROR, bool DOP = false, bool GEN = false>
 __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __restrict__ st, int t,
                                            const T* __restrict__ x, const T* __restrict__ b, T* xw,
-                                           int fcol, T omega, T out[4], int fa = 0, int fb = 3) {
+                                           int fcol, T omega, T out[4], int fa = 0, int fb = 3,
+                                           T* tt = nullptr) {
     static_assert(!FUSE || MIRROR, "fused updates keep the mirror current");
     const size_t len = (size_t)L.len, cs = (size_t)L.cstride;
     const int nif = L.nif;
@@ -1110,7 +1147,7 @@ __device__ __forceinline__ void iface_full(const LevelDev<T>& L, const T* __rest
     for (int g = 1; g < 15; ++g) s[g] = taps[(g - 1) * nif + t];
     const bool dir = (L.if_flag[t] & 1) != 0;
     eval_node<T, MODE, DOP>(st, s, dir, MIRROR ? L.cx : x, MIRROR ? cs : len, b, len, self, out, fa,
-                            fb);
+                            fb, tt);
     // velocity rows of a free-slip vertex: their tangential part
     if ((MODE == MODE_APPLY || MODE == MODE_RES || MODE == MODE_RHS) && (L.if_flag[t] & 2))
         tangential(st + ST_NRM, out);
@@ -1200,12 +1237,17 @@ __device__ __forceinline__ void quad_fused_axis(const LevelDev<T>& L, const T* _
 // DOP (K x and the residual only): the D form a_2, every row from eval_node.
 // GEN (fused passes only): the fused colour update of a general mesh, whose
 // a_1 and c_l couple all 14 neighbours.
+// TOUT (residual, Laplace form): the residual only enters the partial sums of
+// its norm; y receives t = b_k - (B^T p)_k (k = 0..2) instead, the values of
+// the f - B^T p pass up to rounding, for a smoothing step that follows at once.
 template <typename T, int MODE, bool FUSE, bool MIRROR, bool WIN = false, int PART = 0,
-          bool DOP = false, bool GEN = false>
+          bool DOP = false, bool GEN = false, bool TOUT = false>
 __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict__ x,
                                               const T* __restrict__ b,
                                               T* __restrict__ y, double* __restrict__ partials,
                                               int ib, T* xw, int fcol, T omega) {
+    static_assert(!TOUT || (MODE == MODE_RES && !DOP && !FUSE && !GEN),
+                  "t output: the residual of the Laplace form");
     static_assert(!WIN || MODE == MODE_RU || MODE == MODE_BP ||
                       ((MODE == MODE_APPLY || MODE == MODE_RES) && PART == 1 && !DOP && !GEN),
                   "quad windows: RU, BP, and the volume launch of K x and the residual");
@@ -1242,12 +1284,19 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                 const T* st = L.st + (size_t)tl.macro * ST_SIZE;
                 int w[7][6];
                 quad_window_slots(R, P.q, w);
-                T out[4][4];
-                quad_eval<T, MODE>(st, w, x, b, len, out);
+                T out[4][4], tt[4][3];
+                quad_eval<T, MODE, TOUT>(st, w, x, b, len, out, tt);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = 4 * P.q + r;
                     if (i < 1 || i > mm - 1 - j) continue;
+                    if (TOUT) {
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) y[f * len + w[0][r + 1]] = tt[r][f];
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) ss += (double)out[r][f] * (double)out[r][f];
+                        continue;
+                    }
                     if (MODE == MODE_BP && FUSE && !own_rows) {
                         const int cr = (i + 2 * j + 3 * k) & 3;
                         if (fcol < 4 ? cr == fcol : (cr & 1) == fcol - 4) continue;
@@ -1298,13 +1347,20 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
                     if (i < 1 || i > mm - 1 - j) continue;
                     int s[15];
                     nbr_slots(R, i, s);
-                    T out[4];
+                    T out[4], tt[3];
                     if (DOP)
                         eval_node<T, MODE, true>(st, s, false, x, len, b, len, s[0], out);
                     else if (MODE == MODE_APPLY || MODE == MODE_RES)
-                        eval_vol_pairs<T, MODE>(st, s, x, b, len, out);
+                        eval_vol_pairs<T, MODE>(st, s, x, b, len, out, TOUT ? tt : nullptr);
                     else
                         eval_node<T, MODE>(st, s, false, x, len, b, len, s[0], out);
+                    if (TOUT) {
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) y[f * len + s[0]] = tt[f];
+#pragma unroll
+                        for (int f = 0; f < 4; ++f) ss += (double)out[f] * (double)out[f];
+                        continue;
+                    }
                     for (int f = f0; f < f1; ++f) {
                         y[f * len + s[0]] = out[f];
                         if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];
@@ -1415,11 +1471,19 @@ __global__ void __launch_bounds__(TPB) k_full(LevelDev<T> L, const T* __restrict
         const int t = (int)blockIdx.x * TPB + (int)threadIdx.x;
         if (t < L.nif) {
             const T* st = L.st + (size_t)L.if_sid[t] * ST_SIZE;
-            T out[4];
-            iface_full<T, MODE, FUSE, MIRROR, DOP, GEN>(L, st, t, x, b, xw, fcol, omega, out);
+            T out[4], tt[3];
+            iface_full<T, MODE, FUSE, MIRROR, DOP, GEN>(L, st, t, x, b, xw, fcol, omega, out, 0, 3,
+                                                        TOUT ? tt : nullptr);
             const int c0 = L.if_cptr[t], c1 = L.if_cptr[t + 1];
+            if (TOUT) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f)
+                    for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = tt[f];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) ss += (double)out[f] * (double)out[f];
+            }
             const bool skip = MODE == MODE_BP && FUSE && !own_rows && fused_vertex(L, t, fcol, false);
-            for (int f = f0; f < f1; ++f) {
+            for (int f = f0; f < (TOUT ? f0 : f1); ++f) {
                 if (!skip)
                     for (int q = c0; q < c1; ++q) y[f * len + L.if_copy[q]] = out[f];
                 if (MODE == MODE_RES) ss += (double)out[f] * (double)out[f];

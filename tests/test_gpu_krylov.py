@@ -266,6 +266,9 @@ def test_measured_operator_counts():
     exp["A"] += cyc + 1
     exp["B"] += 2 * (cyc + 1)
     exp["C"] += cyc + 1
+    # the first Uzawa step of each cycle takes f - B^T p from the stopping
+    # test's residual before it (one B evaluation fewer per cycle)
+    exp["B"] -= cyc
     _announce(f"UMG {cyc} cycles: measured {info['n_op']}, expected {exp}")
     for blk in "ABCM":
         assert info["n_op"][blk] == pytest.approx(exp[blk], rel=1e-12, abs=1e-12), blk
