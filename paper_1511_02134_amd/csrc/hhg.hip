@@ -1214,16 +1214,17 @@ void colour_pass_rb(hhg_ctx* c, int l, int p, bool vel, T* x, const T* rhs, hipS
 // recompute identical values), its first red half inside the pass that forms
 // f - B^T p; the pressure red (inside the pass that forms B u - g), black,
 // and with p_sweep = 1 black, red again
-// (t_ready: t already holds f - B^T p of this x, and the first red half is a
-// sweep of its own)
+// (vr: f - B^T p of this x is given, and the first red half is a sweep of
+// its own)
 template <typename T>
-void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t_ready) {
-    if (!t_ready) full_pass_fused<T, MODE_RU>(c, l, x, b, t, 4, s);
+void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, const T* vr) {
+    if (!vr) full_pass_fused<T, MODE_RU>(c, l, x, b, t, 4, s);
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
-        if (t_ready) colour_pass_rb<T>(c, l, 0, true, x, t, s);
-        colour_pass_rb<T>(c, l, 1, true, x, t, s);
-        colour_pass_rb<T>(c, l, 0, true, x, t, s);
+        const T* rhs = vr ? vr : t;
+        if (vr) colour_pass_rb<T>(c, l, 0, true, x, rhs, s);
+        colour_pass_rb<T>(c, l, 1, true, x, rhs, s);
+        colour_pass_rb<T>(c, l, 0, true, x, rhs, s);
     }
     full_pass_fused<T, MODE_BP>(c, l, x, b, t, c->opts.p_sweep == 1 ? 4 : 4 + 8, s);
     colour_pass_rb<T>(c, l, 1, false, x, t, s);
@@ -1233,18 +1234,19 @@ void uzawa_step_rb(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, boo
     }
 }
 
-// one inexact Uzawa step (eq. Uzawa_smooth) in place; t_ready (Laplace form,
-// colour or red-black order): t already holds f - B^T p of this x (written by
-// the residual that precedes the step), so the step starts with the velocity
-// sweeps
+// one inexact Uzawa step (eq. Uzawa_smooth) in place.  vr (colour and
+// red-black orders): the velocity fields of vr hold f - B^T p of this x (b
+// itself when x = 0, or what the residual before the step wrote), so the step
+// skips the pass that forms it and starts with the velocity sweeps
 template <typename T>
-void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t_ready = false) {
+void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s,
+                const T* vr = nullptr) {
     if (c->opts.ordering == 1) {
         uzawa_step_hybrid<T>(c, l, x, b, t, s);
         return;
     }
     if (c->opts.ordering == 2) {
-        uzawa_step_rb<T>(c, l, x, b, t, s, t_ready);
+        uzawa_step_rb<T>(c, l, x, b, t, s, vr);
         return;
     }
     // symmetric Gauss-Seidel on A: colours 0 1 2 3 2 1 0 (a second sweep of
@@ -1252,9 +1254,11 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t
     // first sweep runs inside the pass that forms f - B^T p, except for the D
     // form, whose point-block sweeps run on their own
     static const int vorder[6] = {1, 2, 3, 2, 1, 0};
-    if (c->opts.op == 1) {
+    if (vr) {
+        // f - B^T p given
+    } else if (c->opts.op == 1) {
         full_pass<T, MODE_RU>(c, l, x, b, t, s);
-    } else if (!t_ready) {
+    } else {
         full_pass_fused<T, MODE_RU>(c, l, x, b, t, 0, s);
         if (c->mi.slip) {
             // the colour-0 free-slip vertices, which the fused pass leaves out
@@ -1272,8 +1276,9 @@ void uzawa_step(hhg_ctx* c, int l, T* x, const T* b, T* t, hipStream_t s, bool t
     }
     {
         TimedGroup tg(c, HHG_K_VEL, s, l == c->L);
-        if (c->opts.op == 1 || t_ready) colour_pass<T>(c, l, 0, true, x, t, s);
-        for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, t, s);
+        const T* rhs = vr ? vr : t;
+        if (c->opts.op == 1 || vr) colour_pass<T>(c, l, 0, true, x, rhs, s);
+        for (int q = 0; q < 6; ++q) colour_pass<T>(c, l, vorder[q], true, x, rhs, s);
     }
     // forward pressure sweep; colour 0 inside the pass that forms B u - g
     full_pass_fused<T, MODE_BP>(c, l, x, b, t, c->opts.p_sweep == 1 ? 0 : 8, s);
@@ -1354,10 +1359,11 @@ void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
 }
 
 // V-cycle from level l whose top level is `top` (the variable cycle adds
-// 2 (top - l) smoothing steps on level l); t_ready: the level's t holds
-// f - B^T p of x on entry (see uzawa_step)
+// 2 (top - l) smoothing steps on level l); vr0: f - B^T p of x on entry, for
+// the first Uzawa step (see uzawa_step), or null
 template <typename T>
-void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s, bool t_ready = false) {
+void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s,
+            const T* vr0 = nullptr) {
     T *xl, *bl, *rl, *tl;
     vecs<T>(c, l, &xl, &bl, &rl, &tl);
     if (l == 0) {
@@ -1375,7 +1381,7 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s, bool t_
     {
         PhaseTimed pt(c, PH_SMOOTH, l, s);
         for (int q = 0; q < c->opts.nu1 + extra; ++q)
-            uzawa_step<T>(c, l, x, b, tl, s, t_ready && q == 0);
+            uzawa_step<T>(c, l, x, b, tl, s, q == 0 ? vr0 : nullptr);
     }
     {
         PhaseTimed pt(c, PH_RESIDUAL, l, s);
@@ -1395,7 +1401,8 @@ void vcycle(hhg_ctx* c, int l, int top, T* x, const T* b, hipStream_t s, bool t_
             PhaseTimed pt(c, PH_TRANSFER, l - 1, s);
             fill_iterate<T>(c, l - 1, xc, s);
         }
-        vcycle<T>(c, l - 1, top, xc, bc, s);
+        // from x = 0: f - B^T p = b
+        vcycle<T>(c, l - 1, top, xc, bc, s, bc);
     }
     {
         PhaseTimed pt(c, PH_TRANSFER, l, s);
@@ -1855,7 +1862,7 @@ namespace {
 // r64_L must hold b - K x and scal[0] its norm, of the FP64 one with t_ready
 // t64_L f - B^T p
 void cycle_fp64(hhg_ctx* c, double* x, const double* b, hipStream_t s, bool t_ready = false) {
-    vcycle<double>(c, c->L, c->L, x, b, s, t_ready);
+    vcycle<double>(c, c->L, c->L, x, b, s, t_ready ? c->A[c->L].t64 : nullptr);
     project<double>(c, c->L, x, s);
 }
 
@@ -1866,7 +1873,8 @@ void cycle_mixed(hhg_ctx* c, double* x, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, a.r64, c->scal,
                        a.b32, n4);
     fill_iterate<float>(c, L, a.x32, s);
-    vcycle<float>(c, L, L, a.x32, a.b32, s);
+    // the correction starts from 0: f - B^T p = b
+    vcycle<float>(c, L, L, a.x32, a.b32, s, a.b32);
     hipLaunchKernelGGL(k_axpy_cast<float>, dim3(grid_for(n4)), dim3(TPB), 0, s, x, c->scal, a.x32,
                        n4);
     project<double>(c, L, x, s);
