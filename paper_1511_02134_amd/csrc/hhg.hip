@@ -1325,8 +1325,12 @@ template <typename T, int NF = 4>
 void prolong_add(hhg_ctx* c, int l, const T* ec, T* xf, hipStream_t s) {
     LevelDev<T>& C = view<T>(c, l - 1);
     LevelDev<T>& F = view<T>(c, l);
-    hipLaunchKernelGGL((k_prolong<T, false, NF>), dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s, F,
-                       C, ec, xf);
+    if (c->mi.slip)
+        hipLaunchKernelGGL((k_prolong<T, false, NF>), dim3(full_blocks(F.n_ctiles)), dim3(TPB), 0, s,
+                           F, C, ec, xf);
+    else
+        hipLaunchKernelGGL((k_prolong<T, false, NF, false>), dim3(full_blocks(F.n_ctiles)), dim3(TPB),
+                           0, s, F, C, ec, xf);
 }
 
 template <typename T>

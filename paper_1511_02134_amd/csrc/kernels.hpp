@@ -1507,14 +1507,20 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
                                                   int ib) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
     if ((int)blockIdx.x >= ib) {
-        // one coarse vertex per lane, blocks mapped as in the full passes
+        // one coarse vertex per lane: four blocks per tile (dealt to XCDs as
+        // in the full passes), each taking a quarter of the tile's quads with
+        // the four vertices of a quad in consecutive lanes.  A wave then reads
+        // every fine vertex of a row segment (its taps sit two fine vertices
+        // apart per coarse vertex), whole cache lines rather than every
+        // second entry of one sub-array
         const int v = (int)blockIdx.x - ib;
-        const int ti = full_tile(v), r = full_sub(v);
+        const int ti = full_tile(v), h = full_sub(v);
         if (ti >= C.n_vtiles) return;
         const Tile tl = C.vtiles[ti];
         if (tl.macro < 0) return;
         const int n = C.n, k = tl.k, mm = n - k;
-        const LanePos P = decode_lane(tl, n, 1, mm - 2, threadIdx.x);
+        const int r = (int)threadIdx.x & 3;
+        const LanePos P = decode_lane(tl, n, 1, mm - 2, 64 * h + ((int)threadIdx.x >> 2));
         const int j = P.j, i = 4 * P.q + r;
         if (!P.ok || i < 1 || i > mm - 1 - j) return;
         Rows RF;
@@ -1598,8 +1604,9 @@ __host__ __device__ __forceinline__ void parity_dir(int pat, int* di, int* dj, i
 
 // SET (full multigrid): x_f = P e_c instead of x_f += P e_c, except on the
 // velocity slots of Dirichlet vertices, which keep their values.
-// NF = 3: velocity fields only.
-template <typename T, bool SET = false, int NF = 4>
+// NF = 3: velocity fields only.  SLIP = false: the level has no free-slip
+// vertex (no flag lookup on the lanes next to a macro boundary).
+template <typename T, bool SET = false, int NF = 4, bool SLIP = true>
 __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
                                                  const T* __restrict__ ec, T* __restrict__ xf) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
@@ -1623,7 +1630,7 @@ __global__ void __launch_bounds__(TPB) k_prolong(LevelDev<T> F, LevelDev<T> C,
     // vertices, so their mirror entry is their list index)
     const bool keep = SET && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 1);
     // free-slip vertex: the interpolated velocity keeps its tangential part
-    const bool slip = NF >= 3 && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 2);
+    const bool slip = SLIP && NF >= 3 && cm >= 0 && cm < F.nif && (F.if_flag[cm] & 2);
     const int pi = i & 1, pj = j & 1, pk = k & 1;
     T e[NF];
     if ((pi | pj | pk) == 0) {
