@@ -1507,20 +1507,24 @@ __global__ void __launch_bounds__(TPB) k_restrict(LevelDev<T> C, LevelDev<T> F,
                                                   int ib) {
     const size_t lc = (size_t)C.len, lf = (size_t)F.len;
     if ((int)blockIdx.x >= ib) {
-        // one coarse vertex per lane: four blocks per tile (dealt to XCDs as
-        // in the full passes), each taking a quarter of the tile's quads with
-        // the four vertices of a quad in consecutive lanes.  A wave then reads
-        // every fine vertex of a row segment (its taps sit two fine vertices
-        // apart per coarse vertex), whole cache lines rather than every
-        // second entry of one sub-array
+        // one coarse vertex per lane, four blocks per tile (dealt to XCDs as
+        // in the full passes).  Coarse levels with n >= 128: each block takes
+        // a quarter of the tile's quads with the four vertices of a quad in
+        // consecutive lanes, so that a wave reads every fine vertex of a row
+        // segment (the taps of one coarse vertex sit two fine vertices apart),
+        // whole cache lines rather than every second entry of one sub-array;
+        // smaller ones (shorter rows, where that was slower): one block per
+        // sub-row r = i mod 4
         const int v = (int)blockIdx.x - ib;
         const int ti = full_tile(v), h = full_sub(v);
         if (ti >= C.n_vtiles) return;
         const Tile tl = C.vtiles[ti];
         if (tl.macro < 0) return;
         const int n = C.n, k = tl.k, mm = n - k;
-        const int r = (int)threadIdx.x & 3;
-        const LanePos P = decode_lane(tl, n, 1, mm - 2, 64 * h + ((int)threadIdx.x >> 2));
+        const bool spread = n >= 128;
+        const int r = spread ? (int)threadIdx.x & 3 : h;
+        const LanePos P =
+            decode_lane(tl, n, 1, mm - 2, spread ? 64 * h + ((int)threadIdx.x >> 2) : (int)threadIdx.x);
         const int j = P.j, i = 4 * P.q + r;
         if (!P.ok || i < 1 || i > mm - 1 - j) return;
         Rows RF;
