@@ -408,8 +408,10 @@ def main():
                          "primitive-class order of HHG (Section 3.4), or red-black (Kuhn meshes: "
                          "the parities of X+Y+Z).  Default: red-black where the stencils allow it "
                          "(Kuhn macros, Laplace form), the 4-colouring otherwise")
-    ap.add_argument("--graphs", type=int, choices=(0, 1), default=0,
-                    help="1: replay each cycle from a captured HIP graph (opts.graphs)")
+    ap.add_argument("--graphs", type=int, choices=(0, 1), default=1,
+                    help="1 (default): replay each cycle of the solves from a captured HIP graph "
+                         "(opts.graphs; the timed runs of the kernel-class and phase timers launch "
+                         "on the stream); 0: launch every kernel on the stream")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed-precision solve reported beside the FP64 one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -657,7 +659,7 @@ def main():
     }
     if precision == 0 and not args.no_mixed:
         sm = P.Solver(xyz, tet, nu, tags, cfg.R, precision=1, op=1 if dform else 0, cycle=cycle,
-                      ordering=ordering)
+                      ordering=ordering, graphs=args.graphs)
         xm = torch.empty_like(x0)
         ms_m, info_m, _ = timed_solves(sm, f_int, x0, xm, args.steps, args.warmup)
         line["mixed_precision"] = {
