@@ -1007,7 +1007,7 @@ void residual_norm_t(hhg_ctx* c, int l, const T* x, const T* b, T* t, double* ou
                                (T*)nullptr, -1, T(0));
         }
     }
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, c->partials,
                        residual_partials(v), out, 1);
 }
 
@@ -1308,7 +1308,7 @@ void residual_norm(hhg_ctx* c, int l, const T* x, const T* b, T* r, double* out,
         ops(c, l, 1, 2, 1, 0);
         launch_kx<T, MODE_RES, false>(c, v, ib, x, b, r, s);
     }
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, c->partials,
                        residual_partials(v), out, 1);
 }
 
@@ -1355,7 +1355,7 @@ void project(hhg_ctx* c, int l, T* x, hipStream_t s) {
     const int grid = ib + v.n_vtiles;
     const size_t len = (size_t)v.len;
     hipLaunchKernelGGL(k_mass_dot<T>, dim3(grid), dim3(TPB), 0, s, v, x + 3 * len, c->partials, ib);
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, c->partials,
                        v.nv_nat + (v.nif + TPB - 1) / TPB, c->scal + 4, 0);
     const size_t cs = (size_t)v.cstride;
     hipLaunchKernelGGL(k_sub_mean2<T>, dim3(grid_for(len + cs)), dim3(TPB), 0, s, x + 3 * len, len,
@@ -1475,7 +1475,7 @@ inline int vgrid(size_t n) {
 
 // reduce the partials of a vector kernel launched with vgrid(len) into *out
 void vreduce(hhg_ctx* c, size_t len, double* out, bool sqrt_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->kpart, vgrid(len), out,
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, c->kpart, vgrid(len), out,
                        sqrt_out ? 1 : 0);
 }
 
@@ -1790,7 +1790,7 @@ hhg_status hhg_residual_noalloc(hhg_ctx* c, int32_t l, const void* x, const void
     // it, so the scratch needs no clearing between calls
     launch_kx<double, MODE_RES, false>(c, v, iface_blocks(v.nif), (const double*)x,
                                        (const double*)b, (double*)r, s, c->scratch);
-    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, (const double*)c->scratch, np, d_norm,
+    hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, (const double*)c->scratch, np, d_norm,
                        1);
     LAUNCH_CHECK(c);
     return HHG_OK;
@@ -2113,7 +2113,7 @@ hhg_status hhg_adjoint_rhs(hhg_ctx* c, const void* g, void* y, hhg_stream stream
     if (c->mi.project) {
         hipLaunchKernelGGL((k_mass_dot<double, true>), dim3(grid), dim3(TPB), 0, s, v,
                            (const double*)g + 3 * len, c->partials, ib);
-        hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(TPB), 0, s, c->partials,
+        hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(RTPB), 0, s, c->partials,
                            v.nv_nat + (v.nif + TPB - 1) / TPB, c->scal + 16, 0);
     }
     fill<double>((double*)y, 4 * len, 0.0, s);

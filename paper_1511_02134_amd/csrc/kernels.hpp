@@ -1778,20 +1778,34 @@ __global__ void k_grad_reduce(const int* __restrict__ macro_tile0, const double*
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
-__global__ void k_reduce_sum(const double* __restrict__ partials, int n, double* __restrict__ out,
-                             int sqrt_out) {
-    __shared__ double sh[4];
-    // four running sums per lane (entries b, b + TPB, b + 2 TPB, b + 3 TPB of
-    // each stride of 4 TPB), so that four loads are in flight; fixed order
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int b = threadIdx.x; b < n; b += 4 * TPB) {
-        a0 += partials[b];
-        if (b + TPB < n) a1 += partials[b + TPB];
-        if (b + 2 * TPB < n) a2 += partials[b + 2 * TPB];
-        if (b + 3 * TPB < n) a3 += partials[b + 3 * TPB];
+// Sum of n partial sums (square root with sqrt_out) by one block of RTPB
+// threads: a residual on the finest level leaves tens of thousands of
+// partials, and a single block reads them at the rate of the loads it keeps
+// in flight (sixteen waves, eight running sums per lane: entries b + m RTPB,
+// m = 0..7, of each stride of 8 RTPB); fixed order, so the sum is the same
+// on every run.
+constexpr int RTPB = 1024;
+__global__ void __launch_bounds__(RTPB) k_reduce_sum(const double* __restrict__ partials, int n,
+                                                     double* __restrict__ out, int sqrt_out) {
+    __shared__ double sh[RTPB / 64];
+    double a[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) a[m] = 0.0;
+    for (int b = threadIdx.x; b < n; b += 8 * RTPB) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (b + m * RTPB < n) a[m] += partials[b + m * RTPB];
     }
-    const double tot = block_sum256((a0 + a1) + (a2 + a3), sh);
-    if (threadIdx.x == 0) out[0] = sqrt_out ? sqrt(tot) : tot;
+    double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < RTPB / 64; ++w) tot += sh[w];
+        out[0] = sqrt_out ? sqrt(tot) : tot;
+    }
 }
 
 template <typename T>
