@@ -181,7 +181,11 @@ typedef struct {
                               weighted by level, sum_l 8^(l-L) n_op,l (Section 4.2,
                               eq. op_count); a colour sweep counts a quarter of its
                               operator, B and B^T count as B, the exact level-0
-                              solves count nothing */
+                              solves count nothing; the first Uzawa step of a level
+                              in a cycle counts no B when f - B^T p is given (b on
+                              levels whose iterate starts at 0; in the FP64 solve
+                              on Kuhn macros in the Laplace form, the stopping
+                              test's residual leaves it for the top level) */
     /* Phase times of hhg_solve in ms, summed over all cycles and levels, from
      * hipEvent pairs on the stream; 0 unless hhg_set_phase_timing(ctx, 1)
      * (the events cost a few microseconds each and disable graph replay):
